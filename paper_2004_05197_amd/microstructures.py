@@ -1,0 +1,203 @@
+"""Seeded synthetic microstructures for the periodic voxel cell problem.
+
+This module only draws material fields (per-voxel Young's modulus E and
+Poisson ratio nu); it holds none of the solver's arithmetic, so both the
+CPU oracle's tests and the GPU path use it to build identical inputs.
+
+Conventions shared by every generator:
+  * a grid of shape (N_x, N_y[, N_z]) on the unit cell, voxel i covers
+    [i_a/N_a, (i_a+1)/N_a) along each axis;
+  * returned arrays have numpy shape (N_z, N_y, N_x) in 3D and (N_y, N_x)
+    in 2D, so a C-order ``ravel()`` is the colexicographic voxel order
+    (x fastest) that the paper uses for multi-indices (Sec. 3.1);
+  * all randomness comes from ``numpy.random.default_rng(seed)`` (PCG64).
+
+The paper has no microstructure data for this problem; the recipes below
+are the readings recorded in the design notes (circle, random sequential
+addition of spheres, thresholded and log-normal Gaussian random fields,
+laminates).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "circle2d", "rsa_spheres", "gaussian_random_field", "two_phase_grf",
+    "lognormal_field", "laminate", "random_cells", "WORKLOADS",
+]
+
+
+def _centres(shape_xyz):
+    """Voxel-centre coordinates in voxel units, numpy order (z, y, x)."""
+    axes = [np.arange(n, dtype=np.float64) + 0.5 for n in reversed(shape_xyz)]
+    return np.meshgrid(*axes, indexing="ij")
+
+
+def circle2d(n: int = 32, radius: float = 0.25, E_matrix: float = 1.0,
+             E_inclusion: float = 10.0, nu: float = 0.3):
+    """Centred circular inclusion in a square pixel cell.
+
+    A pixel belongs to the inclusion iff its centre lies strictly inside the
+    circle of the given radius (in cell lengths) about the cell centre.
+    Returns (E, nu) arrays of shape (n, n).
+    """
+    yc, xc = _centres((n, n))
+    r2 = (xc / n - 0.5) ** 2 + (yc / n - 0.5) ** 2
+    inside = r2 < radius * radius
+    E = np.where(inside, E_inclusion, E_matrix).astype(np.float64)
+    return E, np.full_like(E, nu)
+
+
+def rsa_spheres(n: int, vf: float, seed: int, rmin: float = 4.0,
+                rmax: float = 8.0, max_reject: int = 1_000_000):
+    """Random sequential addition of non-overlapping periodic spheres.
+
+    Radii r ~ U[rmin, rmax] (voxel units), centres ~ U[0, n)^3.  A candidate
+    is accepted iff its minimum-image distance to every accepted centre is at
+    least the sum of the radii.  A voxel is inside a sphere iff the
+    minimum-image distance from its centre to the sphere centre is < r.
+    Spheres are added until the inclusion voxel fraction reaches ``vf``.
+    Returns (mask[bool, (n, n, n)], achieved_vf, list_of_(centre, r)).
+    """
+    rng = np.random.default_rng(seed)
+    mask = np.zeros((n, n, n), dtype=bool)
+    spheres = []
+    rejects = 0
+    target = vf * n ** 3
+    count = 0
+    while count < target:
+        r = rng.uniform(rmin, rmax)
+        c = rng.uniform(0.0, n, size=3)
+        ok = True
+        for (c2, r2) in spheres:
+            dv = c - c2
+            dv -= n * np.round(dv / n)
+            if np.dot(dv, dv) < (r + r2) ** 2:
+                ok = False
+                break
+        if not ok:
+            rejects += 1
+            if rejects > max_reject:
+                raise RuntimeError("rsa_spheres: too many rejections")
+            continue
+        spheres.append((c, r))
+        # voxels in the bounding box, wrapped periodically
+        lo = np.floor(c - r - 1).astype(int)
+        hi = np.ceil(c + r + 1).astype(int)
+        ix = np.arange(lo[0], hi[0])
+        iy = np.arange(lo[1], hi[1])
+        iz = np.arange(lo[2], hi[2])
+        dx = (ix + 0.5) - c[0]
+        dy = (iy + 0.5) - c[1]
+        dz = (iz + 0.5) - c[2]
+        d2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+        sel = d2 < r * r
+        zz, yy, xx = np.nonzero(sel)
+        mask[iz[zz] % n, iy[yy] % n, ix[xx] % n] = True
+        count = int(mask.sum())
+    return mask, count / n ** 3, spheres
+
+
+def gaussian_random_field(shape_xyz, ell: float, seed: int):
+    """Standardized periodic Gaussian random field.
+
+    White noise w ~ N(0,1) on the grid is filtered in Fourier space by
+    exp(-ell^2 |xi|^2 / 4), xi_a = 2 pi k_a / N_a with signed k_a, which
+    gives a covariance proportional to exp(-r^2 / (2 ell^2)) (r in voxels).
+    The result is shifted/scaled to sample mean 0 and standard deviation 1.
+    Returns an array of numpy shape reversed(shape_xyz).
+    """
+    rng = np.random.default_rng(seed)
+    nshape = tuple(reversed(shape_xyz))
+    w = rng.standard_normal(nshape)
+    ks = [2.0 * np.pi * np.fft.fftfreq(m) for m in nshape]
+    grids = np.meshgrid(*ks, indexing="ij")
+    xi2 = sum(g * g for g in grids)
+    g = np.fft.ifftn(np.fft.fftn(w) * np.exp(-ell * ell * xi2 / 4.0)).real
+    g -= g.mean()
+    g /= g.std()
+    return g
+
+
+def two_phase_grf(n: int, seed: int, ell: float = 8.0, E_soft: float = 1.0,
+                  E_hard: float = 1000.0, nu_soft: float = 0.25,
+                  nu_hard: float = 0.35):
+    """Two-phase field from a GRF thresholded at 0 (g < 0 soft, g >= 0 hard)."""
+    g = gaussian_random_field((n, n, n), ell, seed)
+    hard = g >= 0.0
+    E = np.where(hard, E_hard, E_soft).astype(np.float64)
+    nu = np.where(hard, nu_hard, nu_soft).astype(np.float64)
+    return E, nu
+
+
+def lognormal_field(n: int, seed: int, ell: float = 6.0, mu: float = 0.0,
+                    sigma: float = 1.0, nu: float = 0.3):
+    """Log-normal Young's modulus E = exp(mu + sigma g), g a standardized GRF."""
+    g = gaussian_random_field((n, n, n), ell, seed)
+    E = np.exp(mu + sigma * g)
+    return E, np.full_like(E, nu)
+
+
+def laminate(shape_xyz, axis: int, layer_E, layer_nu, thickness):
+    """Layered material: whole voxel slabs normal to ``axis`` (0 = x).
+
+    ``thickness[k]`` voxels of phase k follow each other along ``axis``
+    (their sum must equal the grid size along that axis).
+    """
+    thickness = list(thickness)
+    if sum(thickness) != shape_xyz[axis]:
+        raise ValueError("layer thicknesses must sum to the grid size")
+    prof_E = np.repeat(np.asarray(layer_E, float), thickness)
+    prof_nu = np.repeat(np.asarray(layer_nu, float), thickness)
+    d = len(shape_xyz)
+    nshape = tuple(reversed(shape_xyz))
+    np_axis = d - 1 - axis
+    bshape = [1] * d
+    bshape[np_axis] = shape_xyz[axis]
+    E = np.broadcast_to(prof_E.reshape(bshape), nshape).copy()
+    nu = np.broadcast_to(prof_nu.reshape(bshape), nshape).copy()
+    return E, nu
+
+
+def random_cells(count: int, base_seed: int = 1000, sizes=(32, 48, 64, 96),
+                 nu: float = 0.3):
+    """Uneven batch of sphere microstructures.
+
+    Cell k uses seed base_seed + k for all its draws: size ~ U(sizes),
+    vf ~ U[0.1, 0.4], contrast ~ U[10, 100], spheres with r ~ U[4, 8] and
+    E = contrast inside, E = 1 outside.  Yields dicts with keys
+    n, vf, contrast, E, nu, achieved_vf.
+    """
+    for k in range(count):
+        rng = np.random.default_rng(base_seed + k)
+        n = int(rng.choice(np.asarray(sizes)))
+        vf = float(rng.uniform(0.1, 0.4))
+        contrast = float(rng.uniform(10.0, 100.0))
+        sub_seed = int(rng.integers(0, 2 ** 31 - 1))
+        mask, avf, _ = rsa_spheres(n, vf, sub_seed)
+        E = np.where(mask, contrast, 1.0).astype(np.float64)
+        yield dict(n=n, vf=vf, contrast=contrast, E=E,
+                   nu=np.full_like(E, nu), achieved_vf=avf)
+
+
+def spheres_cell(n: int, vf: float, seed: int, contrast: float,
+                 nu: float = 0.3, rmin: float = 4.0, rmax: float = 8.0):
+    """Sphere microstructure with E = contrast in the spheres, 1 outside."""
+    mask, avf, _ = rsa_spheres(n, vf, seed, rmin, rmax)
+    E = np.where(mask, contrast, 1.0).astype(np.float64)
+    return E, np.full_like(E, nu), avf
+
+
+# Named workloads (synthetic stand-ins, sizes as used by tests and bench).
+WORKLOADS = {
+    "circle2d_32": dict(dim=2, n=32, desc="2D plane strain 32x32, centred "
+                        "circle r=0.25L, E 1/10, nu 0.3, eps_xx=1e-2, FP64 tol 1e-10"),
+    "spheres3d_64": dict(dim=3, n=64, desc="3D 64^3 RSA spheres r 4-8 vf 0.3 "
+                         "seed 2, E 1:100, nu 0.3, 6 unit loads"),
+    "grf3d_256": dict(dim=3, n=256, desc="3D 256^3 two-phase thresholded GRF "
+                      "ell 8 seed 3, E 1:1000, nu 0.25/0.35, 6 loads, tol 1e-6"),
+    "batch512_spheres": dict(dim=3, n=None, desc="512 cells, N in {32,48,64,96}, "
+                             "RSA spheres vf 0.1-0.4, contrast 10-100, 6 loads"),
+    "lognormal3d_128": dict(dim=3, n=128, desc="3D 128^3 log-normal E (ell 6, "
+                            "seed 5), nu 0.3, J = C1111 + C2323, gradient wrt E"),
+}
