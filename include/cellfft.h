@@ -1,0 +1,140 @@
+/*
+ * cellfft: periodic linear-elastic cell problem on a voxel grid, solved on
+ * an AMD Instinct MI355X (gfx950) by conjugate gradients preconditioned with
+ * the Fourier-diagonalised inverse of a homogeneous reference stiffness.
+ *
+ * Problem (static, periodic special case of the elastic system of the
+ * paper's Sec. 2.1, eq. TimeHarmonicSystem with k = 0): on the cell
+ * Y = [0,L_x) x [0,L_y) (x [0,L_z)) with N_x x N_y (x N_z) voxels, nodes at
+ * the voxel corners (periodic), find the nodal fluctuation u minimising
+ *     sum over voxels v, simplices s of v:  |s| W_v(eps_bar + eps(u)),
+ * with W(eps) = lambda/2 tr(eps)^2 + mu eps:eps (Sec. 2.2, eq.
+ * LinearElastEnergy), lambda = nu E / ((1+nu)(1-2nu)), mu = E / (2(1+nu))
+ * (Sec. 6.3), and u linear on each simplex of the Kuhn subdivision (6
+ * tetrahedra per voxel sharing the main diagonal; 2 triangles per pixel).
+ * 2D is plane strain.  The effective stiffness is
+ *     C*_IJ = (1/|Y|) sum |s| (eps_bar^I + B u^I) : D (eps_bar^J + B u^J).
+ *
+ * Conventions
+ *   - Arrays over voxels/nodes are colexicographic, x fastest (Sec. 3.1):
+ *     index = i_x + N_x (i_y + N_y i_z).  Displacements are [d][n].
+ *   - Voigt order (11,22,33,23,13,12) in 3D, (11,22,12) in 2D; strains use
+ *     engineering shear (a unit shear load is gamma = 1).  C_out[3][3] is
+ *     the tensor component C*_2323.
+ *   - Every array passed in or out is owned by the caller.  Inputs are
+ *     copied before the call returns; the library keeps no caller pointer.
+ *     on_device = 1 means a device pointer on the handle's device, consumed
+ *     in order on the handle's stream; 0 means host memory.
+ *   - Calls that return host results synchronise the handle's stream.
+ *   - A handle is not thread-safe; different handles are independent.
+ *   - No C++ exception crosses this interface.  Negative status: nothing
+ *     was written.  CELL_NOT_CONVERGED: the best iterate and its results
+ *     were written and cell_info holds the residuals.  cell_last_error()
+ *     returns a thread-local message for the last failure.
+ *   - Grid sizes: N_a in {4,6,8,12,16,24,32,48,64,96,128,192,256} (even,
+ *     radix 2/3 FFTs); others return CELL_E_UNSUPPORTED.
+ */
+#ifndef CELLFFT_H
+#define CELLFFT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cell_s* cell_t;
+
+typedef enum {
+  CELL_OK = 0,
+  CELL_NOT_CONVERGED = 1,
+  CELL_E_ARG = -1,         /* invalid argument (null pointer, bad size, nu out of range) */
+  CELL_E_NOMEM = -2,       /* device allocation failed */
+  CELL_E_DEVICE = -3,      /* HIP runtime error */
+  CELL_E_STATE = -4,       /* call order violated (no material / no solve yet) */
+  CELL_E_NONFINITE = -5,   /* non-finite or non-positive Young's modulus */
+  CELL_E_BREAKDOWN = -6,   /* CG breakdown: p.Kp <= 0, r.z <= 0 or non-finite scalar */
+  CELL_E_UNSUPPORTED = -7  /* grid size without an FFT plan */
+} cell_status;
+
+enum { CELL_FP64 = 0, CELL_MIXED = 1 };
+
+typedef struct {
+  int dim;           /* 2 or 3 */
+  int n[3];          /* N_x, N_y, N_z (n[2] ignored in 2D) */
+  double len[3];     /* cell edge lengths; 0 means 1 */
+  int precision;     /* CELL_FP64: every kernel in FP64.  CELL_MIXED: stencil,
+                        FFT and vector updates in FP32, all reductions, CG
+                        scalars and residual recomputation in FP64 */
+  double tol;        /* stop when ||f - K u||_2 <= tol ||f||_2; 0 -> 1e-10 (FP64) / 1e-6 (mixed) */
+  int max_iter;      /* CG iteration cap; 0 -> 10000 */
+  int max_loads;     /* simultaneous load cases; 0 -> 3 (2D) / 6 (3D) */
+  void* stream;      /* hipStream_t to run on; NULL -> a library-owned stream */
+  int device;        /* HIP device ordinal; -1 -> the current device */
+} cell_config;
+
+typedef struct {
+  int nload;
+  int iters[6];            /* CG iterations per load */
+  int refinements[6];      /* FP64 residual recomputations per load */
+  double relres[6];        /* final ||f - K u|| / ||f||, recomputed in FP64 */
+  double hill_mandel_gap;  /* max_J |<sigma:eps>^J - sigma_bar^J . eps_bar^J| / max|C| (effective stiffness) */
+  double sym_gap;          /* max |S_IJ - S_JI| / max|S|, S = mean-stress form (effective stiffness) */
+  double seconds;          /* wall time of the call */
+} cell_info;
+
+/* Create a solver for one cell grid.  Allocates all device buffers for
+ * max_loads simultaneous loads.  *out receives the handle. */
+cell_status cell_create(const cell_config* cfg, cell_t* out);
+
+/* Per-voxel Young's modulus E (> 0, finite) and Poisson ratio nu in
+ * (-1, 0.5), n values each, colexicographic.  Copies the data; also fixes
+ * the preconditioner's reference medium (geometric means of the extreme
+ * bulk and shear moduli). */
+cell_status cell_set_material(cell_t c, const double* E, const double* nu, int on_device);
+
+/* Solve the cell problem for nload (<= max_loads) macro strains
+ * macro_strain[nload][nv] (host, Voigt, engineering shear).  Writes the
+ * mean stress sigma_bar[nload][nv] (host, may be NULL).  The solutions are
+ * kept for cell_get_displacement / cell_adjoint. */
+cell_status cell_solve(cell_t c, int nload, const double* macro_strain, double* mean_stress_out,
+                       cell_info* info);
+
+/* Solve the nv unit loads and write C*[nv][nv] (host, row-major, energy
+ * form; symmetric by construction).  info->sym_gap reports the asymmetry of
+ * the mean-stress form, info->hill_mandel_gap the energy mismatch. */
+cell_status cell_effective_stiffness(cell_t c, double* C_out, cell_info* info);
+
+/* Derivative of J = sum_IJ dJ_dC[I][J] C*_IJ with respect to the Young's
+ * modulus of every voxel (nu fixed), from the solutions of the last
+ * cell_effective_stiffness call: the problem is self-adjoint, so the adjoint
+ * states are the primal solutions and dC*_IJ/dE_v =
+ * (1/|Y|) sum_{s in v} |s| eps^I : (D_v / E_v) eps^J.  dJ_dC is host
+ * [nv][nv]; dJ_dE_out has n values.  CELL_E_STATE before any solve. */
+cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int on_device);
+
+/* Displacement fluctuation of load `load` of the last solve, [d][n], each
+ * component with zero nodal mean. */
+cell_status cell_get_displacement(cell_t c, int load, double* u_out, int on_device);
+
+void cell_destroy(cell_t c);
+
+const char* cell_last_error(void);
+
+/* ---- kernel-level entry points (parity checks of single steps) ---------- */
+
+/* q = K u with the stencil kernel of the given precision (CELL_FP64 or
+ * CELL_MIXED = FP32 arithmetic); u, q host [d][n]. */
+cell_status cell_apply_operator(cell_t c, int precision, const double* u, double* q_out);
+
+/* z = K_ref^{-1} r through the FFT passes of the given precision (the
+ * zero-frequency component of z is 0); r, z host [d][n]; r should have zero
+ * mean per component. */
+cell_status cell_apply_preconditioner(cell_t c, int precision, const double* r, double* z_out);
+
+/* Reference medium (lambda_0, mu_0) used by the preconditioner. */
+cell_status cell_reference_medium(cell_t c, double* lam0, double* mu0);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CELLFFT_H */

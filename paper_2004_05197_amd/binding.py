@@ -1,0 +1,225 @@
+"""ctypes binding of the HIP C-ABI library ``libcellfft.so``.
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  Arrays may be numpy arrays (host) or torch tensors; CUDA
+(HIP) torch tensors are passed as device pointers (``on_device = 1``) and
+the library runs on the stream given at construction (default: its own).
+
+Importing this module loads the library and raises ``ImportError`` if it
+has not been built (``python -m paper_2004_05197_amd.build``); there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcellfft.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2004_05197_amd.build`")
+
+_lib = ct.CDLL(LIB_PATH)
+
+CELL_OK = 0
+CELL_NOT_CONVERGED = 1
+CELL_E_ARG = -1
+CELL_E_NOMEM = -2
+CELL_E_DEVICE = -3
+CELL_E_STATE = -4
+CELL_E_NONFINITE = -5
+CELL_E_BREAKDOWN = -6
+CELL_E_UNSUPPORTED = -7
+FP64 = 0
+MIXED = 1
+
+STATUS_NAMES = {0: "CELL_OK", 1: "CELL_NOT_CONVERGED", -1: "CELL_E_ARG", -2: "CELL_E_NOMEM",
+                -3: "CELL_E_DEVICE", -4: "CELL_E_STATE", -5: "CELL_E_NONFINITE",
+                -6: "CELL_E_BREAKDOWN", -7: "CELL_E_UNSUPPORTED"}
+
+
+class CellConfig(ct.Structure):
+    _fields_ = [("dim", ct.c_int), ("n", ct.c_int * 3), ("len", ct.c_double * 3),
+                ("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
+                ("max_loads", ct.c_int), ("stream", ct.c_void_p), ("device", ct.c_int)]
+
+
+class CellInfo(ct.Structure):
+    _fields_ = [("nload", ct.c_int), ("iters", ct.c_int * 6), ("refinements", ct.c_int * 6),
+                ("relres", ct.c_double * 6), ("hill_mandel_gap", ct.c_double),
+                ("sym_gap", ct.c_double), ("seconds", ct.c_double)]
+
+    def as_dict(self):
+        k = self.nload
+        return dict(nload=k, iters=list(self.iters[:k]), refinements=list(self.refinements[:k]),
+                    relres=list(self.relres[:k]), hill_mandel_gap=self.hill_mandel_gap,
+                    sym_gap=self.sym_gap, seconds=self.seconds)
+
+
+_P = ct.c_void_p
+_D = ct.POINTER(ct.c_double)
+_SIGS = {
+    "cell_create": (ct.c_int, [ct.POINTER(CellConfig), ct.POINTER(_P)]),
+    "cell_set_material": (ct.c_int, [_P, _P, _P, ct.c_int]),
+    "cell_solve": (ct.c_int, [_P, ct.c_int, _P, _P, ct.POINTER(CellInfo)]),
+    "cell_effective_stiffness": (ct.c_int, [_P, _P, ct.POINTER(CellInfo)]),
+    "cell_adjoint": (ct.c_int, [_P, _P, _P, ct.c_int]),
+    "cell_get_displacement": (ct.c_int, [_P, ct.c_int, _P, ct.c_int]),
+    "cell_destroy": (None, [_P]),
+    "cell_last_error": (ct.c_char_p, []),
+    "cell_apply_operator": (ct.c_int, [_P, ct.c_int, _P, _P]),
+    "cell_apply_preconditioner": (ct.c_int, [_P, ct.c_int, _P, _P]),
+    "cell_reference_medium": (ct.c_int, [_P, _D, _D]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class CellError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def last_error():
+    return _lib.cell_last_error().decode()
+
+
+def _check(status):
+    if status < 0:
+        raise CellError(status, last_error())
+    return status
+
+
+def _is_torch(x):
+    try:
+        import torch
+        return isinstance(x, torch.Tensor)
+    except ImportError:
+        return False
+
+
+def _in_ptr(x, count):
+    """(pointer, on_device, keepalive) for a float64 input of `count` values."""
+    if _is_torch(x):
+        if x.dtype != __import__("torch").float64 or x.numel() != count:
+            raise ValueError("expected a float64 tensor with %d values" % count)
+        x = x.contiguous()
+        if x.is_cuda:
+            return ct.c_void_p(x.data_ptr()), 1, x
+        a = x.numpy()
+    else:
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64)).ravel()
+        if a.size != count:
+            raise ValueError("expected %d values, got %d" % (count, a.size))
+    return a.ctypes.data_as(ct.c_void_p), 0, a
+
+
+class Cell:
+    """One periodic cell grid on the GPU (wraps a ``cell_t`` handle)."""
+
+    def __init__(self, shape, precision=FP64, tol=0.0, max_iter=0, max_loads=0,
+                 lengths=None, stream=None, device=-1):
+        shape = tuple(int(s) for s in shape)
+        self.dim = len(shape)
+        cfg = CellConfig()
+        cfg.dim = self.dim
+        for a in range(3):
+            cfg.n[a] = shape[a] if a < self.dim else 1
+            cfg.len[a] = (lengths[a] if lengths is not None and a < self.dim else 0.0)
+        cfg.precision = int(precision)
+        cfg.tol = float(tol)
+        cfg.max_iter = int(max_iter)
+        cfg.max_loads = int(max_loads)
+        cfg.stream = None if stream is None else ct.c_void_p(getattr(stream, "cuda_stream", stream))
+        cfg.device = int(device)
+        h = ct.c_void_p()
+        _check(_lib.cell_create(ct.byref(cfg), ct.byref(h)))
+        self._h = h
+        self.shape = shape
+        self.n = int(np.prod(shape))
+        self.nv = 3 if self.dim == 2 else 6
+        self.precision = int(precision)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cell_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- solver calls ---------------------------------------------------------
+    def set_material(self, E, nu):
+        pe, de, ke = _in_ptr(E, self.n)
+        pn, dn, kn = _in_ptr(nu, self.n)
+        if de != dn:
+            raise ValueError("E and nu must both be on the host or both on the device")
+        _check(_lib.cell_set_material(self._h, pe, pn, de))
+
+    def solve(self, macro_strains):
+        eb = np.ascontiguousarray(np.atleast_2d(np.asarray(macro_strains, dtype=np.float64)))
+        nl = eb.shape[0]
+        out = np.zeros((nl, self.nv))
+        info = CellInfo()
+        st = _check(_lib.cell_solve(self._h, nl, eb.ctypes.data_as(ct.c_void_p),
+                                    out.ctypes.data_as(ct.c_void_p), ct.byref(info)))
+        return out, dict(info.as_dict(), status=STATUS_NAMES[st])
+
+    def effective_stiffness(self):
+        C = np.zeros((self.nv, self.nv))
+        info = CellInfo()
+        st = _check(_lib.cell_effective_stiffness(self._h, C.ctypes.data_as(ct.c_void_p), ct.byref(info)))
+        return C, dict(info.as_dict(), status=STATUS_NAMES[st])
+
+    def adjoint(self, dJ_dC, out=None):
+        a = np.ascontiguousarray(np.asarray(dJ_dC, dtype=np.float64).reshape(self.nv, self.nv))
+        if out is not None and _is_torch(out) and out.is_cuda:
+            _check(_lib.cell_adjoint(self._h, a.ctypes.data_as(ct.c_void_p), ct.c_void_p(out.data_ptr()), 1))
+            return out
+        g = np.zeros(self.n)
+        _check(_lib.cell_adjoint(self._h, a.ctypes.data_as(ct.c_void_p), g.ctypes.data_as(ct.c_void_p), 0))
+        return g
+
+    def displacement(self, load=0):
+        u = np.zeros((self.dim, self.n))
+        _check(_lib.cell_get_displacement(self._h, int(load), u.ctypes.data_as(ct.c_void_p), 0))
+        return u
+
+    def apply_operator(self, u, precision=None):
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()
+        q = np.zeros_like(u)
+        p = self.precision if precision is None else precision
+        _check(_lib.cell_apply_operator(self._h, int(p), u.ctypes.data_as(ct.c_void_p),
+                                        q.ctypes.data_as(ct.c_void_p)))
+        return q
+
+    def apply_preconditioner(self, r, precision=None):
+        r = np.ascontiguousarray(np.asarray(r, dtype=np.float64)).ravel()
+        z = np.zeros_like(r)
+        p = self.precision if precision is None else precision
+        _check(_lib.cell_apply_preconditioner(self._h, int(p), r.ctypes.data_as(ct.c_void_p),
+                                              z.ctypes.data_as(ct.c_void_p)))
+        return z
+
+    def reference_medium(self):
+        lam = ct.c_double()
+        mu = ct.c_double()
+        _check(_lib.cell_reference_medium(self._h, ct.byref(lam), ct.byref(mu)))
+        return lam.value, mu.value
+
+
+def exported_symbols():
+    """Names of the C-ABI functions bound here."""
+    return sorted(_SIGS)

@@ -1,0 +1,220 @@
+// Device-side building blocks shared by the cell-problem kernels (gfx950).
+//
+//  * cpx<T>            minimal complex type (T = float | double)
+//  * block reductions  wave64 shuffle trees + fixed-order cross-wave sum, so
+//                      every FP64 reduction is deterministic (no float atomics)
+//  * last-block        per-launch "last block done" finalisation: every block
+//                      writes one partial, the block that arrives last sums the
+//                      partials in index order and updates per-load scalars
+//  * LDS FFT engine    in-place Stockham autosort FFT over a tile of columns
+//                      held in LDS, compile-time length N = 2^a 3^b, radix
+//                      8/4/3/2 codelets in registers, twiddles from a table.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cellfft {
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct cpx { T re, im; };
+
+template <typename T> __device__ __forceinline__ cpx<T> mk(T a, T b) { return cpx<T>{a, b}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator*(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cpx<T> conj(cpx<T> a) { return {a.re, -a.im}; }
+// multiply by -i (forward sign) or +i (inverse sign)
+template <typename T, bool INV> __device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) {
+  if (INV) return {-a.im, a.re};   // +i * a
+  return {a.im, -a.re};            // -i * a
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  sh must hold NT/64
+// doubles.  Order is fixed by the lane/wave structure (deterministic).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  v = wave_sum(v);
+  if ((tid & (WAVE - 1)) == 0) sh[tid / WAVE] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / WAVE; ++w) s += sh[w];
+  }
+  __syncthreads();
+  return s;
+}
+
+// Thread 0 of each block calls this after storing its partial.  Returns true
+// in exactly one block (the last to arrive).  Release/acquire at agent scope
+// makes every block's partial visible to the finalising block across XCDs.
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned nblocks) {
+  __threadfence();
+  unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+  return prev == nblocks - 1;
+}
+
+// Fixed-order sum of nparts partials by the whole (finalising) block.
+// Call only in the finalising block, after a barrier that follows
+// arrive_last; every thread takes an agent-scope acquire before reading.
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double* parts, int nparts, double* sh) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NT) v += parts[i];
+  return block_sum<NT>(v, sh);
+}
+
+// ---------------------------------------------------------------- FFT codelets
+template <typename T, int R, bool INV> struct Dft;
+
+template <typename T, bool INV> struct Dft<T, 2, INV> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  }
+};
+
+template <typename T, bool INV> struct Dft<T, 3, INV> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T h = T(0.86602540378443864676);  // sqrt(3)/2
+    cpx<T> t = v[1] + v[2];
+    cpx<T> m = v[0] - t * T(0.5);
+    cpx<T> d = (v[1] - v[2]) * h;
+    v[0] = v[0] + t;
+    cpx<T> id = mul_mi<T, INV>(d);  // -i d (fwd) / +i d (inv)
+    v[1] = m + id;
+    v[2] = m - id;
+  }
+};
+
+template <typename T, bool INV> struct Dft<T, 4, INV> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+    cpx<T> t2 = v[1] + v[3], t3 = mul_mi<T, INV>(v[1] - v[3]);
+    v[0] = t0 + t2;
+    v[2] = t0 - t2;
+    v[1] = t1 + t3;
+    v[3] = t1 - t3;
+  }
+};
+
+template <typename T, bool INV> struct Dft<T, 8, INV> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T r = T(0.70710678118654752440);
+    cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<T, 4, INV>::run(e);
+    Dft<T, 4, INV>::run(o);
+    // o[k] *= W8^k, W8 = exp(-+ 2 pi i / 8)
+    cpx<T> o1 = o[1], o3 = o[3];
+    if (!INV) {
+      o[1] = mk<T>((o1.re + o1.im) * r, (o1.im - o1.re) * r);
+      o[3] = mk<T>((o3.im - o3.re) * r, -(o3.re + o3.im) * r);
+    } else {
+      o[1] = mk<T>((o1.re - o1.im) * r, (o1.im + o1.re) * r);
+      o[3] = mk<T>(-(o3.re + o3.im) * r, (o3.re - o3.im) * r);
+    }
+    o[2] = mul_mi<T, INV>(o[2]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = e[k] + o[k];
+      v[k + 4] = e[k] - o[k];
+    }
+  }
+};
+
+// radix schedule: 8 first (except 16 = 4*4), then 4, 2, 3
+__host__ __device__ constexpr int pick_radix(int n) {
+  return (n % 8 == 0 && n != 16) ? 8 : (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : n;
+}
+
+// Tile layouts.  ColMajorTile: element (n, c) at n*CS + c (columns fastest,
+// used for pencils gathered from strided global memory).  RowTile: element
+// (n, c) at c*RS + n (rows of contiguous data, used by the x passes).
+template <int CS> struct ColTile {
+  static __device__ __forceinline__ int at(int n, int c) { return n * CS + c; }
+  static constexpr bool col_fast = true;
+};
+template <int RS> struct RowTile {
+  static __device__ __forceinline__ int at(int n, int c) { return c * RS + n; }
+  static constexpr bool col_fast = false;
+};
+
+// One Stockham stage (radix R, span NS) over NCOL columns of length N.
+// tw[m * TWS] = exp(-2 pi i m / N) for m in [0, N).
+template <typename T, int N, int R, int NS, bool INV, int NCOL, int NT, int TWS, class L>
+__device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
+  constexpr int NB = N / R;
+  constexpr int TOT = NB * NCOL;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  cpx<T> v[PER][R];
+  int dst[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * NT;
+    if ((TOT % NT == 0) || b < TOT) {
+      int j, col;
+      if (L::col_fast) { col = b % NCOL; j = b / NCOL; }
+      else { j = b % NB; col = b / NB; }
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[L::at(j + r * NB, col)];
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[(r * k * (N / (NS * R))) * TWS];
+          if (INV) w.im = -w.im;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      Dft<T, R, INV>::run(v[q]);
+      dst[q] = ((j / NS) * NS * R + k) | (col << 20);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = tid + q * NT;
+    if ((TOT % NT == 0) || b < TOT) {
+      const int idx = dst[q] & 0xFFFFF, col = dst[q] >> 20;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[L::at(idx + r * NS, col)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int REM, int NS, bool INV, int NCOL, int NT, int TWS, class L>
+__device__ __forceinline__ void fft_stages(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
+  if constexpr (REM > 1) {
+    constexpr int R = pick_radix(REM);
+    static_assert(REM % R == 0, "length must be 2^a 3^b");
+    fft_stage<T, N, R, NS, INV, NCOL, NT, TWS, L>(buf, tw);
+    fft_stages<T, N, REM / R, NS * R, INV, NCOL, NT, TWS, L>(buf, tw);
+  }
+}
+
+// In-place FFT (unnormalised; INV uses the +i sign) of NCOL columns of length
+// N held in LDS.  Must be called by all NT threads; ends with a barrier.
+template <typename T, int N, bool INV, int NCOL, int NT, int TWS, class L>
+__device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
+  fft_stages<T, N, N, 1, INV, NCOL, NT, TWS, L>(buf, tw);
+}
+
+}  // namespace cellfft

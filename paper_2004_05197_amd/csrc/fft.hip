@@ -1,0 +1,670 @@
+// FFT passes of the preconditioned CG iteration (gfx950).
+//
+// Spectrum layout ("packed half spectrum"): every x-row of nx reals becomes
+// nx/2 complex slots; slot 0 holds X[0] + i X[nx/2] (both real), slots
+// 1..nx/2-1 hold X[k].  After the y pass, column slot 0 is unmixed per
+// z-plane: rows 1..ny/2-1 hold the spectrum of the X[0] field (wavevector
+// (0, ky)), rows ny/2+1..ny-1 the spectrum of the X[nx/2] field
+// (wavevector (nx/2, ky)), row 0 holds the two real ky = 0, ny/2 values of
+// the X[0] field and row ny/2 those of the X[nx/2] field ("real pairs").
+// The last pass (z in 3D, y in 2D) separates each real pair with the
+// mirrored frequency of the same pencil.  The spectrum therefore has
+// exactly the size of a real field and every pencil is self-contained.
+//
+// Kernels (all unnormalised DFTs; 1/n is folded into the preconditioner):
+//   k_xfwd   r -= alpha q, ||r||^2 partials, real-to-complex FFT along x
+//   k_ypass  complex FFT along y (+ slot-0 unmix / remix)
+//   k_zpass  FFT along z, z_hat = K_ref^{-1} r_hat / n, r.z partials
+//            (Parseval), inverse FFT along z          [3D]
+//   k_ylast  same with y as the last axis               [2D]
+//   k_xinv   complex-to-real FFT along x, x += alpha p, p = z + beta p
+#include "kernels.h"
+
+namespace cellfft {
+
+// ------------------------------------------------------------------ helpers
+template <typename T> struct V2;
+template <> struct V2<float> { using type = float2; };
+template <> struct V2<double> { using type = double2; };
+
+template <typename T> __device__ __forceinline__ bool finite_pos(T v) { return v > T(0) && v < T(1e300); }
+
+__device__ __forceinline__ bool load_live(const LoadState* st, bool allow_converged) {
+  const int s = st->state;
+  return s == ST_ACTIVE || (allow_converged && s == ST_CONVERGED);
+}
+
+// rows per block of the x passes: about 2048 (fp32) / 1024 (fp64) complex
+template <typename T, int M> constexpr int x_rpb() {
+  constexpr int tgt = sizeof(T) == 4 ? 2048 : 1024;
+  return (tgt / M) < 1 ? 1 : (tgt / M);
+}
+template <typename T> constexpr int y_tx() { return sizeof(T) == 4 ? 16 : 8; }
+template <typename T> constexpr int z_tx() { return sizeof(T) == 4 ? 8 : 4; }
+
+// ================================================================= x forward
+template <typename T, int M>
+__global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
+  constexpr int RPB = x_rpb<T, M>();
+  constexpr int RS = M + 1;
+  using T2 = typename V2<T>::type;
+  __shared__ cpx<T> buf[RPB * RS];
+  __shared__ cpx<T> tws[2 * M];
+  __shared__ double sh[NT / WAVE];
+  const int l = blockIdx.y;
+  LoadState* st = a.st + l;
+  if (!load_live(st, false)) return;
+  const T alpha = (T)st->alpha;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * M; i += NT) tws[i] = a.tw[i];
+  const int row0 = blockIdx.x * RPB;
+  T2* r2 = reinterpret_cast<T2*>(a.r + l * a.lstride);
+  const T2* q2 = reinterpret_cast<const T2*>(a.q + l * a.lstride);
+  double acc = 0.0;
+  for (int e = tid; e < RPB * M; e += NT) {
+    const int rr = e / M, m = e - rr * M;
+    const int row = row0 + rr;
+    cpx<T> v = {T(0), T(0)};
+    if (row < a.nrows) {
+      const long long off = (long long)row * M + m;
+      T2 rv = r2[off];
+      const T2 qv = q2[off];
+      rv.x -= alpha * qv.x;
+      rv.y -= alpha * qv.y;
+      r2[off] = rv;
+      acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
+      v = {rv.x, rv.y};
+    }
+    buf[rr * RS + m] = v;
+  }
+  __syncthreads();
+  fft_lds<T, M, false, RPB, NT, 2, RowTile<RS>>(buf, tws);
+  // split the half-length transform into the packed real spectrum
+  constexpr int KH = M / 2 + 1;
+  for (int e = tid; e < RPB * KH; e += NT) {
+    const int rr = e / KH, k = e - rr * KH;
+    cpx<T>* Z = buf + rr * RS;
+    if (k == 0) {
+      const cpx<T> z0 = Z[0];
+      Z[0] = {z0.re + z0.im, z0.re - z0.im};
+    } else {
+      const cpx<T> zk = Z[k], zm = Z[M - k];
+      const cpx<T> E = (zk + conj(zm)) * T(0.5);
+      const cpx<T> D = (zk - conj(zm)) * T(0.5);
+      const cpx<T> O = {D.im, -D.re};  // D / i
+      const cpx<T> WO = cmul(tws[k], O);
+      Z[k] = E + WO;
+      if (M - k != k) Z[M - k] = conj(E - WO);
+    }
+  }
+  __syncthreads();
+  cpx<T>* S = a.S + l * (a.lstride / 2);
+  for (int e = tid; e < RPB * M; e += NT) {
+    const int rr = e / M, m = e - rr * M;
+    const int row = row0 + rr;
+    if (row < a.nrows) S[(long long)row * M + m] = buf[rr * RS + m];
+  }
+  // ||r||^2 partials and finalisation by the last block of this load
+  const double bs = block_sum<NT>(acc, sh);
+  __shared__ bool last;
+  if (tid == 0) {
+    a.red.slot_parts(RED_RR, l)[blockIdx.x] = bs;
+    last = arrive_last(a.red.slot_cnt(RED_RR, l), gridDim.x);
+  }
+  __syncthreads();
+  if (last) {
+    const double rr = sum_partials<NT>(a.red.slot_parts(RED_RR, l), gridDim.x, sh);
+    if (tid == 0) {
+      *a.red.slot_cnt(RED_RR, l) = 0u;
+      st->rr = rr;
+      if (!(rr == rr) || rr > 1e300) {
+        st->state = ST_BREAKDOWN;
+      } else if (rr <= st->thr) {
+        st->state = ST_CONVERGED;
+      } else if (st->iters >= st->maxit) {
+        st->state = ST_CONVERGED;
+        st->maxit_hit = 1;
+      }
+    }
+  }
+}
+
+// ================================================================= x inverse
+template <typename T, int M>
+__global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
+  constexpr int RPB = x_rpb<T, M>();
+  constexpr int RS = M + 1;
+  using T2 = typename V2<T>::type;
+  __shared__ cpx<T> buf[RPB * RS];
+  __shared__ cpx<T> tws[2 * M];
+  const int l = blockIdx.y;
+  LoadState* st = a.st + l;
+  if (!load_live(st, true)) return;
+  const T alpha = (T)st->alpha;
+  const T beta = (T)st->beta;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 2 * M; i += NT) tws[i] = a.tw[i];
+  const int row0 = blockIdx.x * RPB;
+  const cpx<T>* S = a.S + l * (a.lstride / 2);
+  for (int e = tid; e < RPB * M; e += NT) {
+    const int rr = e / M, m = e - rr * M;
+    const int row = row0 + rr;
+    buf[rr * RS + m] = row < a.nrows ? S[(long long)row * M + m] : cpx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  constexpr int KH = M / 2 + 1;
+  for (int e = tid; e < RPB * KH; e += NT) {
+    const int rr = e / KH, k = e - rr * KH;
+    cpx<T>* X = buf + rr * RS;
+    if (k == 0) {
+      const cpx<T> x0 = X[0];
+      X[0] = {x0.re + x0.im, x0.re - x0.im};
+    } else {
+      const cpx<T> xk = X[k], xm = X[M - k];
+      const cpx<T> E = xk + conj(xm);
+      const cpx<T> O = cmul(xk - conj(xm), conj(tws[k]));
+      X[k] = {E.re - O.im, E.im + O.re};  // E + i O
+      if (M - k != k) X[M - k] = {E.re + O.im, -E.im + O.re};  // conj(E) + i conj(O)
+    }
+  }
+  __syncthreads();
+  fft_lds<T, M, true, RPB, NT, 2, RowTile<RS>>(buf, tws);
+  T2* x2 = reinterpret_cast<T2*>(a.x + l * a.lstride);
+  T2* p2 = reinterpret_cast<T2*>(a.p + l * a.lstride);
+  for (int e = tid; e < RPB * M; e += NT) {
+    const int rr = e / M, m = e - rr * M;
+    const int row = row0 + rr;
+    if (row < a.nrows) {
+      const long long off = (long long)row * M + m;
+      const cpx<T> z = buf[rr * RS + m];
+      const T2 po = p2[off];
+      T2 xv = x2[off];
+      xv.x += alpha * po.x;
+      xv.y += alpha * po.y;
+      x2[off] = xv;
+      T2 pn;
+      pn.x = z.re + beta * po.x;
+      pn.y = z.im + beta * po.y;
+      p2[off] = pn;
+    }
+  }
+  __shared__ bool last;
+  __syncthreads();
+  if (tid == 0) last = arrive_last(a.red.slot_cnt(RED_XINV, l), gridDim.x);
+  __syncthreads();
+  if (last && tid == 0) {
+    *a.red.slot_cnt(RED_XINV, l) = 0u;
+    if (st->state == ST_CONVERGED) st->state = ST_DONE;
+  }
+}
+
+// ================================================================= y pass 3D
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(NT) void k_ypass(YArgs<T> a) {
+  constexpr int TX = y_tx<T>();
+  __shared__ cpx<T> buf[N * TX];
+  __shared__ cpx<T> tws[N];
+  const int l = blockIdx.y;
+  if (!load_live(a.st + l, true)) return;
+  const int M = a.nx / 2;
+  const int ntile = (M + TX - 1) / TX;
+  int b = blockIdx.x;
+  const int tile = b % ntile;
+  b /= ntile;
+  const int z = b % a.nz;
+  const int c = b / a.nz;
+  const int s0 = tile * TX;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tws[i] = a.tw[i];
+  cpx<T>* base = a.S + l * a.lstrideC + ((long long)(c * a.nz + z) * a.ny) * M + s0;
+  for (int e = tid; e < N * TX; e += NT) {
+    const int y = e / TX, s = e - y * TX;
+    buf[e] = (s0 + s < M) ? base[(long long)y * M + s] : cpx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  if (INV && s0 == 0) {
+    // remix column 0: c(k) = A(k) + i B(k)
+    cpx<T> v[(N + NT - 1) / NT];
+#pragma unroll
+    for (int q = 0; q < (N + NT - 1) / NT; ++q) {
+      const int k = tid + q * NT;
+      if (k < N) {
+        const cpx<T> rk = buf[k * TX], rm = buf[((N - k) % N) * TX];
+        if (k == 0) v[q] = {rk.re, buf[(N / 2) * TX].re};
+        else if (k == N / 2) v[q] = {buf[0].im, rk.im};
+        else if (k < N / 2) v[q] = {rk.re + rm.im, rk.im + rm.re};       // r_k + i conj(r_{N-k})
+        else v[q] = {rm.re - rk.im, -rm.im + rk.re};                     // conj(r_{N-k}) + i r_k
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (N + NT - 1) / NT; ++q) {
+      const int k = tid + q * NT;
+      if (k < N) buf[k * TX] = v[q];
+    }
+    __syncthreads();
+  }
+  fft_lds<T, N, INV, TX, NT, 1, ColTile<TX>>(buf, tws);
+  if (!INV && s0 == 0) {
+    // unmix column 0 into the X[0] field (rows < N/2) and X[nx/2] field
+    cpx<T> v[(N + NT - 1) / NT];
+#pragma unroll
+    for (int q = 0; q < (N + NT - 1) / NT; ++q) {
+      const int k = tid + q * NT;
+      if (k < N) {
+        const cpx<T> ck = buf[k * TX], cm = buf[((N - k) % N) * TX];
+        if (k == 0) v[q] = {ck.re, buf[(N / 2) * TX].re};
+        else if (k == N / 2) v[q] = {buf[0].im, ck.im};
+        else if (k < N / 2) v[q] = {(ck.re + cm.re) * T(0.5), (ck.im - cm.im) * T(0.5)};  // (c_k + conj c_-k)/2
+        else v[q] = {(ck.im + cm.im) * T(0.5), (cm.re - ck.re) * T(0.5)};              // (c_k - conj c_-k)/(2i)
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (N + NT - 1) / NT; ++q) {
+      const int k = tid + q * NT;
+      if (k < N) buf[k * TX] = v[q];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < N * TX; e += NT) {
+    const int y = e / TX, s = e - y * TX;
+    if (s0 + s < M) base[(long long)y * M + s] = buf[e];
+  }
+}
+
+// ===================================================== reference symbol
+// Fourier symbol of the homogeneous reference operator on the Kuhn mesh
+// (real symmetric), theta_a = pi k_a / N_a, sigma_a = 2 sin(theta_a) / h_a:
+//   K_cc = d! w [lam sigma_c^2 + mu (|sigma|^2 + sigma_c^2)]
+//   K_cd = 2 w (lam + mu) sigma_c sigma_d [2 cos(th_c + th_d) + cos(th_c + th_d + 2 th_e)]  (3D)
+//   K_01 = 2 w (lam + mu) sigma_0 sigma_1 cos(th_0 + th_1)                                   (2D)
+// Applies z = K^{-1} r * inv_n to a complex 3-vector (2-vector).
+template <typename T>
+__device__ __forceinline__ void sym_solve3(const PArgs<T>& P, int kx, int ky, int kz,
+                                           const cpx<T>* r, cpx<T>* z) {
+  const T sx = P.trig[0][2 * kx], cx = P.trig[0][2 * kx + 1];
+  const T sy = P.trig[1][2 * ky], cy = P.trig[1][2 * ky + 1];
+  const T sz = P.trig[2][2 * kz], cz = P.trig[2][2 * kz + 1];
+  const T gx = T(2) * sx * P.ih[0], gy = T(2) * sy * P.ih[1], gz = T(2) * sz * P.ih[2];
+  const T gx2 = gx * gx, gy2 = gy * gy, gz2 = gz * gz;
+  const T ss = gx2 + gy2 + gz2;
+  const T c6 = T(6) * P.w;
+  const T lam = P.lam0, mu = P.mu0;
+  const T a00 = c6 * (lam * gx2 + mu * (ss + gx2));
+  const T a11 = c6 * (lam * gy2 + mu * (ss + gy2));
+  const T a22 = c6 * (lam * gz2 + mu * (ss + gz2));
+  const T co = T(2) * P.w * (lam + mu);
+  // pair (c, d) with third axis e: cos(tc + td) and cos(tc + td + 2 te)
+  auto off = [&](T sc, T cc, T sd, T cd, T se, T ce, T gc, T gd) {
+    const T c2 = cc * cd - sc * sd;
+    const T s2 = sc * cd + cc * sd;
+    const T c2e = T(1) - T(2) * se * se;
+    const T s2e = T(2) * se * ce;
+    return co * gc * gd * (T(2) * c2 + (c2 * c2e - s2 * s2e));
+  };
+  const T a01 = off(sx, cx, sy, cy, sz, cz, gx, gy);
+  const T a02 = off(sx, cx, sz, cz, sy, cy, gx, gz);
+  const T a12 = off(sy, cy, sz, cz, sx, cx, gy, gz);
+  const T b00 = a11 * a22 - a12 * a12;
+  const T b11 = a00 * a22 - a02 * a02;
+  const T b22 = a00 * a11 - a01 * a01;
+  const T b01 = a02 * a12 - a01 * a22;
+  const T b02 = a01 * a12 - a11 * a02;
+  const T b12 = a01 * a02 - a00 * a12;
+  const T det = a00 * b00 + a01 * b01 + a02 * b02;
+  const T s = P.inv_n / det;
+  z[0] = (r[0] * b00 + r[1] * b01 + r[2] * b02) * s;
+  z[1] = (r[0] * b01 + r[1] * b11 + r[2] * b12) * s;
+  z[2] = (r[0] * b02 + r[1] * b12 + r[2] * b22) * s;
+}
+
+template <typename T>
+__device__ __forceinline__ void sym_solve2(const PArgs<T>& P, int kx, int ky,
+                                           const cpx<T>* r, cpx<T>* z) {
+  const T sx = P.trig[0][2 * kx], cx = P.trig[0][2 * kx + 1];
+  const T sy = P.trig[1][2 * ky], cy = P.trig[1][2 * ky + 1];
+  const T gx = T(2) * sx * P.ih[0], gy = T(2) * sy * P.ih[1];
+  const T gx2 = gx * gx, gy2 = gy * gy, ss = gx2 + gy2;
+  const T c2w = T(2) * P.w;
+  const T a00 = c2w * (P.lam0 * gx2 + P.mu0 * (ss + gx2));
+  const T a11 = c2w * (P.lam0 * gy2 + P.mu0 * (ss + gy2));
+  const T a01 = c2w * (P.lam0 + P.mu0) * gx * gy * (cx * cy - sx * sy);
+  const T det = a00 * a11 - a01 * a01;
+  const T s = P.inv_n / det;
+  z[0] = (r[0] * a11 - r[1] * a01) * s;
+  z[1] = (r[1] * a00 - r[0] * a01) * s;
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ T redot(const cpx<T>* r, const cpx<T>* z) {
+  T s = T(0);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s += r[c].re * z[c].re + r[c].im * z[c].im;
+  return s;
+}
+
+// finalisation of r.z (shared by the 3D and 2D last passes)
+__device__ __forceinline__ void finalize_rz(LoadState* st, double rz) {
+  const bool conv = st->state == ST_CONVERGED;
+  if (!(rz == rz) || (!(rz > 0.0) && !conv)) {
+    st->state = ST_BREAKDOWN;
+    return;
+  }
+  st->beta = (st->first || !(st->rz > 0.0)) ? 0.0 : rz / st->rz;
+  st->rz = rz;
+  st->first = 0;
+}
+
+// ===================================================== z pass (3D, last)
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
+  constexpr int TX = z_tx<T>();
+  constexpr int NC = 3 * TX;  // columns: component-major, then slot
+  __shared__ cpx<T> buf[N * NC];
+  __shared__ cpx<T> tws[N];
+  __shared__ double sh[NT / WAVE];
+  const int l = blockIdx.y;
+  LoadState* st = a.st + l;
+  if (!load_live(st, true)) return;
+  const int M = a.nx / 2;
+  const int ntile = (M + TX - 1) / TX;
+  const int tile = blockIdx.x % ntile;
+  const int y = blockIdx.x / ntile;
+  const int s0 = tile * TX;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tws[i] = a.tw[i];
+  cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
+  const long long cstride = (long long)a.nz * a.ny * M;   // component
+  const long long zstride = (long long)a.ny * M;          // z plane
+  for (int e = tid; e < N * NC; e += NT) {
+    const int z = e / NC, rem = e - z * NC;
+    const int c = rem / TX, s = rem - c * TX;
+    buf[e] = (s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  fft_lds<T, N, false, NC, NT, 1, ColTile<NC>>(buf, tws);
+  const bool pair_row = (s0 == 0) && (y == 0 || y == a.ny / 2);
+  double acc = 0.0;
+  // ordinary wavevectors (weight 2: each stands for itself and its conjugate)
+  for (int e = tid; e < N * TX; e += NT) {
+    const int kz = e / TX, s = e - kz * TX;
+    const int slot = s0 + s;
+    if (slot >= M || (slot == 0 && pair_row)) continue;
+    const int kx = slot == 0 ? (y < a.ny / 2 ? 0 : M) : slot;
+    cpx<T> r[3], z[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = buf[kz * NC + c * TX + s];
+    sym_solve3(a, kx, y, kz, r, z);
+    acc += 2.0 * (double)redot<T, 3>(r, z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) buf[kz * NC + c * TX + s] = z[c];
+  }
+  if (pair_row) {
+    // column slot 0 of rows ky = 0, ny/2: w = A_hat + i B_hat with A, B real
+    // along z; A: (kx, ky) = (0 | M, 0), B: (0 | M, ny/2).
+    const int kxf = (y == 0) ? 0 : M;
+    constexpr int Q = (N + NT - 1) / NT;
+    cpx<T> out[Q][3];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int kz = tid + q * NT;
+      if (kz < N) {
+        const int km = (N - kz) % N;
+        cpx<T> A[3], B[3], zA[3], zB[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const cpx<T> wk = buf[kz * NC + c * TX], wm = buf[km * NC + c * TX];
+          A[c] = {(wk.re + wm.re) * T(0.5), (wk.im - wm.im) * T(0.5)};
+          B[c] = {(wk.im + wm.im) * T(0.5), (wm.re - wk.re) * T(0.5)};
+        }
+        if (y == 0 && kz == 0) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) zA[c] = {T(0), T(0)};
+        } else {
+          sym_solve3(a, kxf, 0, kz, A, zA);
+        }
+        sym_solve3(a, kxf, a.ny / 2, kz, B, zB);
+        acc += (double)redot<T, 3>(A, zA) + (double)redot<T, 3>(B, zB);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[q][c] = {zA[c].re - zB[c].im, zA[c].im + zB[c].re};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int kz = tid + q * NT;
+      if (kz < N) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) buf[kz * NC + c * TX] = out[q][c];
+      }
+    }
+  }
+  __syncthreads();
+  fft_lds<T, N, true, NC, NT, 1, ColTile<NC>>(buf, tws);
+  for (int e = tid; e < N * NC; e += NT) {
+    const int z = e / NC, rem = e - z * NC;
+    const int c = rem / TX, s = rem - c * TX;
+    if (s0 + s < M) base[c * cstride + z * zstride + s] = buf[e];
+  }
+  const double bs = block_sum<NT>(acc, sh);
+  __shared__ bool last;
+  if (tid == 0) {
+    a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
+    last = arrive_last(a.red.slot_cnt(RED_RZ, l), gridDim.x);
+  }
+  __syncthreads();
+  if (last) {
+    const double rz = sum_partials<NT>(a.red.slot_parts(RED_RZ, l), gridDim.x, sh);
+    if (tid == 0) {
+      *a.red.slot_cnt(RED_RZ, l) = 0u;
+      finalize_rz(st, rz);
+    }
+  }
+}
+
+// ===================================================== y pass (2D, last)
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_ylast(PArgs<T> a) {
+  constexpr int TX = z_tx<T>();
+  constexpr int NC = 2 * TX;
+  __shared__ cpx<T> buf[N * NC];
+  __shared__ cpx<T> tws[N];
+  __shared__ double sh[NT / WAVE];
+  const int l = blockIdx.y;
+  LoadState* st = a.st + l;
+  if (!load_live(st, true)) return;
+  const int M = a.nx / 2;
+  const int s0 = blockIdx.x * TX;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tws[i] = a.tw[i];
+  cpx<T>* base = a.S + l * a.lstrideC + s0;
+  const long long cstride = (long long)a.ny * M;
+  for (int e = tid; e < N * NC; e += NT) {
+    const int y = e / NC, rem = e - y * NC;
+    const int c = rem / TX, s = rem - c * TX;
+    buf[e] = (s0 + s < M) ? base[c * cstride + (long long)y * M + s] : cpx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  fft_lds<T, N, false, NC, NT, 1, ColTile<NC>>(buf, tws);
+  double acc = 0.0;
+  for (int e = tid; e < N * TX; e += NT) {
+    const int ky = e / TX, s = e - ky * TX;
+    const int slot = s0 + s;
+    if (slot >= M || slot == 0) continue;
+    cpx<T> r[2], z[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) r[c] = buf[ky * NC + c * TX + s];
+    sym_solve2(a, slot, ky, r, z);
+    acc += 2.0 * (double)redot<T, 2>(r, z);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) buf[ky * NC + c * TX + s] = z[c];
+  }
+  if (s0 == 0) {
+    constexpr int Q = (N + NT - 1) / NT;
+    cpx<T> out[Q][2];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int ky = tid + q * NT;
+      if (ky < N) {
+        const int km = (N - ky) % N;
+        cpx<T> A[2], B[2], zA[2], zB[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const cpx<T> wk = buf[ky * NC + c * TX], wm = buf[km * NC + c * TX];
+          A[c] = {(wk.re + wm.re) * T(0.5), (wk.im - wm.im) * T(0.5)};
+          B[c] = {(wk.im + wm.im) * T(0.5), (wm.re - wk.re) * T(0.5)};
+        }
+        if (ky == 0) {
+          zA[0] = zA[1] = {T(0), T(0)};
+        } else {
+          sym_solve2(a, 0, ky, A, zA);
+        }
+        sym_solve2(a, M, ky, B, zB);
+        acc += (double)redot<T, 2>(A, zA) + (double)redot<T, 2>(B, zB);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) out[q][c] = {zA[c].re - zB[c].im, zA[c].im + zB[c].re};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int ky = tid + q * NT;
+      if (ky < N) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) buf[ky * NC + c * TX] = out[q][c];
+      }
+    }
+  }
+  __syncthreads();
+  fft_lds<T, N, true, NC, NT, 1, ColTile<NC>>(buf, tws);
+  for (int e = tid; e < N * NC; e += NT) {
+    const int y = e / NC, rem = e - y * NC;
+    const int c = rem / TX, s = rem - c * TX;
+    if (s0 + s < M) base[c * cstride + (long long)y * M + s] = buf[e];
+  }
+  const double bs = block_sum<NT>(acc, sh);
+  __shared__ bool last;
+  if (tid == 0) {
+    a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
+    last = arrive_last(a.red.slot_cnt(RED_RZ, l), gridDim.x);
+  }
+  __syncthreads();
+  if (last) {
+    const double rz = sum_partials<NT>(a.red.slot_parts(RED_RZ, l), gridDim.x, sh);
+    if (tid == 0) {
+      *a.red.slot_cnt(RED_RZ, l) = 0u;
+      finalize_rz(st, rz);
+    }
+  }
+}
+
+// ================================================================ dispatch
+#define CELLFFT_NSIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+#define CELLFFT_MSIZES(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+
+bool fft_size_ok(int n) {
+  switch (n) {
+#define C_(v) case v:
+    CELLFFT_NSIZES(C_)
+#undef C_
+    return true;
+    default:
+      return false;
+  }
+}
+
+int xpass_blocks(int nx, int nrows, bool fp64) {
+  const int M = nx / 2;
+  const int tgt = fp64 ? 1024 : 2048;
+  const int rpb = (tgt / M) < 1 ? 1 : tgt / M;
+  return (nrows + rpb - 1) / rpb;
+}
+
+template <typename T>
+hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, hipStream_t s) {
+  const int nb = xpass_blocks(nx, a.nrows, sizeof(T) == 8);
+  dim3 grid(nb, nload);
+  switch (nx / 2) {
+#define C_(m) case m: hipLaunchKernelGGL((k_xfwd<T, m>), grid, dim3(NT), 0, s, a); break;
+    CELLFFT_MSIZES(C_)
+#undef C_
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xinv(const XArgs<T>& a, int nx, int nload, hipStream_t s) {
+  const int nb = xpass_blocks(nx, a.nrows, sizeof(T) == 8);
+  dim3 grid(nb, nload);
+  switch (nx / 2) {
+#define C_(m) case m: hipLaunchKernelGGL((k_xinv<T, m>), grid, dim3(NT), 0, s, a); break;
+    CELLFFT_MSIZES(C_)
+#undef C_
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, hipStream_t s) {
+  constexpr int TX = y_tx<T>();
+  const int M = a.nx / 2;
+  const int ntile = (M + TX - 1) / TX;
+  dim3 grid(ntile * a.nz * a.ncomp, nload);
+  switch (a.ny) {
+#define C_(n)                                                                  \
+  case n:                                                                      \
+    if (inverse) hipLaunchKernelGGL((k_ypass<T, n, true>), grid, dim3(NT), 0, s, a); \
+    else hipLaunchKernelGGL((k_ypass<T, n, false>), grid, dim3(NT), 0, s, a);       \
+    break;
+    CELLFFT_NSIZES(C_)
+#undef C_
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_last(const PArgs<T>& a, int dim, int nload, hipStream_t s) {
+  constexpr int TX = z_tx<T>();
+  const int M = a.nx / 2;
+  const int ntile = (M + TX - 1) / TX;
+  if (dim == 3) {
+    dim3 grid(ntile * a.ny, nload);
+    switch (a.nz) {
+#define C_(n) case n: hipLaunchKernelGGL((k_zpass<T, n>), grid, dim3(NT), 0, s, a); break;
+      CELLFFT_NSIZES(C_)
+#undef C_
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    dim3 grid(ntile, nload);
+    switch (a.ny) {
+#define C_(n) case n: hipLaunchKernelGGL((k_ylast<T, n>), grid, dim3(NT), 0, s, a); break;
+      CELLFFT_NSIZES(C_)
+#undef C_
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_xfwd<float>(const XArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_xfwd<double>(const XArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_xinv<float>(const XArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_xinv<double>(const XArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_ypass<float>(const YArgs<float>&, bool, int, hipStream_t);
+template hipError_t launch_ypass<double>(const YArgs<double>&, bool, int, hipStream_t);
+template hipError_t launch_last<float>(const PArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_last<double>(const PArgs<double>&, int, int, hipStream_t);
+
+}  // namespace cellfft

@@ -1,0 +1,616 @@
+// Fused P1 finite-element operator on the Kuhn subdivision (gfx950).
+//
+// Per voxel and per simplex s (3D: the 6 axis permutations p, vertices
+// v0 = 0, v_j = v_{j-1} + e_{p_j}; 2D: the 2 triangles), the displacement
+// gradient is exact from successive differences along the monotone vertex
+// path, G[:, p_j] = (u(v_j) - u(v_{j-1})) / h_{p_j}; the stress is the linear
+// isotropic law sigma = lambda tr(eps) I + 2 mu eps (eps = sym G); the
+// divergence scatter B^T sigma sends |s| sigma[:, p_j] / h_{p_j} with
+// opposite signs to the two ends of path step j.  2D is plane strain.
+//
+// k_stencil3   3D, z-marching tiles of bx x by nodes: each layer of voxels
+//              is computed once per tile (plus a one-voxel halo), corner
+//              contributions are exchanged through LDS, the +z contributions
+//              are carried in registers to the next node plane.
+//              mode 0: q = K p with p.q partials, alpha = rz / pq finalised
+//              mode 1: r = -B^T D (eps_bar + B u) with ||r||^2 (FP64)
+// k_stencil2   2D analogue (node-centric gather; the 2D grids are small)
+// k_homog      energy-form effective stiffness and mean stress partials
+// k_grad       per-voxel derivative of sum_IJ a_IJ C*_IJ w.r.t. E
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace cellfft {
+
+__constant__ int kPerm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+template <int I, int J> struct SymIdx;  // tensor (I, J) -> storage (00,11,22,12,02,01)
+template <> struct SymIdx<0, 0> { static constexpr int v = 0; };
+template <> struct SymIdx<1, 1> { static constexpr int v = 1; };
+template <> struct SymIdx<2, 2> { static constexpr int v = 2; };
+template <> struct SymIdx<1, 2> { static constexpr int v = 3; };
+template <> struct SymIdx<2, 1> { static constexpr int v = 3; };
+template <> struct SymIdx<0, 2> { static constexpr int v = 4; };
+template <> struct SymIdx<2, 0> { static constexpr int v = 4; };
+template <> struct SymIdx<0, 1> { static constexpr int v = 5; };
+template <> struct SymIdx<1, 0> { static constexpr int v = 5; };
+
+__host__ __device__ constexpr int sym_idx(int i, int j) {
+  return i == j ? i : (i + j == 3 ? 3 : (i + j == 2 ? 4 : 5));
+}
+
+// One simplex of the Kuhn split (compile-time permutation) for one voxel.
+// u[c][k]: corner c = ox + 2 oy + 4 oz, component k.  lw = lambda |s|,
+// mw = mu |s|, sb = |s| D eps_bar (tensor storage) if MACRO.
+template <typename T, int A0, int A1, int A2, bool MACRO>
+__device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw, const T* ih,
+                                         const T* sb, T (&f)[8][3]) {
+  constexpr int c0 = 0, c1 = 1 << A0, c2 = c1 | (1 << A1), c3 = 7;
+  T G[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    G[k][A0] = (u[c1][k] - u[c0][k]) * ih[A0];
+    G[k][A1] = (u[c2][k] - u[c1][k]) * ih[A1];
+    G[k][A2] = (u[c3][k] - u[c2][k]) * ih[A2];
+  }
+  const T tr = G[0][0] + G[1][1] + G[2][2];
+  const T lt = lw * tr;
+  T s[6];
+  s[0] = lt + T(2) * mw * G[0][0];
+  s[1] = lt + T(2) * mw * G[1][1];
+  s[2] = lt + T(2) * mw * G[2][2];
+  s[3] = mw * (G[1][2] + G[2][1]);
+  s[4] = mw * (G[0][2] + G[2][0]);
+  s[5] = mw * (G[0][1] + G[1][0]);
+  if (MACRO) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) s[i] += sb[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T t1 = s[sym_idx(k, A0)] * ih[A0];
+    const T t2 = s[sym_idx(k, A1)] * ih[A1];
+    const T t3 = s[sym_idx(k, A2)] * ih[A2];
+    f[c0][k] -= t1;
+    f[c1][k] += t1 - t2;
+    f[c2][k] += t2 - t3;
+    f[c3][k] += t3;
+  }
+}
+
+template <typename T, bool MACRO>
+__device__ __forceinline__ void voxel3(const T (&u)[8][3], T lw, T mw, const T* ih, const T* sb,
+                                       T (&f)[8][3]) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[c][k] = T(0);
+  simplex3<T, 0, 1, 2, MACRO>(u, lw, mw, ih, sb, f);
+  simplex3<T, 0, 2, 1, MACRO>(u, lw, mw, ih, sb, f);
+  simplex3<T, 1, 0, 2, MACRO>(u, lw, mw, ih, sb, f);
+  simplex3<T, 1, 2, 0, MACRO>(u, lw, mw, ih, sb, f);
+  simplex3<T, 2, 0, 1, MACRO>(u, lw, mw, ih, sb, f);
+  simplex3<T, 2, 1, 0, MACRO>(u, lw, mw, ih, sb, f);
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// macro stress |s| D eps_bar in tensor storage
+template <typename T>
+__device__ __forceinline__ void macro_stress(const double* e, T lw, T mw, T* sb) {
+  const T tr = (T)(e[0] + e[1] + e[2]);
+  sb[0] = lw * tr + T(2) * mw * (T)e[0];
+  sb[1] = lw * tr + T(2) * mw * (T)e[1];
+  sb[2] = lw * tr + T(2) * mw * (T)e[2];
+  sb[3] = T(2) * mw * (T)e[3];
+  sb[4] = T(2) * mw * (T)e[4];
+  sb[5] = T(2) * mw * (T)e[5];
+}
+
+// =========================================================== 3D stencil
+// T: arithmetic type of u and the material; TO: output type.
+template <typename T, typename TO, int MODE>
+__global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int tz) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* pl = reinterpret_cast<T*>(smem_raw);
+  const int PW = bx + 2, PH = by + 2, PP = PW * PH;
+  T* cb = pl + 6 * PP;
+  const int VW = bx + 1, VV = VW * (by + 1);
+  __shared__ double sh[NT / WAVE];
+  __shared__ bool last;
+  const int tid = threadIdx.x;
+  const int tx = tid % bx, ty = tid / bx;
+  const bool worker = ty < by;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const long long n = a.g.n;
+  const int x0 = blockIdx.x * bx, y0 = blockIdx.y * by, z0 = blockIdx.z * tz;
+  const T ih[3] = {(T)(1.0 / a.g.h[0]), (T)(1.0 / a.g.h[1]), (T)(1.0 / a.g.h[2])};
+  const T w = (T)(a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0);
+  const int nextra = bx + by + 1;
+  const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int nblk = gridDim.x * gridDim.y * gridDim.z;
+  for (int l = 0; l < a.nload; ++l) {
+    bool live;
+    if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
+    else live = a.only_load < 0 || a.only_load == l;
+    if (!live) continue;
+    const T* u = a.u ? a.u + l * a.lstride : nullptr;
+    TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
+    T sbv[6];
+    const double* eb = a.eps[l];
+    auto load_plane = [&](int zp, int slot) {
+      const int zw = wrapi(zp, nz);
+      T* dst = pl + slot * 3 * PP;
+      for (int e = tid; e < 3 * PP; e += NT) {
+        const int c = e / PP, rem = e - c * PP;
+        const int py = rem / PW, px = rem - py * PW;
+        const int gx = wrapi(x0 - 1 + px, nx), gy = wrapi(y0 - 1 + py, ny);
+        dst[e] = u ? u[c * n + ((long long)zw * ny + gy) * nx + gx] : T(0);
+      }
+    };
+    // voxel (vx, vy) of layer k (lower corner node (x0+vx, y0+vy, k)):
+    // writes the exchanged corners to cb, returns the (1,1,oz) corner.
+    auto voxel = [&](int vx, int vy, int k, int L, T (&own)[2][3]) {
+      const T* p0 = pl + (L & 1) * 3 * PP;        // plane k
+      const T* p1 = pl + ((L + 1) & 1) * 3 * PP;  // plane k+1
+      T uu[8][3];
+#pragma unroll
+      for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+          for (int ox = 0; ox < 2; ++ox)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              uu[ox + 2 * oy + 4 * oz][c] =
+                  (oz ? p1 : p0)[c * PP + (vy + 1 + oy) * PW + (vx + 1 + ox)];
+      const long long vid = ((long long)wrapi(k, nz) * ny + wrapi(y0 + vy, ny)) * nx + wrapi(x0 + vx, nx);
+      const T lw = a.mat[2 * vid] * w, mw = a.mat[2 * vid + 1] * w;
+      T f[8][3];
+      if (MODE == 1) {
+        macro_stress(eb, lw, mw, sbv);
+        voxel3<T, true>(uu, lw, mw, ih, sbv, f);
+      } else {
+        voxel3<T, false>(uu, lw, mw, ih, sbv, f);
+      }
+      const int vi = (vy + 1) * VW + (vx + 1);
+#pragma unroll
+      for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cb[((0 * 2 + oz) * 3 + c) * VV + vi] = f[0 + 4 * oz][c];  // corner (0,0)
+          cb[((1 * 2 + oz) * 3 + c) * VV + vi] = f[1 + 4 * oz][c];  // corner (1,0)
+          cb[((2 * 2 + oz) * 3 + c) * VV + vi] = f[2 + 4 * oz][c];  // corner (0,1)
+          own[oz][c] = f[3 + 4 * oz][c];                            // corner (1,1)
+        }
+    };
+    double acc = 0.0;
+    T carry[3] = {T(0), T(0), T(0)};
+    load_plane(z0 - 1, 0);
+    for (int L = 0; L <= tz; ++L) {
+      const int k = z0 - 1 + L;
+      load_plane(k + 1, (L + 1) & 1);
+      __syncthreads();
+      T own[2][3];
+      if (worker) voxel(tx - 1, ty - 1, k, L, own);
+      for (int e = tid; e < nextra; e += NT) {
+        T dummy[2][3];
+        if (e < by) voxel(bx - 1, e - 1, k, L, dummy);
+        else voxel(e - by - 1, by - 1, k, L, dummy);
+      }
+      __syncthreads();
+      if (worker) {
+        const int i00 = (ty + 1) * VW + (tx + 1);  // voxel (tx, ty)
+        const int i10 = (ty + 1) * VW + tx;        // voxel (tx-1, ty)
+        const int i01 = ty * VW + (tx + 1);        // voxel (tx, ty-1)
+        T val[3], nc[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          val[c] = carry[c] + own[0][c] + cb[((0 * 2 + 0) * 3 + c) * VV + i00] +
+                   cb[((1 * 2 + 0) * 3 + c) * VV + i10] + cb[((2 * 2 + 0) * 3 + c) * VV + i01];
+          nc[c] = own[1][c] + cb[((0 * 2 + 1) * 3 + c) * VV + i00] +
+                  cb[((1 * 2 + 1) * 3 + c) * VV + i10] + cb[((2 * 2 + 1) * 3 + c) * VV + i01];
+        }
+        const int gx = x0 + tx, gy = y0 + ty;
+        if (L >= 1 && k < nz && gx < nx && gy < ny) {
+          const long long node = ((long long)k * ny + gy) * nx + gx;
+          const T* pk = pl + (L & 1) * 3 * PP;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            if (MODE == 0) {
+              out[c * n + node] = (TO)val[c];
+              acc += (double)pk[c * PP + (ty + 1) * PW + (tx + 1)] * (double)val[c];
+            } else {
+              out[c * n + node] = (TO)(-val[c]);
+              acc += (double)val[c] * (double)val[c];
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) carry[c] = nc[c];
+      }
+      __syncthreads();
+    }
+    const double bs = block_sum<NT>(acc, sh);
+    // partial per load, one counter per launch
+    if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
+  }
+  const int cslot = MODE == 0 ? RED_PQ : RED_RES;
+  if (tid == 0) last = arrive_last(a.red.slot_cnt(cslot, 0), nblk);
+  __syncthreads();
+  if (last) {
+    for (int l = 0; l < a.nload; ++l) {
+      bool live;
+      if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
+      else live = a.only_load < 0 || a.only_load == l;
+      if (!live) continue;
+      const double s = sum_partials<NT>(a.red.slot_parts(cslot, l), nblk, sh);
+      if (tid == 0) {
+        if (MODE == 0) {
+          LoadState* st = a.st + l;
+          st->pq = s;
+          st->iters += 1;
+          if (!(s > 0.0) || !(s < 1e300)) st->state = ST_BREAKDOWN;
+          else st->alpha = st->rz / s;
+        } else {
+          a.res2[l] = s;
+        }
+      }
+    }
+    if (tid == 0) *a.red.slot_cnt(cslot, 0) = 0u;
+  }
+}
+
+// =========================================================== 2D stencil
+// plane strain, 2 triangles per pixel: (0,0)->(1,0)->(1,1), (0,0)->(0,1)->(1,1)
+template <typename T, int A0, int A1, bool MACRO>
+__device__ __forceinline__ void simplex2(const T (&u)[4][2], T lw, T mw, const T* ih, const T* sb,
+                                         T (&f)[4][2]) {
+  constexpr int c0 = 0, c1 = 1 << A0, c2 = 3;
+  T G[2][2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    G[k][A0] = (u[c1][k] - u[c0][k]) * ih[A0];
+    G[k][A1] = (u[c2][k] - u[c1][k]) * ih[A1];
+  }
+  const T lt = lw * (G[0][0] + G[1][1]);
+  T s[3];  // 00, 11, 01
+  s[0] = lt + T(2) * mw * G[0][0];
+  s[1] = lt + T(2) * mw * G[1][1];
+  s[2] = mw * (G[0][1] + G[1][0]);
+  if (MACRO) {
+    s[0] += sb[0];
+    s[1] += sb[1];
+    s[2] += sb[2];
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const T t1 = s[k == A0 ? k : 2] * ih[A0];
+    const T t2 = s[k == A1 ? k : 2] * ih[A1];
+    f[c0][k] -= t1;
+    f[c1][k] += t1 - t2;
+    f[c2][k] += t2;
+  }
+}
+
+template <typename T, typename TO, int MODE>
+__global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
+  __shared__ double sh[NT / WAVE];
+  __shared__ bool last;
+  const int l = blockIdx.y;
+  bool live;
+  if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
+  else live = a.only_load < 0 || a.only_load == l;
+  if (!live) return;
+  const int nx = a.g.nx, ny = a.g.ny;
+  const long long n = a.g.n;
+  const T ih[2] = {(T)(1.0 / a.g.h[0]), (T)(1.0 / a.g.h[1])};
+  const T w = (T)(a.g.h[0] * a.g.h[1] / 2.0);
+  const T* u = a.u ? a.u + l * a.lstride : nullptr;
+  TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
+  const double* eb = a.eps[l];
+  double acc = 0.0;
+  const long long node = (long long)blockIdx.x * NT + threadIdx.x;
+  if (node < n) {
+    const int i = (int)(node % nx), j = (int)(node / nx);
+    T val[2] = {T(0), T(0)};
+    // the node is corner (ox, oy) of pixel (i - ox, j - oy)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const int pi = wrapi(i - ox, nx), pj = wrapi(j - oy, ny);
+        T uu[4][2];
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx) {
+            const long long nd = (long long)wrapi(pj + cy, ny) * nx + wrapi(pi + cx, nx);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) uu[cx + 2 * cy][c] = u ? u[c * n + nd] : T(0);
+          }
+        const long long vid = (long long)pj * nx + pi;
+        const T lw = a.mat[2 * vid] * w, mw = a.mat[2 * vid + 1] * w;
+        T sb[3];
+        if (MODE == 1) {
+          const T tr = (T)(eb[0] + eb[1]);
+          sb[0] = lw * tr + T(2) * mw * (T)eb[0];
+          sb[1] = lw * tr + T(2) * mw * (T)eb[1];
+          sb[2] = T(2) * mw * (T)eb[5];
+        }
+        T f[4][2] = {};
+        simplex2<T, 0, 1, MODE == 1>(uu, lw, mw, ih, sb, f);
+        simplex2<T, 1, 0, MODE == 1>(uu, lw, mw, ih, sb, f);
+        val[0] += f[ox + 2 * oy][0];
+        val[1] += f[ox + 2 * oy][1];
+      }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (MODE == 0) {
+        out[c * n + node] = (TO)val[c];
+        acc += (double)(u ? u[c * n + node] : T(0)) * (double)val[c];
+      } else {
+        out[c * n + node] = (TO)(-val[c]);
+        acc += (double)val[c] * (double)val[c];
+      }
+    }
+  }
+  const int cslot = MODE == 0 ? RED_PQ : RED_RES;
+  const double bs = block_sum<NT>(acc, sh);
+  if (threadIdx.x == 0) {
+    a.red.slot_parts(cslot, l)[blockIdx.x] = bs;
+    last = arrive_last(a.red.slot_cnt(cslot, l), gridDim.x);
+  }
+  __syncthreads();
+  if (last) {
+    const double s = sum_partials<NT>(a.red.slot_parts(cslot, l), gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      *a.red.slot_cnt(cslot, l) = 0u;
+      if (MODE == 0) {
+        LoadState* st = a.st + l;
+        st->pq = s;
+        st->iters += 1;
+        if (!(s > 0.0) || !(s < 1e300)) st->state = ST_BREAKDOWN;
+        else st->alpha = st->rz / s;
+      } else {
+        a.res2[l] = s;
+      }
+    }
+  }
+}
+
+// ============================================== homogenisation (FP64, once)
+// Total strain of every simplex: eps = eps_bar + sym(G).  Accumulates per
+// block  C_IJ += |s| eps^I : sigma^J  and  sbar_J += |s| sigma^J.
+template <int D>
+__device__ __forceinline__ void simplex_strain(const double* ucorner /*[nc][D]*/, const int* path,
+                                               const double* ih, const double* eb, double* e) {
+  // path: D axes; corners along the monotone path
+  double G[3][3] = {};
+  int c = 0;
+  for (int j = 0; j < D; ++j) {
+    const int a = path[j];
+    const int cn = c | (1 << a);
+    for (int k = 0; k < D; ++k) G[k][a] = (ucorner[cn * D + k] - ucorner[c * D + k]) * ih[a];
+    c = cn;
+  }
+  if (D == 3) {
+    e[0] = eb[0] + G[0][0];
+    e[1] = eb[1] + G[1][1];
+    e[2] = eb[2] + G[2][2];
+    e[3] = eb[3] + 0.5 * (G[1][2] + G[2][1]);
+    e[4] = eb[4] + 0.5 * (G[0][2] + G[2][0]);
+    e[5] = eb[5] + 0.5 * (G[0][1] + G[1][0]);
+  } else {
+    e[0] = eb[0] + G[0][0];
+    e[1] = eb[1] + G[1][1];
+    e[2] = 0.0;
+    e[3] = 0.0;
+    e[4] = 0.0;
+    e[5] = eb[5] + 0.5 * (G[0][1] + G[1][0]);
+  }
+}
+
+__device__ __forceinline__ void stress_from_strain(const double* e, double lam, double mu, double* s) {
+  const double tr = e[0] + e[1] + e[2];
+  s[0] = lam * tr + 2.0 * mu * e[0];
+  s[1] = lam * tr + 2.0 * mu * e[1];
+  s[2] = lam * tr + 2.0 * mu * e[2];
+  s[3] = 2.0 * mu * e[3];
+  s[4] = 2.0 * mu * e[4];
+  s[5] = 2.0 * mu * e[5];
+}
+
+__device__ __forceinline__ double contract(const double* e, const double* s) {
+  return e[0] * s[0] + e[1] * s[1] + e[2] * s[2] + 2.0 * (e[3] * s[3] + e[4] * s[4] + e[5] * s[5]);
+}
+
+__device__ __forceinline__ void gather_corners(const HArgs& a, int l, int i, int j, int k, double* uc) {
+  const int D = a.g.dim;
+  const int nc = D == 3 ? 8 : 4;
+  const double* u = a.u + l * a.lstride;
+  for (int c = 0; c < nc; ++c) {
+    const int ox = c & 1, oy = (c >> 1) & 1, oz = (c >> 2) & 1;
+    const long long nd = ((long long)wrapi(k + oz, a.g.nz) * a.g.ny + wrapi(j + oy, a.g.ny)) * a.g.nx +
+                         wrapi(i + ox, a.g.nx);
+    for (int q = 0; q < D; ++q) uc[c * D + q] = u[q * a.g.n + nd];
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_homog(HArgs a) {
+  __shared__ double sh[NT / WAVE];
+  const int D = a.g.dim;
+  const int nl = a.nload;
+  const int nv = D == 3 ? 6 : 3;
+  const int nval = nl * nl + nl * nv;
+  const double ih[3] = {1.0 / a.g.h[0], 1.0 / a.g.h[1], 1.0 / a.g.h[2]};
+  const double w = D == 3 ? a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0 : a.g.h[0] * a.g.h[1] / 2.0;
+  const int nsimp = D == 3 ? 6 : 2;
+  const int perm2[2][2] = {{0, 1}, {1, 0}};
+  double C[6][6] = {};
+  double sb[6][6] = {};
+  for (long long v = (long long)blockIdx.x * NT + threadIdx.x; v < a.g.n; v += (long long)gridDim.x * NT) {
+    const int i = (int)(v % a.g.nx);
+    const int j = (int)((v / a.g.nx) % a.g.ny);
+    const int k = (int)(v / ((long long)a.g.nx * a.g.ny));
+    const double lam = a.mat[2 * v], mu = a.mat[2 * v + 1];
+    double uc[6][24];
+    for (int l = 0; l < nl; ++l) gather_corners(a, l, i, j, k, uc[l]);
+    for (int p = 0; p < nsimp; ++p) {
+      int path[3];
+      for (int q = 0; q < D; ++q) path[q] = D == 3 ? kPerm3[p][q] : perm2[p][q];
+      double e[6][6], s[6][6];
+      for (int l = 0; l < nl; ++l) {
+        if (D == 3) simplex_strain<3>(uc[l], path, ih, a.eps[l], e[l]);
+        else simplex_strain<2>(uc[l], path, ih, a.eps[l], e[l]);
+        stress_from_strain(e[l], lam, mu, s[l]);
+      }
+      for (int J = 0; J < nl; ++J) {
+        for (int I = 0; I < nl; ++I) C[I][J] += w * contract(e[I], s[J]);
+        if (D == 3) {
+          for (int q = 0; q < 6; ++q) sb[J][q] += w * s[J][q];
+        } else {
+          sb[J][0] += w * s[J][0];
+          sb[J][1] += w * s[J][1];
+          sb[J][2] += w * s[J][5];
+        }
+      }
+    }
+  }
+  for (int t = 0; t < nval; ++t) {
+    double v;
+    if (t < nl * nl) v = C[t / nl][t % nl];
+    else v = sb[(t - nl * nl) / nv][(t - nl * nl) % nv];
+    const double bs = block_sum<NT>(v, sh);
+    if (threadIdx.x == 0) a.parts[(long long)t * a.nblk + blockIdx.x] = bs;
+  }
+}
+
+// one block per value: fixed-order sum of the block partials
+__global__ __launch_bounds__(NT) void k_sum_rows(const double* parts, int nblk, double scale, double* out) {
+  __shared__ double sh[NT / WAVE];
+  const double* row = parts + (long long)blockIdx.x * nblk;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += NT) v += row[i];
+  const double s = block_sum<NT>(v, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s * scale;
+}
+
+__global__ __launch_bounds__(NT) void k_grad(HArgs a) {
+  const int D = a.g.dim;
+  const int nl = a.nload;
+  const double ih[3] = {1.0 / a.g.h[0], 1.0 / a.g.h[1], 1.0 / a.g.h[2]};
+  const double w = D == 3 ? a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0 : a.g.h[0] * a.g.h[1] / 2.0;
+  const double vol = a.g.h[0] * a.g.h[1] * (D == 3 ? a.g.h[2] : 1.0) * a.g.n;
+  const int nsimp = D == 3 ? 6 : 2;
+  const int perm2[2][2] = {{0, 1}, {1, 0}};
+  for (long long v = (long long)blockIdx.x * NT + threadIdx.x; v < a.g.n; v += (long long)gridDim.x * NT) {
+    const int i = (int)(v % a.g.nx);
+    const int j = (int)((v / a.g.nx) % a.g.ny);
+    const int k = (int)(v / ((long long)a.g.nx * a.g.ny));
+    const double E = a.E[v];
+    const double lam = a.mat[2 * v] / E, mu = a.mat[2 * v + 1] / E;
+    double uc[6][24];
+    for (int l = 0; l < nl; ++l) gather_corners(a, l, i, j, k, uc[l]);
+    double g = 0.0;
+    for (int p = 0; p < nsimp; ++p) {
+      int path[3];
+      for (int q = 0; q < D; ++q) path[q] = D == 3 ? kPerm3[p][q] : perm2[p][q];
+      double e[6][6], s[6][6];
+      for (int l = 0; l < nl; ++l) {
+        if (D == 3) simplex_strain<3>(uc[l], path, ih, a.eps[l], e[l]);
+        else simplex_strain<2>(uc[l], path, ih, a.eps[l], e[l]);
+        stress_from_strain(e[l], lam, mu, s[l]);
+      }
+      for (int I = 0; I < nl; ++I)
+        for (int J = 0; J < nl; ++J)
+          if (a.a[I][J] != 0.0) g += a.a[I][J] * w * contract(e[I], s[J]);
+    }
+    a.grad[v] = g / vol;
+  }
+}
+
+// ================================================================ launchers
+struct Tile3 {
+  int bx, by, tz;
+};
+
+// x extent: largest divisor of nx up to 64 (fp32) / 32 (fp64, LDS budget)
+static Tile3 pick_tile3(const Geom& g, bool fp64) {
+  Tile3 t;
+  t.bx = 1;
+  for (int d = fp64 ? 32 : 64; d >= 1; --d)
+    if (g.nx % d == 0) { t.bx = d; break; }
+  t.by = NT / t.bx;
+  if (t.by > g.ny) t.by = g.ny;
+  t.tz = g.nz >= 16 ? 16 : g.nz;
+  return t;
+}
+
+template <typename T>
+static size_t stencil3_lds(const Tile3& t) {
+  return sizeof(T) * (6 * (t.bx + 2) * (t.by + 2) + 18 * (t.bx + 1) * (t.by + 1));
+}
+
+int stencil_blocks(const Geom& g) {
+  if (g.dim == 2) return (int)((g.n + NT - 1) / NT);
+  int mb = 0;
+  for (int fp64 = 0; fp64 < 2; ++fp64) {
+    const Tile3 t = pick_tile3(g, fp64);
+    mb = std::max(mb, (g.nx / t.bx) * ((g.ny + t.by - 1) / t.by) * ((g.nz + t.tz - 1) / t.tz));
+  }
+  return mb;
+}
+
+template <typename T, typename TO, int MODE>
+static hipError_t launch_stencil_impl(const KArgs<T>& a, hipStream_t s) {
+  const Geom& g = a.g;
+  if (g.dim == 3) {
+    const Tile3 t = pick_tile3(g, sizeof(T) == 8);
+    dim3 grid(g.nx / t.bx, (g.ny + t.by - 1) / t.by, (g.nz + t.tz - 1) / t.tz);
+    const size_t lds = stencil3_lds<T>(t);
+    hipLaunchKernelGGL((k_stencil3<T, TO, MODE>), grid, dim3(NT), lds, s, a, t.bx, t.by, t.tz);
+  } else {
+    dim3 grid((unsigned)((g.n + NT - 1) / NT), a.nload);
+    hipLaunchKernelGGL((k_stencil2<T, TO, MODE>), grid, dim3(NT), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stencil(const KArgs<T>& a, hipStream_t s) {
+  if (a.mode == 0) return launch_stencil_impl<T, T, 0>(a, s);
+  return launch_stencil_impl<T, T, 1>(a, s);
+}
+
+hipError_t launch_residual_mixed(const KArgs<double>& a, float* out32, hipStream_t s) {
+  KArgs<double> b = a;
+  b.out = out32;
+  return launch_stencil_impl<double, float, 1>(b, s);
+}
+
+int homog_blocks(const Geom& g) {
+  long long nb = (g.n + NT - 1) / NT;
+  return (int)(nb < 1024 ? nb : 1024);
+}
+
+hipError_t launch_homog(const HArgs& a, hipStream_t s) {
+  const int nv = a.g.dim == 3 ? 6 : 3;
+  const int nval = a.nload * a.nload + a.nload * nv;
+  hipLaunchKernelGGL(k_homog, dim3(a.nblk), dim3(NT), 0, s, a);
+  const double vol = a.g.h[0] * a.g.h[1] * (a.g.dim == 3 ? a.g.h[2] : 1.0) * a.g.n;
+  hipLaunchKernelGGL(k_sum_rows, dim3(nval), dim3(NT), 0, s, (const double*)a.parts, a.nblk, 1.0 / vol,
+                     a.result);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const HArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad, dim3(a.nblk), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_stencil<float>(const KArgs<float>&, hipStream_t);
+template hipError_t launch_stencil<double>(const KArgs<double>&, hipStream_t);
+
+}  // namespace cellfft

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (relative, max-norm):
+  * operator K u:            FP64 1e-12, FP32 2e-5 (single rounding of
+                             ~50 terms per node)
+  * preconditioner:          FP64 1e-10, FP32 1e-4 (three FFT passes)
+  * effective stiffness C*:  FP64 1e-10 (solver tol 1e-10 on the relative
+                             residual; the energy form is second order in
+                             the solution error), mixed 1e-6 (tol 1e-7)
+  * gradient dC*/dE:         FP64 1e-8 (first order in the solution error)
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, matfree
+from paper_2004_05197_amd import microstructures as ms
+from closed_forms import backus
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rand_material(shape, seed, Emin=1.0, Emax=10.0):
+    rng = np.random.default_rng(seed)
+    nshape = tuple(reversed(shape))
+    return rng.uniform(Emin, Emax, nshape), rng.uniform(0.05, 0.45, nshape)
+
+
+OP_SHAPES = [(8, 6, 4), (16, 12, 8), (12, 8, 6), (32, 32, 16), (8, 6), (32, 32), (48, 12)]
+
+
+@pytest.mark.parametrize("shape", OP_SHAPES)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+def test_operator_parity(lib, shape, prec, tol):
+    E, nu = rand_material(shape, 1)
+    grid = fem.Grid(shape, lengths=[1.0 + 0.25 * a for a in range(len(shape))])
+    lam, mu = fem.lame(E, nu)
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((grid.d,) + grid.nshape)
+    ref = matfree.apply_K(grid, lam, mu, u).ravel()
+    with lib.Cell(shape, precision=prec, lengths=grid.L) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        q = c.apply_operator(u.ravel(), precision=prec)
+    assert relerr(q, ref) < tol
+
+
+@pytest.mark.parametrize("shape", [(8, 6, 4), (16, 12, 8), (24, 16, 12), (8, 6), (32, 32), (12, 48)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-4)])
+def test_preconditioner_parity(lib, shape, prec, tol):
+    E, nu = rand_material(shape, 3, 1.0, 50.0)
+    grid = fem.Grid(shape, lengths=[1.0 + 0.2 * a for a in range(len(shape))])
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal((grid.d,) + grid.nshape)
+    r -= r.reshape(grid.d, -1).mean(axis=1).reshape((grid.d,) + (1,) * grid.d)
+    with lib.Cell(shape, precision=prec, lengths=grid.L) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        lam0, mu0 = c.reference_medium()
+        z = c.apply_preconditioner(r.ravel(), precision=prec)
+    assert (lam0, mu0) == pytest.approx(matfree.reference_medium(E, nu, grid.d), rel=1e-14)
+    zref = matfree.FourierPreconditioner(grid, lam0, mu0)(r).ravel()
+    assert relerr(z, zref) < tol
+
+
+def oracle_C(shape, E, nu, lengths=None):
+    grid = fem.Grid(shape, lengths)
+    C, Cs, u = fem.effective_stiffness(grid, E, nu)
+    return grid, C, Cs, u
+
+
+def _check_C(lib, shape, E, nu, prec, tol_solve, tol_C, lengths=None):
+    grid, Cref, Csref, uref = oracle_C(shape, E, nu, lengths)
+    with lib.Cell(shape, precision=prec, tol=tol_solve, lengths=lengths) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+        u0 = c.displacement(0)
+    assert info["status"] == "CELL_OK", info
+    assert relerr(C, Cref) < tol_C, (C, Cref, info)
+    assert max(info["relres"]) <= tol_solve * 1.0000001
+    return C, info, grid, uref, u0
+
+
+def test_circle2d_fp64(lib):
+    E, nu = ms.circle2d(32)
+    C, info, grid, uref, u0 = _check_C(lib, (32, 32), E, nu, 0, 1e-10, 1e-10)
+    # x<->y symmetric input: C1111 = C2222
+    assert abs(C[0, 0] - C[1, 1]) < 1e-10 * C[0, 0]
+    assert info["sym_gap"] < 1e-9
+
+
+def test_circle2d_mean_stress(lib):
+    E, nu = ms.circle2d(32)
+    grid = fem.Grid((32, 32))
+    eb = np.array([[1e-2, 0.0, 0.0]])
+    u = fem.solve_direct(grid, E, nu, eb)
+    ref = fem.homogenize(grid, E, nu, u, eb)["mean_stress"][0]
+    with lib.Cell((32, 32), precision=0, tol=1e-10) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        s, info = c.solve(eb)
+        ug = c.displacement(0)
+    assert relerr(s[0], ref) < 1e-9
+    assert relerr(ug.ravel(), u[0]) < 1e-8
+
+
+def test_spheres16_fp64_and_mixed(lib):
+    mask, vf, _ = ms.rsa_spheres(16, 0.3, seed=2, rmin=1.0, rmax=2.0)
+    E = np.where(mask, 100.0, 1.0)
+    nu = np.full_like(E, 0.3)
+    _check_C(lib, (16, 16, 16), E, nu, 0, 1e-10, 1e-10)
+    _check_C(lib, (16, 16, 16), E, nu, 1, 1e-7, 1e-6)
+
+
+def test_noncubic_lengths(lib):
+    shape = (12, 8, 6)
+    E, nu = rand_material(shape, 7, 1.0, 30.0)
+    C, info, grid, uref, u0 = _check_C(lib, shape, E, nu, 0, 1e-10, 1e-10, lengths=(1.0, 1.4, 0.8))
+    assert relerr(u0.ravel(), uref[0]) < 1e-7
+
+
+def test_mixed_2d(lib):
+    E, nu = ms.circle2d(32)
+    _check_C(lib, (32, 32), E, nu, 1, 1e-7, 1e-6)
+
+
+def test_homogeneous_zero_iterations(lib):
+    shape = (8, 8, 8)
+    E = np.full(tuple(reversed(shape)), 4.0)
+    nu = np.full_like(E, 0.3)
+    with lib.Cell(shape, precision=0) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+    lam, mu = fem.lame(4.0, 0.3)
+    assert relerr(C, fem.D_voigt(lam, mu, 3)) < 1e-13
+    assert max(info["iters"]) == 0
+
+
+def test_laminate_closed_form(lib):
+    shape = (8, 12, 16)
+    Es, nus, th = [1.0, 20.0, 5.0], [0.3, 0.2, 0.4], [5, 7, 4]
+    E, nu = ms.laminate(shape, 2, Es, nus, th)
+    with lib.Cell(shape, precision=0, tol=1e-12) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+    lam, mu = fem.lame(np.array(Es), np.array(nus))
+    Cb = backus(lam, mu, np.array(th) / 16.0, 3, 2)
+    assert relerr(C, Cb) < 1e-11
+
+
+def test_adjoint_matches_oracle(lib):
+    shape = (8, 6, 4)
+    E, nu = rand_material(shape, 9, 1.0, 20.0)
+    grid, Cref, _, uref = oracle_C(shape, E, nu)
+    G = fem.dC_dE(grid, E, nu, uref, fem.unit_loads(3))
+    a = np.zeros((6, 6))
+    a[0, 0] = 1.0
+    a[3, 3] = 1.0
+    a[1, 2] = 0.5
+    ref = np.einsum("ij,ijv->v", a, G)
+    with lib.Cell(shape, precision=0, tol=1e-12) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        c.effective_stiffness()
+        g = c.adjoint(a)
+    assert relerr(g, ref) < 1e-8
+
+
+def test_deterministic(lib):
+    shape = (16, 16, 16)
+    E, nu = rand_material(shape, 11, 1.0, 100.0)
+    out = []
+    for _ in range(2):
+        with lib.Cell(shape, precision=1, tol=1e-6) as c:
+            c.set_material(E.ravel(), nu.ravel())
+            C, info = c.effective_stiffness()
+            out.append((C.copy(), info["iters"]))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+def test_error_paths(lib):
+    with pytest.raises(lib.CellError) as ei:
+        lib.Cell((10, 8, 8))
+    assert ei.value.status == lib.CELL_E_UNSUPPORTED
+    with lib.Cell((8, 8, 8)) as c:
+        with pytest.raises(lib.CellError) as ei:
+            c.adjoint(np.eye(6))
+        assert ei.value.status == lib.CELL_E_STATE
+        with pytest.raises(lib.CellError) as ei:
+            c.effective_stiffness()
+        assert ei.value.status == lib.CELL_E_STATE
+        E = np.ones(512)
+        nu = np.full(512, 0.3)
+        E[5] = np.nan
+        with pytest.raises(lib.CellError) as ei:
+            c.set_material(E, nu)
+        assert ei.value.status == lib.CELL_E_NONFINITE
+        E[5] = 1.0
+        nu[7] = 0.5
+        with pytest.raises(lib.CellError) as ei:
+            c.set_material(E, nu)
+        assert ei.value.status == lib.CELL_E_ARG
+    E, nu = rand_material((8, 8, 8), 12, 1.0, 1000.0)
+    with lib.Cell((8, 8, 8), max_iter=2) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+    assert info["status"] == "CELL_NOT_CONVERGED"

@@ -25,6 +25,7 @@ import pytest
 
 from oracle import fem, matfree
 from paper_2004_05197_amd import microstructures as ms
+from closed_forms import backus
 
 
 def rand_material(grid, seed, Emin=1.0, Emax=10.0):
@@ -128,29 +129,6 @@ def test_homogeneous_exact(shape):
 # --------------------------------------------------------------------------
 # laminates (Backus averaging is exact for P1 here)
 # --------------------------------------------------------------------------
-
-def backus(lam, mu, w, d, normal):
-    """Exact effective Voigt stiffness of a laminate with layer weights w."""
-    avg = lambda x: float(np.sum(w * x))
-    M = lam + 2 * mu
-    inv1M = 1.0 / avg(1.0 / M)
-    lM = avg(lam / M)
-    C = np.zeros((3, 3) if d == 2 else (6, 6))
-    pairs = fem.voigt_pairs(d)
-    idx = {p: k for k, p in enumerate(pairs)}
-    idx.update({(b, a): k for (a, b), k in list(idx.items())})
-    tang = [a for a in range(d) if a != normal]
-    C[normal, normal] = inv1M
-    for t in tang:
-        C[t, normal] = C[normal, t] = lM * inv1M
-        C[t, t] = avg(4 * mu * (lam + mu) / M) + lM ** 2 * inv1M
-        C[idx[(t, normal)], idx[(t, normal)]] = 1.0 / avg(1.0 / mu)
-    if d == 3:
-        t1, t2 = tang
-        C[t1, t2] = C[t2, t1] = avg(2 * mu * lam / M) + lM ** 2 * inv1M
-        C[idx[(t1, t2)], idx[(t1, t2)]] = avg(mu)
-    return C
-
 
 @pytest.mark.parametrize("d,shape", [(2, (6, 5)), (3, (4, 5, 6))])
 def test_laminates_exact(d, shape):
