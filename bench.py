@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark: DOF-CG-iterations/s of the effective-stiffness solve at 256^3.
+
+Workload (synthetic): 3D 256^3 voxels, two-phase microstructure from a
+seeded Gaussian random field (correlation length 8 voxels, seed 3)
+thresholded at 0, E 1 : 1000, nu 0.25 / 0.35, all 6 unit macro strains
+solved together, mixed precision (FP32 stencil/FFT/vector updates, FP64
+reductions and reliable-update residuals), tol 1e-6 on ||r||/||f||.
+
+One step = one cell_effective_stiffness call (load vectors, PCG for the 6
+loads, FP64 residual refreshes, homogenisation).  value = sum over steps and
+loads of 3 n iterations / wall time.  The inputs are resident on the GPU
+before timing starts.
+
+Besides the headline line it reports (same JSON object):
+  * roofline: the kernel with the largest share of GPU time, its algorithmic
+    bytes per launch (the byte model of the design notes) divided by its
+    average launch time (HIP events on the library's stream, timed region);
+  * fp64: the same solve in FP64 to tol 1e-6 (time to solution, speed-up of
+    mixed over FP64) and the normwise C* error of both against an FP64
+    solve at tol 1e-10;
+  * cpu_baseline: the CPU oracle (numpy/scipy FP64) timed on this host on a
+    bounded sample: 3 PCG iterations on one load of a 128^3 periodic
+    sub-block of the same field.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def byte_model(kind, n, prec_bytes):
+    """Algorithmic HBM bytes per load per launch of each kernel kind (3D).
+
+    A real field is 3 n values, its packed half spectrum the same size.
+    """
+    f = 3 * n * prec_bytes
+    return {
+        "k_apply": 2 * f,      # read p, write q (+ material once per launch)
+        "x_fwd": 4 * f,        # read r, q; write r, spectrum
+        "y_fwd": 2 * f,        # read/write spectrum
+        "last": 2 * f,         # read/write spectrum
+        "y_inv": 2 * f,
+        "x_inv": 5 * f,        # read spectrum, p, x; write x, p
+    }[kind]
+
+
+def cpu_baseline(E, nu, sub=128, iters=3):
+    from oracle import fem, matfree
+    Es = np.ascontiguousarray(E[:sub, :sub, :sub])
+    nus = np.ascontiguousarray(nu[:sub, :sub, :sub])
+    g = fem.Grid((sub, sub, sub))
+    pre = matfree.FourierPreconditioner(g, *matfree.reference_medium(Es, nus, 3))
+    t0 = time.perf_counter()
+    matfree.pcg(g, Es, nus, np.eye(6)[0], tol=1e-30, maxit=iters, precond=pre)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": 3 * g.n * iters / dt,
+        "unit": "DOF-CG-iterations/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{iters} PCG iterations (FP64 numpy matrix-free K-apply, single thread; "
+                  f"scipy.fft preconditioner on {cores} workers) on load eps_11 of a {sub}^3 "
+                  f"periodic sub-block of the {E.shape[0]}^3 field, preconditioner setup excluded, "
+                  f"{dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the cell solve is not sharded "
+              "across GPUs); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2004_05197_amd import binding as B
+    from paper_2004_05197_amd import microstructures as ms
+
+    torch.cuda.set_device(0)
+    n1 = args.n
+    n = n1 ** 3
+    E, nu = ms.two_phase_grf(n1, seed=3)
+    Ed = torch.from_numpy(E.ravel()).cuda()
+    nud = torch.from_numpy(nu.ravel()).cuda()
+    torch.cuda.synchronize()
+
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    # ---------------------------------------------------------------- mixed
+    cell = B.Cell((n1, n1, n1), precision=B.MIXED, tol=1e-6)
+    cell.set_material(Ed, nud)
+    for i in range(args.warmup):
+        C_mixed, info = cell.effective_stiffness()
+        progress(f"warmup {i}: iters {info['iters']} {info['seconds']:.2f} s")
+    cell.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters_total = 0
+    per_step = []
+    for i in range(args.steps):
+        C_mixed, info = cell.effective_stiffness()
+        iters_total += sum(info["iters"])
+        per_step.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = cell.profile_read()
+    cell.profile(False)
+    dt = t1 - t0
+    progress(f"timed {args.steps} steps in {dt:.3f} s, iters {per_step[-1]['iters']}, "
+             f"refinements {per_step[-1]['refinements']}")
+    dof_iter = 3 * n * iters_total
+    value = dof_iter / dt
+    mixed_tts = dt / args.steps
+    cell.close()
+    del cell
+
+    # roofline of the dominant kernel (largest GPU time in the timed region)
+    kinds = ["k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv"]
+    dom = max(kinds, key=lambda k: prof[k][0])
+    ms_tot, launches = prof[dom]
+    load_launches = iters_total + (0 if dom == "k_apply" else 6 * args.steps)
+    alg_bytes = load_launches * byte_model(dom, n, 4)
+    if dom == "k_apply":
+        alg_bytes += launches * 8 * n
+    achieved = alg_bytes / (ms_tot * 1e-3) / 1e9
+    gpu_ms = sum(prof[k][0] for k in prof)
+    roofline = {
+        "bound": "hbm",
+        "kernel": dom,
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(ms_tot / launches, 4),
+        "launches": launches,
+        "bytes_per_launch": round(alg_bytes / launches),
+    }
+    # whole-iteration byte model: all six kernels
+    all_bytes = sum((iters_total + (0 if k == "k_apply" else 6 * args.steps)) * byte_model(k, n, 4)
+                    for k in kinds) + prof["k_apply"][1] * 8 * n
+    loop_ms = sum(prof[k][0] for k in kinds)
+    kernel_ms = {k: round(v[0], 2) for k, v in prof.items()}
+
+    # ---------------------------------------------------------------- fp64
+    fp64 = None
+    if not args.no_fp64:
+        with B.Cell((n1, n1, n1), precision=B.FP64, tol=1e-10) as c64:
+            c64.set_material(Ed, nud)
+            C_ref, info_ref = c64.effective_stiffness()
+            progress(f"fp64 tol 1e-10: iters {info_ref['iters']} {info_ref['seconds']:.2f} s")
+        with B.Cell((n1, n1, n1), precision=B.FP64, tol=1e-6) as c64:
+            c64.set_material(Ed, nud)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            C_64, info_64 = c64.effective_stiffness()
+            torch.cuda.synchronize()
+            fp64_tts = time.perf_counter() - t2
+            progress(f"fp64 tol 1e-6: iters {info_64['iters']} {fp64_tts:.2f} s")
+        err = lambda C: float(np.abs(C - C_ref).max() / np.abs(C_ref).max())
+        fp64 = {
+            "time_to_solution_s": round(fp64_tts, 4),
+            "iters": info_64["iters"],
+            "dof_cg_iter_per_s": 3 * n * sum(info_64["iters"]) / fp64_tts,
+            "mixed_time_to_solution_s": round(mixed_tts, 4),
+            "speedup_mixed_over_fp64": round(fp64_tts / mixed_tts, 3),
+            "C_err_mixed_vs_fp64_tol1e-10": err(C_mixed),
+            "C_err_fp64_tol1e-6_vs_fp64_tol1e-10": err(C_64),
+        }
+
+    cpu = None
+    if not args.no_cpu:
+        progress("cpu oracle baseline ...")
+        cpu = cpu_baseline(E, nu)
+
+    out = {
+        "metric": "DOF-CG-iterations/sec at 256^3 (mixed vs FP64, rel err <=1e-6); % HBM roofline",
+        "value": value,
+        "unit": "DOF-CG-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"grf3d_{n1}: {n1}^3 voxels, thresholded Gaussian random field (ell 8, seed 3), "
+                        "E 1:1000, nu 0.25/0.35, 6 unit loads batched, mixed precision (FP32 bulk, "
+                        "FP64 reductions and residual refreshes), tol 1e-6",
+            "voxels": n,
+            "loads": 6,
+            "iters_per_step": per_step[-1]["iters"],
+            "refinements_per_step": per_step[-1]["refinements"],
+        },
+        "roofline": roofline,
+        "iteration_byte_model_frac": round(all_bytes / (loop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernel_ms": kernel_ms,
+        "gpu_busy_frac": round(gpu_ms * 1e-3 / dt, 4),
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

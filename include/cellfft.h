@@ -133,6 +133,30 @@ cell_status cell_apply_preconditioner(cell_t c, int precision, const double* r, 
 /* Reference medium (lambda_0, mu_0) used by the preconditioner. */
 cell_status cell_reference_medium(cell_t c, double* lam0, double* mu0);
 
+/* ---- per-kernel timing --------------------------------------------------- */
+
+/* Kernel kinds timed by cell_profile (HIP events on the handle's stream
+ * around every launch). */
+enum {
+  CELL_K_APPLY = 0,     /* q = K p (fused stencil) */
+  CELL_K_XFWD = 1,      /* r -= alpha q, FFT along x */
+  CELL_K_YFWD = 2,      /* FFT along y (3D) */
+  CELL_K_LAST = 3,      /* FFT, K_ref^{-1}, inverse FFT along the last axis */
+  CELL_K_YINV = 4,      /* inverse FFT along y (3D) */
+  CELL_K_XINV = 5,      /* inverse FFT along x, x and p updates */
+  CELL_K_RESIDUAL = 6,  /* FP64 residual f - K u */
+  CELL_K_MERGE = 7,     /* FP64 solution += FP32 correction */
+  CELL_K_HOMOG = 8,     /* effective stiffness / mean stress */
+  CELL_NKERNEL = 9
+};
+
+/* enable = 1: time every launch from now on (counters reset); 0: stop. */
+cell_status cell_profile(cell_t c, int enable);
+
+/* Accumulated milliseconds and launch counts per kernel kind
+ * (CELL_NKERNEL entries each, host). */
+cell_status cell_profile_read(cell_t c, double* ms_out, long long* launches_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,7 +73,11 @@ _SIGS = {
     "cell_apply_operator": (ct.c_int, [_P, ct.c_int, _P, _P]),
     "cell_apply_preconditioner": (ct.c_int, [_P, ct.c_int, _P, _P]),
     "cell_reference_medium": (ct.c_int, [_P, _D, _D]),
+    "cell_profile": (ct.c_int, [_P, ct.c_int]),
+    "cell_profile_read": (ct.c_int, [_P, _P, _P]),
 }
+
+KERNEL_KINDS = ["k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv", "residual", "merge", "homog"]
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
@@ -212,6 +216,15 @@ class Cell:
         _check(_lib.cell_apply_preconditioner(self._h, int(p), r.ctypes.data_as(ct.c_void_p),
                                               z.ctypes.data_as(ct.c_void_p)))
         return z
+
+    def profile(self, enable=True):
+        _check(_lib.cell_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        ms = np.zeros(len(KERNEL_KINDS))
+        cnt = np.zeros(len(KERNEL_KINDS), dtype=np.int64)
+        _check(_lib.cell_profile_read(self._h, ms.ctypes.data_as(ct.c_void_p), cnt.ctypes.data_as(ct.c_void_p)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     def reference_medium(self):
         lam = ct.c_double()

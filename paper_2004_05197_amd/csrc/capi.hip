@@ -133,11 +133,52 @@ struct cell_s {
   double eps_v[6][6] = {};
   bool solved = false;
   bool solved_unit = false;
+  // per-kernel HIP-event timing (cell_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
+  int ev_used = 0;
+  double prof_ms[CELL_NKERNEL] = {};
+  long long prof_cnt[CELL_NKERNEL] = {};
 };
 
 namespace {
 
 RedBuf red_of(cell_s* c) { return RedBuf{c->parts, c->cnt, c->maxblk, c->max_loads}; }
+
+constexpr int PROF_PAIRS = 256;
+
+// Sum the elapsed times of the recorded event pairs (all complete: called
+// after a stream synchronisation) and recycle the pool.
+cell_status prof_collect(cell_s* c) {
+  for (int i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    c->prof_ms[c->ev_kind[i]] += ms;
+    c->prof_cnt[c->ev_kind[i]] += 1;
+  }
+  c->ev_used = 0;
+  return CELL_OK;
+}
+
+// Brackets one kernel launch with an event pair on the handle's stream.
+struct ProfScope {
+  cell_s* c;
+  int slot = -1;
+  ProfScope(cell_s* c_, int kind) : c(c_) {
+    if (!c->prof) return;
+    if (c->ev_used == PROF_PAIRS) {
+      (void)hipStreamSynchronize(c->stream);
+      (void)prof_collect(c);
+    }
+    slot = c->ev_used++;
+    c->ev_kind[slot] = kind;
+    (void)hipEventRecord(c->ev[2 * slot], c->stream);
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+  }
+};
 
 template <typename T> Fields<T>& fields(cell_s* c);
 template <> Fields<float>& fields<float>(cell_s* c) { return c->f32; }
@@ -236,6 +277,7 @@ cell_status iteration(cell_s* c, int nload, bool kapply) {
   hipStream_t s = c->stream;
   if (kapply) {
     KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c), nload);
+    ProfScope ps(c, CELL_K_APPLY);
     HIPCHK(launch_stencil<T>(ka, s));
   }
   XArgs<T> xa{};
@@ -249,7 +291,12 @@ cell_status iteration(cell_s* c, int nload, bool kapply) {
   xa.tw = F.tw[0];
   xa.st = c->st;
   xa.red = red_of(c);
-  HIPCHK(launch_xfwd<T>(xa, c->g.nx, nload, s));
+  {
+    ProfScope ps(c, CELL_K_XFWD);
+    HIPCHK(launch_xfwd<T>(xa, c->g.nx, nload, s));
+  }
+  HIPCHK(launch_finalize(xa.red, c->st, c->res2, RED_RR, xpass_blocks(c->g.nx, xa.nrows, sizeof(T) == 8), nload,
+                         -1, s));
   YArgs<T> ya{};
   ya.S = F.S;
   ya.lstrideC = c->lstride / 2;
@@ -274,10 +321,24 @@ cell_status iteration(cell_s* c, int nload, bool kapply) {
   pa.inv_n = (T)(1.0 / (double)c->n);
   pa.st = c->st;
   pa.red = red_of(c);
-  if (c->d == 3) HIPCHK(launch_ypass<T>(ya, false, nload, s));
-  HIPCHK(launch_last<T>(pa, c->d, nload, s));
-  if (c->d == 3) HIPCHK(launch_ypass<T>(ya, true, nload, s));
-  HIPCHK(launch_xinv<T>(xa, c->g.nx, nload, s));
+  if (c->d == 3) {
+    ProfScope ps(c, CELL_K_YFWD);
+    HIPCHK(launch_ypass<T>(ya, false, nload, s));
+  }
+  {
+    ProfScope ps(c, CELL_K_LAST);
+    HIPCHK(launch_last<T>(pa, c->d, nload, s));
+  }
+  HIPCHK(launch_finalize(pa.red, c->st, c->res2, RED_RZ, last_pass_blocks(c->d, c->g.nx, c->g.ny, sizeof(T) == 8),
+                         nload, -1, s));
+  if (c->d == 3) {
+    ProfScope ps(c, CELL_K_YINV);
+    HIPCHK(launch_ypass<T>(ya, true, nload, s));
+  }
+  {
+    ProfScope ps(c, CELL_K_XINV);
+    HIPCHK(launch_xinv<T>(xa, c->g.nx, nload, s));
+  }
   return CELL_OK;
 }
 
@@ -287,11 +348,14 @@ cell_status residual(cell_s* c, int nload, int load, const double* u) {
   Fields<T>& F = fields<T>(c);
   KArgs<double> ka = kargs<double>(c, 1, u, nullptr, c->mat64, nload);
   ka.only_load = load;
-  if (sizeof(T) == 4) {
-    HIPCHK(launch_residual_mixed(ka, reinterpret_cast<float*>(F.r), c->stream));
-  } else {
-    ka.out = F.r;
-    HIPCHK(launch_stencil<double>(ka, c->stream));
+  {
+    ProfScope ps(c, CELL_K_RESIDUAL);
+    if (sizeof(T) == 4) {
+      HIPCHK(launch_residual_mixed(ka, reinterpret_cast<float*>(F.r), c->stream));
+    } else {
+      ka.out = F.r;
+      HIPCHK(launch_stencil<double>(ka, c->stream));
+    }
   }
   HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * c->max_loads, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -346,6 +410,7 @@ cell_status run_solve(cell_s* c, int nload, cell_info* info) {
     for (int i = 0; i < CHUNK; ++i) STCHK(iteration<T>(c, nload, true));
     HIPCHK(hipMemcpyAsync(c->st_h, c->st, sizeof(LoadState) * c->max_loads, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (c->prof) STCHK(prof_collect(c));
     done = true;
     for (int l = 0; l < nload; ++l) {
       if (fin[l]) continue;
@@ -355,13 +420,19 @@ cell_status run_solve(cell_s* c, int nload, cell_info* info) {
         result = fail(CELL_E_BREAKDOWN, "CG breakdown in load " + std::to_string(l));
         continue;
       }
-      const bool ru = S.state == ST_DONE || (mixed && S.state == ST_ACTIVE && S.rr < DELTA * DELTA * rr_ru[l]);
+      // CONVERGED: the converging iteration has completed (its operator
+      // finalisation, which marks DONE, has not run yet)
+      const bool finished = S.state == ST_DONE || S.state == ST_CONVERGED;
+      const bool ru = finished || (mixed && S.state == ST_ACTIVE && S.rr < DELTA * DELTA * rr_ru[l]);
       if (ru) {
         const double* u64;
         if (mixed) {
           const long long off = (long long)l * c->lstride;
-          hipLaunchKernelGGL(k_merge, dim3(1024), dim3(256), 0, s, c->x64 + off,
-                             reinterpret_cast<float*>(F.x) + off, c->lstride);
+          {
+            ProfScope ps(c, CELL_K_MERGE);
+            hipLaunchKernelGGL(k_merge, dim3(1024), dim3(256), 0, s, c->x64 + off,
+                               reinterpret_cast<float*>(F.x) + off, c->lstride);
+          }
           HIPCHK(hipGetLastError());
           u64 = c->x64;
         } else {
@@ -376,7 +447,7 @@ cell_status run_solve(cell_s* c, int nload, cell_info* info) {
           result = fail(CELL_E_BREAKDOWN, "non-finite residual in load " + std::to_string(l));
           continue;
         }
-        if (rt <= S.thr || (S.state == ST_DONE && S.maxit_hit) || S.iters >= c->max_iter) {
+        if (rt <= S.thr || (finished && S.maxit_hit) || S.iters >= c->max_iter) {
           fin[l] = 1;
           S.rr = rt;
           S.state = ST_DONE;
@@ -433,11 +504,15 @@ cell_status homogenize(cell_s* c, int nload, std::vector<double>& out) {
   h.parts = c->hparts;
   h.result = c->hres;
   h.nblk = c->hblk;
-  HIPCHK(launch_homog(h, c->stream));
+  {
+    ProfScope ps(c, CELL_K_HOMOG);
+    HIPCHK(launch_homog(h, c->stream));
+  }
   const int nval = nload * nload + nload * c->nv;
   out.resize(nval);
   HIPCHK(hipMemcpyAsync(out.data(), c->hres, sizeof(double) * nval, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->prof) STCHK(prof_collect(c));
   return CELL_OK;
 }
 
@@ -493,6 +568,7 @@ void cell_destroy(cell_t c) {
   fr(c->hres);
   fr(c->grad);
   fr(c->scratch);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->st_h) (void)hipHostFree(c->st_h);
   if (c->res2_h) (void)hipHostFree(c->res2_h);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -764,6 +840,36 @@ cell_status cell_get_displacement(cell_t c, int load, double* u_out, int on_devi
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(tmp);
   if (e != hipSuccess) return fail(CELL_E_DEVICE, hipGetErrorString(e));
+  return CELL_OK;
+}
+
+cell_status cell_profile(cell_t c, int enable) {
+  if (!c) return fail(CELL_E_ARG, "null argument");
+  DevGuard dg(c->dev);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * PROF_PAIRS);
+    c->ev_kind.resize(PROF_PAIRS);
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+  }
+  if (c->prof) STCHK(prof_collect(c));
+  c->prof = enable != 0;
+  for (int k = 0; k < CELL_NKERNEL; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_cnt[k] = 0;
+  }
+  return CELL_OK;
+}
+
+cell_status cell_profile_read(cell_t c, double* ms_out, long long* launches_out) {
+  if (!c || !ms_out || !launches_out) return fail(CELL_E_ARG, "null argument");
+  DevGuard dg(c->dev);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->prof) STCHK(prof_collect(c));
+  for (int k = 0; k < CELL_NKERNEL; ++k) {
+    ms_out[k] = c->prof_ms[k];
+    launches_out[k] = c->prof_cnt[k];
+  }
   return CELL_OK;
 }
 

@@ -104,29 +104,9 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
     const int row = row0 + rr;
     if (row < a.nrows) S[(long long)row * M + m] = buf[rr * RS + m];
   }
-  // ||r||^2 partials and finalisation by the last block of this load
+  // ||r||^2 partial of this block (finalised by k_finalize)
   const double bs = block_sum<NT>(acc, sh);
-  __shared__ bool last;
-  if (tid == 0) {
-    a.red.slot_parts(RED_RR, l)[blockIdx.x] = bs;
-    last = arrive_last(a.red.slot_cnt(RED_RR, l), gridDim.x);
-  }
-  __syncthreads();
-  if (last) {
-    const double rr = sum_partials<NT>(a.red.slot_parts(RED_RR, l), gridDim.x, sh);
-    if (tid == 0) {
-      *a.red.slot_cnt(RED_RR, l) = 0u;
-      st->rr = rr;
-      if (!(rr == rr) || rr > 1e300) {
-        st->state = ST_BREAKDOWN;
-      } else if (rr <= st->thr) {
-        st->state = ST_CONVERGED;
-      } else if (st->iters >= st->maxit) {
-        st->state = ST_CONVERGED;
-        st->maxit_hit = 1;
-      }
-    }
-  }
+  if (tid == 0) a.red.slot_parts(RED_RR, l)[blockIdx.x] = bs;
 }
 
 // ================================================================= x inverse
@@ -187,14 +167,6 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
       pn.y = z.im + beta * po.y;
       p2[off] = pn;
     }
-  }
-  __shared__ bool last;
-  __syncthreads();
-  if (tid == 0) last = arrive_last(a.red.slot_cnt(RED_XINV, l), gridDim.x);
-  __syncthreads();
-  if (last && tid == 0) {
-    *a.red.slot_cnt(RED_XINV, l) = 0u;
-    if (st->state == ST_CONVERGED) st->state = ST_DONE;
   }
 }
 
@@ -344,18 +316,6 @@ __device__ __forceinline__ T redot(const cpx<T>* r, const cpx<T>* z) {
   return s;
 }
 
-// finalisation of r.z (shared by the 3D and 2D last passes)
-__device__ __forceinline__ void finalize_rz(LoadState* st, double rz) {
-  const bool conv = st->state == ST_CONVERGED;
-  if (!(rz == rz) || (!(rz > 0.0) && !conv)) {
-    st->state = ST_BREAKDOWN;
-    return;
-  }
-  st->beta = (st->first || !(st->rz > 0.0)) ? 0.0 : rz / st->rz;
-  st->rz = rz;
-  st->first = 0;
-}
-
 // ===================================================== z pass (3D, last)
 template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
@@ -365,8 +325,7 @@ __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
   __shared__ cpx<T> tws[N];
   __shared__ double sh[NT / WAVE];
   const int l = blockIdx.y;
-  LoadState* st = a.st + l;
-  if (!load_live(st, true)) return;
+  if (!load_live(a.st + l, true)) return;
   const int M = a.nx / 2;
   const int ntile = (M + TX - 1) / TX;
   const int tile = blockIdx.x % ntile;
@@ -449,19 +408,7 @@ __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
     if (s0 + s < M) base[c * cstride + z * zstride + s] = buf[e];
   }
   const double bs = block_sum<NT>(acc, sh);
-  __shared__ bool last;
-  if (tid == 0) {
-    a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
-    last = arrive_last(a.red.slot_cnt(RED_RZ, l), gridDim.x);
-  }
-  __syncthreads();
-  if (last) {
-    const double rz = sum_partials<NT>(a.red.slot_parts(RED_RZ, l), gridDim.x, sh);
-    if (tid == 0) {
-      *a.red.slot_cnt(RED_RZ, l) = 0u;
-      finalize_rz(st, rz);
-    }
-  }
+  if (tid == 0) a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
 }
 
 // ===================================================== y pass (2D, last)
@@ -473,8 +420,7 @@ __global__ __launch_bounds__(NT) void k_ylast(PArgs<T> a) {
   __shared__ cpx<T> tws[N];
   __shared__ double sh[NT / WAVE];
   const int l = blockIdx.y;
-  LoadState* st = a.st + l;
-  if (!load_live(st, true)) return;
+  if (!load_live(a.st + l, true)) return;
   const int M = a.nx / 2;
   const int s0 = blockIdx.x * TX;
   const int tid = threadIdx.x;
@@ -546,19 +492,79 @@ __global__ __launch_bounds__(NT) void k_ylast(PArgs<T> a) {
     if (s0 + s < M) base[c * cstride + (long long)y * M + s] = buf[e];
   }
   const double bs = block_sum<NT>(acc, sh);
-  __shared__ bool last;
-  if (tid == 0) {
-    a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
-    last = arrive_last(a.red.slot_cnt(RED_RZ, l), gridDim.x);
+  if (tid == 0) a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
+}
+
+// ================================================================ finalize
+// One block per load: fixed-order sum of the per-block partials written by
+// the producing kernel, then the scalar update of that reduction.
+__global__ __launch_bounds__(NT) void k_finalize(RedBuf red, LoadState* st, double* res2, int slot,
+                                                 int nparts, int only_load) {
+  __shared__ double sh[NT / WAVE];
+  const int l = blockIdx.x;
+  LoadState* S = st + l;
+  bool live;
+  switch (slot) {
+    case RED_PQ: live = S->state == ST_ACTIVE || S->state == ST_CONVERGED; break;
+    case RED_RR: live = S->state == ST_ACTIVE; break;
+    case RED_RZ: live = S->state == ST_ACTIVE || S->state == ST_CONVERGED; break;
+    default: live = only_load < 0 || only_load == l; break;
   }
-  __syncthreads();
-  if (last) {
-    const double rz = sum_partials<NT>(a.red.slot_parts(RED_RZ, l), gridDim.x, sh);
-    if (tid == 0) {
-      *a.red.slot_cnt(RED_RZ, l) = 0u;
-      finalize_rz(st, rz);
+  if (!live) return;
+  if (slot == RED_PQ && S->state == ST_CONVERGED) {
+    // the iteration that converged has completed (preconditioning and
+    // updates ran); no operator was applied to this load in this one
+    if (threadIdx.x == 0) S->state = ST_DONE;
+    return;
+  }
+  const double* parts = red.slot_parts(slot, l);
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NT) v += parts[i];
+  const double s = block_sum<NT>(v, sh);
+  if (threadIdx.x != 0) return;
+  switch (slot) {
+    case RED_PQ:
+      S->pq = s;
+      S->iters += 1;
+      if (!(s > 0.0) || !(s < 1e300)) S->state = ST_BREAKDOWN;
+      else S->alpha = S->rz / s;
+      break;
+    case RED_RR:
+      S->rr = s;
+      if (!(s == s) || s > 1e300) S->state = ST_BREAKDOWN;
+      else if (s <= S->thr) S->state = ST_CONVERGED;
+      else if (S->iters >= S->maxit) {
+        S->state = ST_CONVERGED;
+        S->maxit_hit = 1;
+      }
+      break;
+    case RED_RZ: {
+      const bool conv = S->state == ST_CONVERGED;
+      if (!(s == s) || (!(s > 0.0) && !conv)) {
+        S->state = ST_BREAKDOWN;
+        break;
+      }
+      S->beta = (S->first || !(S->rz > 0.0)) ? 0.0 : s / S->rz;
+      S->rz = s;
+      S->first = 0;
+      break;
     }
+    default:
+      res2[l] = s;
+      break;
   }
+}
+
+hipError_t launch_finalize(const RedBuf& red, LoadState* st, double* res2, int slot, int nparts, int nload,
+                           int only_load, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(nload), dim3(NT), 0, s, red, st, res2, slot, nparts, only_load);
+  return hipGetLastError();
+}
+
+int last_pass_blocks(int dim, int nx, int ny, bool fp64) {
+  const int TX = fp64 ? z_tx<double>() : z_tx<float>();
+  const int ntile = (nx / 2 + TX - 1) / TX;
+  return dim == 3 ? ntile * ny : ntile;
 }
 
 // ================================================================ dispatch

@@ -111,6 +111,12 @@ hipError_t launch_residual_mixed(const KArgs<double>& a, float* out32, hipStream
 hipError_t launch_homog(const HArgs& a, hipStream_t s);
 hipError_t launch_grad(const HArgs& a, hipStream_t s);
 
+// fixed-order sum of per-block partials and the scalar update of `slot`
+// (one block per load)
+hipError_t launch_finalize(const RedBuf& red, LoadState* st, double* res2, int slot, int nparts, int nload,
+                           int only_load, hipStream_t s);
+int last_pass_blocks(int dim, int nx, int ny, bool fp64);
+
 // blocks used by each kernel (for sizing the partials buffer)
 int xpass_blocks(int nx, int nrows, bool fp64);
 int stencil_blocks(const Geom& g);

@@ -118,7 +118,6 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
   T* cb = pl + 6 * PP;
   const int VW = bx + 1, VV = VW * (by + 1);
   __shared__ double sh[NT / WAVE];
-  __shared__ bool last;
   const int tid = threadIdx.x;
   const int tx = tid % bx, ty = tid / bx;
   const bool worker = ty < by;
@@ -129,7 +128,6 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
   const T w = (T)(a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0);
   const int nextra = bx + by + 1;
   const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const int nblk = gridDim.x * gridDim.y * gridDim.z;
   for (int l = 0; l < a.nload; ++l) {
     bool live;
     if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
@@ -233,32 +231,7 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
       __syncthreads();
     }
     const double bs = block_sum<NT>(acc, sh);
-    // partial per load, one counter per launch
     if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
-  }
-  const int cslot = MODE == 0 ? RED_PQ : RED_RES;
-  if (tid == 0) last = arrive_last(a.red.slot_cnt(cslot, 0), nblk);
-  __syncthreads();
-  if (last) {
-    for (int l = 0; l < a.nload; ++l) {
-      bool live;
-      if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
-      else live = a.only_load < 0 || a.only_load == l;
-      if (!live) continue;
-      const double s = sum_partials<NT>(a.red.slot_parts(cslot, l), nblk, sh);
-      if (tid == 0) {
-        if (MODE == 0) {
-          LoadState* st = a.st + l;
-          st->pq = s;
-          st->iters += 1;
-          if (!(s > 0.0) || !(s < 1e300)) st->state = ST_BREAKDOWN;
-          else st->alpha = st->rz / s;
-        } else {
-          a.res2[l] = s;
-        }
-      }
-    }
-    if (tid == 0) *a.red.slot_cnt(cslot, 0) = 0u;
   }
 }
 
@@ -297,7 +270,6 @@ __device__ __forceinline__ void simplex2(const T (&u)[4][2], T lw, T mw, const T
 template <typename T, typename TO, int MODE>
 __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   __shared__ double sh[NT / WAVE];
-  __shared__ bool last;
   const int l = blockIdx.y;
   bool live;
   if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
@@ -358,26 +330,7 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   }
   const int cslot = MODE == 0 ? RED_PQ : RED_RES;
   const double bs = block_sum<NT>(acc, sh);
-  if (threadIdx.x == 0) {
-    a.red.slot_parts(cslot, l)[blockIdx.x] = bs;
-    last = arrive_last(a.red.slot_cnt(cslot, l), gridDim.x);
-  }
-  __syncthreads();
-  if (last) {
-    const double s = sum_partials<NT>(a.red.slot_parts(cslot, l), gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      *a.red.slot_cnt(cslot, l) = 0u;
-      if (MODE == 0) {
-        LoadState* st = a.st + l;
-        st->pq = s;
-        st->iters += 1;
-        if (!(s > 0.0) || !(s < 1e300)) st->state = ST_BREAKDOWN;
-        else st->alpha = st->rz / s;
-      } else {
-        a.res2[l] = s;
-      }
-    }
-  }
+  if (threadIdx.x == 0) a.red.slot_parts(cslot, l)[blockIdx.x] = bs;
 }
 
 // ============================================== homogenisation (FP64, once)
@@ -566,16 +519,21 @@ int stencil_blocks(const Geom& g) {
 template <typename T, typename TO, int MODE>
 static hipError_t launch_stencil_impl(const KArgs<T>& a, hipStream_t s) {
   const Geom& g = a.g;
+  int nparts;
   if (g.dim == 3) {
     const Tile3 t = pick_tile3(g, sizeof(T) == 8);
     dim3 grid(g.nx / t.bx, (g.ny + t.by - 1) / t.by, (g.nz + t.tz - 1) / t.tz);
+    nparts = grid.x * grid.y * grid.z;
     const size_t lds = stencil3_lds<T>(t);
     hipLaunchKernelGGL((k_stencil3<T, TO, MODE>), grid, dim3(NT), lds, s, a, t.bx, t.by, t.tz);
   } else {
     dim3 grid((unsigned)((g.n + NT - 1) / NT), a.nload);
+    nparts = grid.x;
     hipLaunchKernelGGL((k_stencil2<T, TO, MODE>), grid, dim3(NT), 0, s, a);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(a.red, a.st, a.res2, MODE == 0 ? RED_PQ : RED_RES, nparts, a.nload, a.only_load, s);
 }
 
 template <typename T>
