@@ -41,25 +41,32 @@ __host__ __device__ constexpr int sym_idx(int i, int j) {
 }
 
 // One simplex of the Kuhn split (compile-time permutation) for one voxel.
-// u[c][k]: corner c = ox + 2 oy + 4 oz, component k.  lw = lambda |s|,
-// mw = mu |s|, sb = |s| D eps_bar (tensor storage) if MACRO.
-template <typename T, int A0, int A1, int A2, bool MACRO>
-__device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw, const T* ih,
+// u[c][k]: corner c = ox + 2 oy + 4 oz, component k.
+// UNI (equal edge lengths h): G holds raw differences and lw = lambda |s| / h^2,
+//   mw = mu |s| / h^2, sb = |s| D eps_bar / h, so the corner forces come out
+//   without any per-axis scaling.
+// !UNI: G = differences / h_a, fluxes * 1/h_a, lw = lambda |s|, sb = |s| D eps_bar.
+template <typename T, int A0, int A1, int A2, bool MACRO, bool UNI>
+__device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw2, T mw, const T* ih,
                                          const T* sb, T (&f)[8][3]) {
   constexpr int c0 = 0, c1 = 1 << A0, c2 = c1 | (1 << A1), c3 = 7;
   T G[3][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    G[k][A0] = (u[c1][k] - u[c0][k]) * ih[A0];
-    G[k][A1] = (u[c2][k] - u[c1][k]) * ih[A1];
-    G[k][A2] = (u[c3][k] - u[c2][k]) * ih[A2];
+    G[k][A0] = u[c1][k] - u[c0][k];
+    G[k][A1] = u[c2][k] - u[c1][k];
+    G[k][A2] = u[c3][k] - u[c2][k];
+    if (!UNI) {
+      G[k][A0] *= ih[A0];
+      G[k][A1] *= ih[A1];
+      G[k][A2] *= ih[A2];
+    }
   }
-  const T tr = G[0][0] + G[1][1] + G[2][2];
-  const T lt = lw * tr;
+  const T lt = lw * (G[0][0] + G[1][1] + G[2][2]);
   T s[6];
-  s[0] = lt + T(2) * mw * G[0][0];
-  s[1] = lt + T(2) * mw * G[1][1];
-  s[2] = lt + T(2) * mw * G[2][2];
+  s[0] = lt + mw2 * G[0][0];
+  s[1] = lt + mw2 * G[1][1];
+  s[2] = lt + mw2 * G[2][2];
   s[3] = mw * (G[1][2] + G[2][1]);
   s[4] = mw * (G[0][2] + G[2][0]);
   s[5] = mw * (G[0][1] + G[1][0]);
@@ -69,9 +76,12 @@ __device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw, const T
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const T t1 = s[sym_idx(k, A0)] * ih[A0];
-    const T t2 = s[sym_idx(k, A1)] * ih[A1];
-    const T t3 = s[sym_idx(k, A2)] * ih[A2];
+    T t1 = s[sym_idx(k, A0)], t2 = s[sym_idx(k, A1)], t3 = s[sym_idx(k, A2)];
+    if (!UNI) {
+      t1 *= ih[A0];
+      t2 *= ih[A1];
+      t3 *= ih[A2];
+    }
     f[c0][k] -= t1;
     f[c1][k] += t1 - t2;
     f[c2][k] += t2 - t3;
@@ -79,38 +89,49 @@ __device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw, const T
   }
 }
 
-template <typename T, bool MACRO>
+template <typename T, bool MACRO, bool UNI>
 __device__ __forceinline__ void voxel3(const T (&u)[8][3], T lw, T mw, const T* ih, const T* sb,
                                        T (&f)[8][3]) {
 #pragma unroll
   for (int c = 0; c < 8; ++c)
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[c][k] = T(0);
-  simplex3<T, 0, 1, 2, MACRO>(u, lw, mw, ih, sb, f);
-  simplex3<T, 0, 2, 1, MACRO>(u, lw, mw, ih, sb, f);
-  simplex3<T, 1, 0, 2, MACRO>(u, lw, mw, ih, sb, f);
-  simplex3<T, 1, 2, 0, MACRO>(u, lw, mw, ih, sb, f);
-  simplex3<T, 2, 0, 1, MACRO>(u, lw, mw, ih, sb, f);
-  simplex3<T, 2, 1, 0, MACRO>(u, lw, mw, ih, sb, f);
+  const T mw2 = mw + mw;
+  simplex3<T, 0, 1, 2, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
+  simplex3<T, 0, 2, 1, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
+  simplex3<T, 1, 0, 2, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
+  simplex3<T, 1, 2, 0, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
+  simplex3<T, 2, 0, 1, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
+  simplex3<T, 2, 1, 0, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// macro stress |s| D eps_bar in tensor storage
+// macro stress D eps_bar (tensor storage) scaled by sc, with lw/mw already
+// holding the |s| (and 1/h^2) factors of the caller
 template <typename T>
-__device__ __forceinline__ void macro_stress(const double* e, T lw, T mw, T* sb) {
+__device__ __forceinline__ void macro_stress(const double* e, T lw, T mw, T sc, T* sb) {
   const T tr = (T)(e[0] + e[1] + e[2]);
-  sb[0] = lw * tr + T(2) * mw * (T)e[0];
-  sb[1] = lw * tr + T(2) * mw * (T)e[1];
-  sb[2] = lw * tr + T(2) * mw * (T)e[2];
-  sb[3] = T(2) * mw * (T)e[3];
-  sb[4] = T(2) * mw * (T)e[4];
-  sb[5] = T(2) * mw * (T)e[5];
+  sb[0] = sc * (lw * tr + T(2) * mw * (T)e[0]);
+  sb[1] = sc * (lw * tr + T(2) * mw * (T)e[1]);
+  sb[2] = sc * (lw * tr + T(2) * mw * (T)e[2]);
+  sb[3] = sc * (T(2) * mw * (T)e[3]);
+  sb[4] = sc * (T(2) * mw * (T)e[4]);
+  sb[5] = sc * (T(2) * mw * (T)e[5]);
 }
 
 // =========================================================== 3D stencil
-// T: arithmetic type of u and the material; TO: output type.
-template <typename T, typename TO, int MODE>
+// Block: bx x by node tile, marching tz node planes along z.  Per layer k
+// (voxels between node planes k and k+1) every thread computes voxel
+// (tx-1, ty-1) of the tile (the node's lower-left-back voxel) and keeps its
+// (1,1,*) corners; the (bx+by+1) halo voxels are spread over the first
+// threads.  The (0,0,*), (1,0,*), (0,1,*) corners go to LDS for the three
+// neighbouring nodes; the (.,.,1) corners are carried to the next plane.
+// Node plane k+2 and the material of layer k+1 are prefetched into
+// registers while layer k is computed.
+constexpr int PF_MAX = 8;  // ceil(3 (bx+2)(by+2) / 256) for every tile used
+
+template <typename T, typename TO, int MODE, bool UNI>
 __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int tz) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* pl = reinterpret_cast<T*>(smem_raw);
@@ -125,9 +146,28 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
   const long long n = a.g.n;
   const int x0 = blockIdx.x * bx, y0 = blockIdx.y * by, z0 = blockIdx.z * tz;
   const T ih[3] = {(T)(1.0 / a.g.h[0]), (T)(1.0 / a.g.h[1]), (T)(1.0 / a.g.h[2])};
-  const T w = (T)(a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0);
+  const double wd = a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0;
+  const T w = (T)(UNI ? wd / (a.g.h[0] * a.g.h[0]) : wd);
+  const T msc = (T)(UNI ? a.g.h[0] : 1.0);  // macro stress scale relative to lw, mw
   const int nextra = bx + by + 1;
+  const bool has_extra = tid < nextra;
+  // voxel handled as the extra of this thread (relative to the tile)
+  const int ex = tid < by ? bx - 1 : tid - by - 1;
+  const int ey = tid < by ? tid - 1 : by - 1;
   const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  // per prefetch slot: offset of this thread's plane element within a
+  // z-plane of the field (component c, wrapped x and y), -1 if unused
+  int poff[PF_MAX];
+#pragma unroll
+  for (int q = 0; q < PF_MAX; ++q) {
+    const int e = tid + q * NT;
+    poff[q] = -1;
+    if (e < 3 * PP) {
+      const int c = e / PP, rem = e - c * PP;
+      const int py = rem / PW, px = rem - py * PW;
+      poff[q] = c * (int)n + wrapi(y0 - 1 + py, ny) * nx + wrapi(x0 - 1 + px, nx);
+    }
+  }
   for (int l = 0; l < a.nload; ++l) {
     bool live;
     if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
@@ -135,23 +175,29 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
     if (!live) continue;
     const T* u = a.u ? a.u + l * a.lstride : nullptr;
     TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
-    T sbv[6];
     const double* eb = a.eps[l];
-    auto load_plane = [&](int zp, int slot) {
-      const int zw = wrapi(zp, nz);
-      T* dst = pl + slot * 3 * PP;
-      for (int e = tid; e < 3 * PP; e += NT) {
-        const int c = e / PP, rem = e - c * PP;
-        const int py = rem / PW, px = rem - py * PW;
-        const int gx = wrapi(x0 - 1 + px, nx), gy = wrapi(y0 - 1 + py, ny);
-        dst[e] = u ? u[c * n + ((long long)zw * ny + gy) * nx + gx] : T(0);
-      }
+    T pf[PF_MAX];
+    auto fetch_plane = [&](int zp) {
+      const int zoff = wrapi(zp, nz) * (ny * nx);
+#pragma unroll
+      for (int q = 0; q < PF_MAX; ++q)
+        if (poff[q] >= 0) pf[q] = u ? u[poff[q] + zoff] : T(0);
     };
-    // voxel (vx, vy) of layer k (lower corner node (x0+vx, y0+vy, k)):
-    // writes the exchanged corners to cb, returns the (1,1,oz) corner.
-    auto voxel = [&](int vx, int vy, int k, int L, T (&own)[2][3]) {
-      const T* p0 = pl + (L & 1) * 3 * PP;        // plane k
-      const T* p1 = pl + ((L + 1) & 1) * 3 * PP;  // plane k+1
+    auto store_plane = [&](int slot) {
+      T* dst = pl + slot * 3 * PP;
+#pragma unroll
+      for (int q = 0; q < PF_MAX; ++q)
+        if (poff[q] >= 0) dst[tid + q * NT] = pf[q];
+    };
+    auto mat_of = [&](int vx, int vy, int k, T& lw, T& mw) {
+      const long long vid = ((long long)wrapi(k, nz) * ny + wrapi(y0 + vy, ny)) * nx + wrapi(x0 + vx, nx);
+      lw = a.mat[2 * vid] * w;
+      mw = a.mat[2 * vid + 1] * w;
+    };
+    // computes voxel (vx, vy) of layer k from planes in slots s0 (k), s1 (k+1)
+    auto voxel = [&](int vx, int vy, int s0, int s1, T lw, T mw, T (&own)[2][3]) {
+      const T* p0 = pl + s0 * 3 * PP;
+      const T* p1 = pl + s1 * 3 * PP;
       T uu[8][3];
 #pragma unroll
       for (int oz = 0; oz < 2; ++oz)
@@ -161,16 +207,14 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
           for (int ox = 0; ox < 2; ++ox)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-              uu[ox + 2 * oy + 4 * oz][c] =
-                  (oz ? p1 : p0)[c * PP + (vy + 1 + oy) * PW + (vx + 1 + ox)];
-      const long long vid = ((long long)wrapi(k, nz) * ny + wrapi(y0 + vy, ny)) * nx + wrapi(x0 + vx, nx);
-      const T lw = a.mat[2 * vid] * w, mw = a.mat[2 * vid + 1] * w;
+              uu[ox + 2 * oy + 4 * oz][c] = (oz ? p1 : p0)[c * PP + (vy + 1 + oy) * PW + (vx + 1 + ox)];
       T f[8][3];
+      T sb[6];
       if (MODE == 1) {
-        macro_stress(eb, lw, mw, sbv);
-        voxel3<T, true>(uu, lw, mw, ih, sbv, f);
+        macro_stress(eb, lw, mw, msc, sb);
+        voxel3<T, true, UNI>(uu, lw, mw, ih, sb, f);
       } else {
-        voxel3<T, false>(uu, lw, mw, ih, sbv, f);
+        voxel3<T, false, UNI>(uu, lw, mw, ih, sb, f);
       }
       const int vi = (vy + 1) * VW + (vx + 1);
 #pragma unroll
@@ -185,17 +229,44 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
     };
     double acc = 0.0;
     T carry[3] = {T(0), T(0), T(0)};
-    load_plane(z0 - 1, 0);
+    fetch_plane(z0 - 1);
+    store_plane(0);
+    fetch_plane(z0);
+    store_plane(1);
+    T lw0 = T(0), mw0 = T(0), lwe = T(0), mwe = T(0);
+    if (worker) mat_of(tx - 1, ty - 1, z0 - 1, lw0, mw0);
+    if (has_extra) mat_of(ex, ey, z0 - 1, lwe, mwe);
+    __syncthreads();
     for (int L = 0; L <= tz; ++L) {
       const int k = z0 - 1 + L;
-      load_plane(k + 1, (L + 1) & 1);
-      __syncthreads();
-      T own[2][3];
-      if (worker) voxel(tx - 1, ty - 1, k, L, own);
-      for (int e = tid; e < nextra; e += NT) {
-        T dummy[2][3];
-        if (e < by) voxel(bx - 1, e - 1, k, L, dummy);
-        else voxel(e - by - 1, by - 1, k, L, dummy);
+      const int s0 = L & 1, s1 = (L + 1) & 1;
+      if (L < tz) fetch_plane(k + 2);
+      T lw1 = T(0), mw1 = T(0), lwe1 = T(0), mwe1 = T(0);
+      if (L < tz) {
+        if (worker) mat_of(tx - 1, ty - 1, k + 1, lw1, mw1);
+        if (has_extra) mat_of(ex, ey, k + 1, lwe1, mwe1);
+      }
+      T own[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+      T pk[3] = {T(0), T(0), T(0)};  // p at this thread's node of plane k
+      if (worker && MODE == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pk[c] = pl[s0 * 3 * PP + c * PP + (ty + 1) * PW + (tx + 1)];
+      }
+      // pass 0: the thread's own voxel, pass 1: its halo voxel (if any);
+      // one code body so the two are not interleaved (register pressure)
+#pragma nounroll
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool doit = pass == 0 ? worker : has_extra;
+        if (!doit) continue;
+        T o[2][3];
+        voxel(pass == 0 ? tx - 1 : ex, pass == 0 ? ty - 1 : ey, s0, s1, pass == 0 ? lw0 : lwe,
+              pass == 0 ? mw0 : mwe, o);
+        if (pass == 0) {
+#pragma unroll
+          for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) own[z][c] = o[z][c];
+        }
       }
       __syncthreads();
       if (worker) {
@@ -213,12 +284,11 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
         const int gx = x0 + tx, gy = y0 + ty;
         if (L >= 1 && k < nz && gx < nx && gy < ny) {
           const long long node = ((long long)k * ny + gy) * nx + gx;
-          const T* pk = pl + (L & 1) * 3 * PP;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             if (MODE == 0) {
               out[c * n + node] = (TO)val[c];
-              acc += (double)pk[c * PP + (ty + 1) * PW + (tx + 1)] * (double)val[c];
+              acc += (double)pk[c] * (double)val[c];
             } else {
               out[c * n + node] = (TO)(-val[c]);
               acc += (double)val[c] * (double)val[c];
@@ -228,9 +298,208 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
 #pragma unroll
         for (int c = 0; c < 3; ++c) carry[c] = nc[c];
       }
+      if (L < tz) store_plane(s0);
+      lw0 = lw1;
+      mw0 = mw1;
+      lwe = lwe1;
+      mwe = mwe1;
       __syncthreads();
     }
     const double bs = block_sum<NT>(acc, sh);
+    if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
+  }
+}
+
+// Same scheme with compile-time tile shape (BX x BY nodes, NTH = BX * BY
+// threads): all LDS offsets are constants and every per-voxel global index is
+// a precomputed in-plane offset plus the plane base, so the loop body is the
+// simplex arithmetic, LDS traffic and a handful of adds.
+template <typename T, typename TO, int MODE, bool UNI, int BX, int BY>
+__global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz) {
+  constexpr int NTH = BX * BY;
+  constexpr int PW = BX + 2, PP = PW * (BY + 2);
+  constexpr int VW = BX + 1, VV = VW * (BY + 1);
+  constexpr int PF = (3 * PP + NTH - 1) / NTH;
+  constexpr int NEXTRA = BX + BY + 1;
+  __shared__ T pl[2 * 3 * PP];
+  __shared__ T cb[18 * VV];
+  __shared__ double sh[NTH / WAVE];
+  const int tid = threadIdx.x;
+  const int tx = tid % BX, ty = tid / BX;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int n = (int)a.g.n;
+  const int nxy = nx * ny;
+  const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY, z0 = blockIdx.z * tz;
+  const T ih[3] = {(T)(1.0 / a.g.h[0]), (T)(1.0 / a.g.h[1]), (T)(1.0 / a.g.h[2])};
+  const double wd = a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0;
+  const T w = (T)(UNI ? wd / (a.g.h[0] * a.g.h[0]) : wd);
+  const T msc = (T)(UNI ? a.g.h[0] : 1.0);
+  const bool has_extra = tid < NEXTRA;
+  const int ex = tid < BY ? BX - 1 : tid - BY - 1;
+  const int ey = tid < BY ? tid - 1 : BY - 1;
+  const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  int poff[PF];
+#pragma unroll
+  for (int q = 0; q < PF; ++q) {
+    const int e = tid + q * NTH;
+    poff[q] = -1;
+    if (e < 3 * PP) {
+      const int c = e / PP, rem = e - c * PP;
+      const int py = rem / PW, px = rem - py * PW;
+      poff[q] = c * n + wrapi(y0 - 1 + py, ny) * nx + wrapi(x0 - 1 + px, nx);
+    }
+  }
+  // in-plane voxel offsets (material) and LDS corner bases of the two voxels
+  const int vown = wrapi(y0 + ty - 1, ny) * nx + wrapi(x0 + tx - 1, nx);
+  const int vext = wrapi(y0 + ey, ny) * nx + wrapi(x0 + ex, nx);
+  const int bown = ty * PW + tx;              // voxel (tx-1, ty-1): corner (0,0) at (tx, ty)
+  const int bext = (ey + 1) * PW + (ex + 1);
+  const int cown = ty * VW + tx;              // cb index of voxel (tx-1, ty-1)
+  const int cext = (ey + 1) * VW + (ex + 1);
+  const bool out_ok = (x0 + tx < nx) && (y0 + ty < ny);
+  for (int l = 0; l < a.nload; ++l) {
+    bool live;
+    if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
+    else live = a.only_load < 0 || a.only_load == l;
+    if (!live) continue;
+    const T* u = a.u ? a.u + l * a.lstride : nullptr;
+    TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
+    T sbd[6];
+    if (MODE == 1) {
+      const double* e = a.eps[l];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) sbd[i] = (T)e[i];
+    }
+    T pf[PF];
+    auto fetch_plane = [&](int zp) {
+      const int zoff = wrapi(zp, nz) * nxy;
+#pragma unroll
+      for (int q = 0; q < PF; ++q)
+        if (poff[q] >= 0) pf[q] = u ? u[poff[q] + zoff] : T(0);
+    };
+    auto store_plane = [&](int slot) {
+#pragma unroll
+      for (int q = 0; q < PF; ++q)
+        if (poff[q] >= 0) pl[slot * 3 * PP + tid + q * NTH] = pf[q];
+    };
+    auto voxel = [&](int base, int ci, int s0, int s1, T lw, T mw, T (&own)[2][3]) {
+      T uu[8][3];
+#pragma unroll
+      for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+          for (int ox = 0; ox < 2; ++ox)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              uu[ox + 2 * oy + 4 * oz][c] = pl[(oz ? s1 : s0) * 3 * PP + c * PP + base + oy * PW + ox];
+      T f[8][3];
+      if (MODE == 1) {
+        T sb[6];
+        const T tr = sbd[0] + sbd[1] + sbd[2];
+        sb[0] = msc * (lw * tr + T(2) * mw * sbd[0]);
+        sb[1] = msc * (lw * tr + T(2) * mw * sbd[1]);
+        sb[2] = msc * (lw * tr + T(2) * mw * sbd[2]);
+        sb[3] = msc * (T(2) * mw * sbd[3]);
+        sb[4] = msc * (T(2) * mw * sbd[4]);
+        sb[5] = msc * (T(2) * mw * sbd[5]);
+        voxel3<T, true, UNI>(uu, lw, mw, ih, sb, f);
+      } else {
+        voxel3<T, false, UNI>(uu, lw, mw, ih, nullptr, f);
+      }
+#pragma unroll
+      for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cb[((0 * 2 + oz) * 3 + c) * VV + ci] = f[0 + 4 * oz][c];
+          cb[((1 * 2 + oz) * 3 + c) * VV + ci] = f[1 + 4 * oz][c];
+          cb[((2 * 2 + oz) * 3 + c) * VV + ci] = f[2 + 4 * oz][c];
+          own[oz][c] = f[3 + 4 * oz][c];
+        }
+    };
+    double acc = 0.0;
+    T carry[3] = {T(0), T(0), T(0)};
+    fetch_plane(z0 - 1);
+    store_plane(0);
+    fetch_plane(z0);
+    store_plane(1);
+    int zm = wrapi(z0 - 1, nz) * nxy;
+    T lw0 = a.mat[2 * (zm + vown)] * w, mw0 = a.mat[2 * (zm + vown) + 1] * w;
+    T lwe = T(0), mwe = T(0);
+    if (has_extra) {
+      lwe = a.mat[2 * (zm + vext)] * w;
+      mwe = a.mat[2 * (zm + vext) + 1] * w;
+    }
+    __syncthreads();
+    for (int L = 0; L <= tz; ++L) {
+      const int k = z0 - 1 + L;
+      const int s0 = L & 1, s1 = (L + 1) & 1;
+      if (L < tz) fetch_plane(k + 2);
+      T lw1 = T(0), mw1 = T(0), lwe1 = T(0), mwe1 = T(0);
+      if (L < tz) {
+        const int zn = wrapi(k + 1, nz) * nxy;
+        lw1 = a.mat[2 * (zn + vown)] * w;
+        mw1 = a.mat[2 * (zn + vown) + 1] * w;
+        if (has_extra) {
+          lwe1 = a.mat[2 * (zn + vext)] * w;
+          mwe1 = a.mat[2 * (zn + vext) + 1] * w;
+        }
+      }
+      T pk[3] = {T(0), T(0), T(0)};
+      if (MODE == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pk[c] = pl[s0 * 3 * PP + c * PP + (ty + 1) * PW + (tx + 1)];
+      }
+      T own[2][3];
+#pragma nounroll
+      for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1 && !has_extra) break;
+        T o[2][3];
+        voxel(pass == 0 ? bown : bext, pass == 0 ? cown : cext, s0, s1, pass == 0 ? lw0 : lwe,
+              pass == 0 ? mw0 : mwe, o);
+        if (pass == 0) {
+#pragma unroll
+          for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) own[z][c] = o[z][c];
+        }
+      }
+      __syncthreads();
+      {
+        const int i00 = (ty + 1) * VW + (tx + 1);
+        const int i10 = (ty + 1) * VW + tx;
+        const int i01 = ty * VW + (tx + 1);
+        T val[3], nc[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          val[c] = carry[c] + own[0][c] + cb[(0 * 3 + c) * VV + i00] + cb[(6 + c) * VV + i10] +
+                   cb[(12 + c) * VV + i01];
+          nc[c] = own[1][c] + cb[(3 + c) * VV + i00] + cb[(9 + c) * VV + i10] + cb[(15 + c) * VV + i01];
+        }
+        if (L >= 1 && k < nz && out_ok) {
+          const int node = k * nxy + (y0 + ty) * nx + (x0 + tx);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            if (MODE == 0) {
+              out[c * n + node] = (TO)val[c];
+              acc += (double)pk[c] * (double)val[c];
+            } else {
+              out[c * n + node] = (TO)(-val[c]);
+              acc += (double)val[c] * (double)val[c];
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) carry[c] = nc[c];
+      }
+      if (L < tz) store_plane(s0);
+      lw0 = lw1;
+      mw0 = mw1;
+      lwe = lwe1;
+      mwe = mwe1;
+      __syncthreads();
+    }
+    const double bs = block_sum<NTH>(acc, sh);
     if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
   }
 }
@@ -497,8 +766,19 @@ static Tile3 pick_tile3(const Geom& g, bool fp64) {
     if (g.nx % d == 0) { t.bx = d; break; }
   t.by = NT / t.bx;
   if (t.by > g.ny) t.by = g.ny;
-  t.tz = g.nz >= 16 ? 16 : g.nz;
+  t.tz = g.nz >= 32 ? 32 : g.nz;
   return t;
+}
+
+// compile-time tiles: fp32 64 x 4 (or 64 x 8), fp64 32 x 8
+template <typename T> struct FastTile;
+template <> struct FastTile<float> { static constexpr int BX = 64, BY = 4; };
+template <> struct FastTile<double> { static constexpr int BX = 32, BY = 8; };
+
+static bool use_fast3(const Geom& g, bool fp64) {
+  const int bx = fp64 ? FastTile<double>::BX : FastTile<float>::BX;
+  const int by = fp64 ? FastTile<double>::BY : FastTile<float>::BY;
+  return g.dim == 3 && g.nx % bx == 0 && g.ny % by == 0 && g.n < (1LL << 29);
 }
 
 template <typename T>
@@ -512,6 +792,9 @@ int stencil_blocks(const Geom& g) {
   for (int fp64 = 0; fp64 < 2; ++fp64) {
     const Tile3 t = pick_tile3(g, fp64);
     mb = std::max(mb, (g.nx / t.bx) * ((g.ny + t.by - 1) / t.by) * ((g.nz + t.tz - 1) / t.tz));
+    const int bx = fp64 ? FastTile<double>::BX : FastTile<float>::BX;
+    const int by = fp64 ? FastTile<double>::BY : FastTile<float>::BY;
+    if (use_fast3(g, fp64)) mb = std::max(mb, (g.nx / bx) * (g.ny / by) * ((g.nz + t.tz - 1) / t.tz));
   }
   return mb;
 }
@@ -520,12 +803,23 @@ template <typename T, typename TO, int MODE>
 static hipError_t launch_stencil_impl(const KArgs<T>& a, hipStream_t s) {
   const Geom& g = a.g;
   int nparts;
-  if (g.dim == 3) {
+  if (g.dim == 3 && use_fast3(g, sizeof(T) == 8)) {
+    constexpr int BX = FastTile<T>::BX, BY = FastTile<T>::BY;
+    const int tz = pick_tile3(g, sizeof(T) == 8).tz;
+    dim3 grid(g.nx / BX, g.ny / BY, (g.nz + tz - 1) / tz);
+    nparts = grid.x * grid.y * grid.z;
+    const bool uni = g.h[0] == g.h[1] && g.h[1] == g.h[2];
+    if (uni) hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, true, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz);
+    else hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, false, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz);
+  } else if (g.dim == 3) {
     const Tile3 t = pick_tile3(g, sizeof(T) == 8);
     dim3 grid(g.nx / t.bx, (g.ny + t.by - 1) / t.by, (g.nz + t.tz - 1) / t.tz);
     nparts = grid.x * grid.y * grid.z;
     const size_t lds = stencil3_lds<T>(t);
-    hipLaunchKernelGGL((k_stencil3<T, TO, MODE>), grid, dim3(NT), lds, s, a, t.bx, t.by, t.tz);
+    if (3 * (t.bx + 2) * (t.by + 2) > PF_MAX * NT) return hipErrorInvalidValue;
+    const bool uni = g.h[0] == g.h[1] && g.h[1] == g.h[2];
+    if (uni) hipLaunchKernelGGL((k_stencil3<T, TO, MODE, true>), grid, dim3(NT), lds, s, a, t.bx, t.by, t.tz);
+    else hipLaunchKernelGGL((k_stencil3<T, TO, MODE, false>), grid, dim3(NT), lds, s, a, t.bx, t.by, t.tz);
   } else {
     dim3 grid((unsigned)((g.n + NT - 1) / NT), a.nload);
     nparts = grid.x;
