@@ -319,6 +319,7 @@ cell_status iteration(cell_s* c, int nload, bool kapply) {
   pa.w = (T)(c->d == 3 ? c->g.h[0] * c->g.h[1] * c->g.h[2] / 6.0 : c->g.h[0] * c->g.h[1] / 2.0);
   for (int a = 0; a < 3; ++a) pa.ih[a] = (T)(1.0 / c->g.h[a]);
   pa.inv_n = (T)(1.0 / (double)c->n);
+  pa.nload = nload;
   pa.st = c->st;
   pa.red = red_of(c);
   if (c->d == 3) {

@@ -78,6 +78,21 @@ __device__ __forceinline__ double sum_partials(const double* parts, int nparts, 
   return block_sum<NT>(v, sh);
 }
 
+// ---------------------------------------------------------------- XCD order
+// Workgroups of a launch are dealt round-robin to the 8 XCDs (each with its
+// own L2).  xcd_order maps the hardware block id so that every XCD receives
+// a contiguous range of the logical work list: consecutive logical items
+// (tiles that share cache lines, or the load cases of one tile that share
+// the material) then run back to back on the same L2.  Launch 8 * chunk
+// blocks, chunk = ceil(total / 8); returns -1 for padding blocks.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_order(int b, int total) {
+  const int chunk = (total + NXCD - 1) / NXCD;
+  const int logical = (b % NXCD) * chunk + b / NXCD;
+  return logical < total ? logical : -1;
+}
+inline int xcd_grid(int total) { return NXCD * ((total + NXCD - 1) / NXCD); }
+
 // ---------------------------------------------------------------- FFT codelets
 template <typename T, int R, bool INV> struct Dft;
 

@@ -324,12 +324,18 @@ __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
   __shared__ cpx<T> buf[N * NC];
   __shared__ cpx<T> tws[N];
   __shared__ double sh[NT / WAVE];
-  const int l = blockIdx.y;
-  if (!load_live(a.st + l, true)) return;
+  // logical item = (load, y, slot tile), slot tile fastest: the two tiles
+  // sharing each 128-byte line run back to back on one XCD
   const int M = a.nx / 2;
   const int ntile = (M + TX - 1) / TX;
-  const int tile = blockIdx.x % ntile;
-  const int y = blockIdx.x / ntile;
+  const int per_load = ntile * a.ny;
+  const int item = xcd_order(blockIdx.x, per_load * a.nload);
+  if (item < 0) return;
+  const int l = item / per_load;
+  const int pb = item - l * per_load;  // partial index within the load
+  if (!load_live(a.st + l, true)) return;
+  const int tile = pb % ntile;
+  const int y = pb / ntile;
   const int s0 = tile * TX;
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tws[i] = a.tw[i];
@@ -408,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
     if (s0 + s < M) base[c * cstride + z * zstride + s] = buf[e];
   }
   const double bs = block_sum<NT>(acc, sh);
-  if (tid == 0) a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
+  if (tid == 0) a.red.slot_parts(RED_RZ, l)[pb] = bs;
 }
 
 // ===================================================== y pass (2D, last)
@@ -643,7 +649,7 @@ hipError_t launch_last(const PArgs<T>& a, int dim, int nload, hipStream_t s) {
   const int M = a.nx / 2;
   const int ntile = (M + TX - 1) / TX;
   if (dim == 3) {
-    dim3 grid(ntile * a.ny, nload);
+    dim3 grid(xcd_grid(ntile * a.ny * nload));
     switch (a.nz) {
 #define C_(n) case n: hipLaunchKernelGGL((k_zpass<T, n>), grid, dim3(NT), 0, s, a); break;
       CELLFFT_NSIZES(C_)

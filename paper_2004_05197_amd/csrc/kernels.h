@@ -66,6 +66,7 @@ template <typename T> struct PArgs {
   T w;                  // simplex weight |s| = h_x h_y (h_z) / d!
   T ih[3];              // 1 / h_a
   T inv_n;              // 1 / (nx ny nz): folds the unnormalised inverse DFT
+  int nload;            // load cases in the launch
   LoadState* st;
   RedBuf red;
 };

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
 // a precomputed in-plane offset plus the plane base, so the loop body is the
 // simplex arithmetic, LDS traffic and a handful of adds.
 template <typename T, typename TO, int MODE, bool UNI, int BX, int BY>
-__global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz) {
+__global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nxt, int nyt, int nzt) {
   constexpr int NTH = BX * BY;
   constexpr int PW = BX + 2, PP = PW * (BY + 2);
   constexpr int VW = BX + 1, VV = VW * (BY + 1);
@@ -329,7 +329,20 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz) {
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const int n = (int)a.g.n;
   const int nxy = nx * ny;
-  const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY, z0 = blockIdx.z * tz;
+  // logical work item = (tile, load), load fastest, tiles x-then-y-then-z
+  const int ntiles = nxt * nyt * nzt;
+  const int item = xcd_order(blockIdx.x, ntiles * a.nload);
+  if (item < 0) return;
+  const int l = item % a.nload;
+  const int blk = item / a.nload;
+  {
+    bool live;
+    if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
+    else live = a.only_load < 0 || a.only_load == l;
+    if (!live) return;
+  }
+  const int bxi = blk % nxt, byi = (blk / nxt) % nyt, bzi = blk / (nxt * nyt);
+  const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * tz;
   const T ih[3] = {(T)(1.0 / a.g.h[0]), (T)(1.0 / a.g.h[1]), (T)(1.0 / a.g.h[2])};
   const double wd = a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0;
   const T w = (T)(UNI ? wd / (a.g.h[0] * a.g.h[0]) : wd);
@@ -337,7 +350,6 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz) {
   const bool has_extra = tid < NEXTRA;
   const int ex = tid < BY ? BX - 1 : tid - BY - 1;
   const int ey = tid < BY ? tid - 1 : BY - 1;
-  const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   int poff[PF];
 #pragma unroll
   for (int q = 0; q < PF; ++q) {
@@ -357,11 +369,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz) {
   const int cown = ty * VW + tx;              // cb index of voxel (tx-1, ty-1)
   const int cext = (ey + 1) * VW + (ex + 1);
   const bool out_ok = (x0 + tx < nx) && (y0 + ty < ny);
-  for (int l = 0; l < a.nload; ++l) {
-    bool live;
-    if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
-    else live = a.only_load < 0 || a.only_load == l;
-    if (!live) continue;
+  {
     const T* u = a.u ? a.u + l * a.lstride : nullptr;
     TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
     T sbd[6];
@@ -806,11 +814,14 @@ static hipError_t launch_stencil_impl(const KArgs<T>& a, hipStream_t s) {
   if (g.dim == 3 && use_fast3(g, sizeof(T) == 8)) {
     constexpr int BX = FastTile<T>::BX, BY = FastTile<T>::BY;
     const int tz = pick_tile3(g, sizeof(T) == 8).tz;
-    dim3 grid(g.nx / BX, g.ny / BY, (g.nz + tz - 1) / tz);
-    nparts = grid.x * grid.y * grid.z;
+    const int nxt = g.nx / BX, nyt = g.ny / BY, nzt = (g.nz + tz - 1) / tz;
+    nparts = nxt * nyt * nzt;
+    dim3 grid(xcd_grid(nparts * a.nload));
     const bool uni = g.h[0] == g.h[1] && g.h[1] == g.h[2];
-    if (uni) hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, true, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz);
-    else hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, false, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz);
+    if (uni)
+      hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, true, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz, nxt, nyt, nzt);
+    else
+      hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, false, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz, nxt, nyt, nzt);
   } else if (g.dim == 3) {
     const Tile3 t = pick_tile3(g, sizeof(T) == 8);
     dim3 grid(g.nx / t.bx, (g.ny + t.by - 1) / t.by, (g.nz + t.tz - 1) / t.tz);
