@@ -59,6 +59,9 @@ template <typename T> struct Fields {
   cpx<T>* S = nullptr;
   cpx<T>* tw[3] = {nullptr, nullptr, nullptr};
   T* trig[3] = {nullptr, nullptr, nullptr};
+  T* symtab = nullptr;   // 3D: tabulated K_ref^{-1}/n (see k_symtab)
+  T* symtabB = nullptr;
+  double sym_lam0 = -1.0, sym_mu0 = -1.0;  // reference medium of the table
   bool ready = false;
 };
 
@@ -270,6 +273,52 @@ KArgs<T> kargs(cell_s* c, int mode, const T* u, void* out, const T* mat, int nlo
   return a;
 }
 
+template <typename T>
+PArgs<T> make_pargs(cell_s* c, int nload) {
+  Fields<T>& F = fields<T>(c);
+  PArgs<T> pa{};
+  pa.S = F.S;
+  pa.lstrideC = c->lstride / 2;
+  pa.nx = c->g.nx;
+  pa.ny = c->g.ny;
+  pa.nz = c->g.nz;
+  pa.tw = F.tw[c->d - 1];
+  for (int a = 0; a < 3; ++a) pa.trig[a] = F.trig[a];
+  pa.lam0 = (T)c->lam0;
+  pa.mu0 = (T)c->mu0;
+  pa.w = (T)(c->d == 3 ? c->g.h[0] * c->g.h[1] * c->g.h[2] / 6.0 : c->g.h[0] * c->g.h[1] / 2.0);
+  for (int a = 0; a < 3; ++a) pa.ih[a] = (T)(1.0 / c->g.h[a]);
+  pa.inv_n = (T)(1.0 / (double)c->n);
+  pa.nload = nload;
+  pa.tab = nullptr;
+  pa.tabB = nullptr;
+  pa.st = c->st;
+  pa.red = red_of(c);
+  return pa;
+}
+
+// 3D: (re)builds the tabulated inverse symbol when the reference medium
+// changed, and points pa at it
+template <typename T>
+cell_status ensure_symtab(cell_s* c, PArgs<T>& pa) {
+  if (c->d != 3) return CELL_OK;
+  Fields<T>& F = fields<T>(c);
+  if (!F.symtab) {
+    const size_t entries = (size_t)c->g.ny * c->g.nz * (c->g.nx / 2);
+    if (hipMalloc((void**)&F.symtab, sizeof(T) * 6 * entries) != hipSuccess ||
+        hipMalloc((void**)&F.symtabB, sizeof(T) * 6 * 2 * c->g.nz) != hipSuccess)
+      return fail(CELL_E_NOMEM, "device allocation of the symbol table failed");
+  }
+  if (F.sym_lam0 != c->lam0 || F.sym_mu0 != c->mu0) {
+    HIPCHK(launch_symtab<T>(pa, F.symtab, F.symtabB, c->stream));
+    F.sym_lam0 = c->lam0;
+    F.sym_mu0 = c->mu0;
+  }
+  pa.tab = F.symtab;
+  pa.tabB = F.symtabB;
+  return CELL_OK;
+}
+
 // one PCG iteration (or the initial preconditioning if !kapply)
 template <typename T>
 cell_status iteration(cell_s* c, int nload, bool kapply) {
@@ -306,22 +355,8 @@ cell_status iteration(cell_s* c, int nload, bool kapply) {
   ya.ncomp = c->d;
   ya.tw = F.tw[1];
   ya.st = c->st;
-  PArgs<T> pa{};
-  pa.S = F.S;
-  pa.lstrideC = c->lstride / 2;
-  pa.nx = c->g.nx;
-  pa.ny = c->g.ny;
-  pa.nz = c->g.nz;
-  pa.tw = F.tw[c->d - 1];
-  for (int a = 0; a < 3; ++a) pa.trig[a] = F.trig[a];
-  pa.lam0 = (T)c->lam0;
-  pa.mu0 = (T)c->mu0;
-  pa.w = (T)(c->d == 3 ? c->g.h[0] * c->g.h[1] * c->g.h[2] / 6.0 : c->g.h[0] * c->g.h[1] / 2.0);
-  for (int a = 0; a < 3; ++a) pa.ih[a] = (T)(1.0 / c->g.h[a]);
-  pa.inv_n = (T)(1.0 / (double)c->n);
-  pa.nload = nload;
-  pa.st = c->st;
-  pa.red = red_of(c);
+  PArgs<T> pa = make_pargs<T>(c, nload);
+  STCHK(ensure_symtab<T>(c, pa));
   if (c->d == 3) {
     ProfScope ps(c, CELL_K_YFWD);
     HIPCHK(launch_ypass<T>(ya, false, nload, s));
@@ -552,7 +587,9 @@ void cell_destroy(cell_t c) {
   fr(c->mat32);
   fr(c->E64);
   for (void* p : {(void*)c->f32.x, (void*)c->f32.r, (void*)c->f32.p, (void*)c->f32.q, (void*)c->f32.S,
-                  (void*)c->f64.x, (void*)c->f64.r, (void*)c->f64.p, (void*)c->f64.q, (void*)c->f64.S})
+                  (void*)c->f32.symtab, (void*)c->f32.symtabB, (void*)c->f64.x, (void*)c->f64.r,
+                  (void*)c->f64.p, (void*)c->f64.q, (void*)c->f64.S, (void*)c->f64.symtab,
+                  (void*)c->f64.symtabB})
     fr(p);
   for (int a = 0; a < 3; ++a) {
     fr(c->f32.tw[a]);

@@ -41,6 +41,10 @@ template <typename T, int M> constexpr int x_rpb() {
 }
 template <typename T> constexpr int y_tx() { return sizeof(T) == 4 ? 16 : 8; }
 template <typename T> constexpr int z_tx() { return sizeof(T) == 4 ? 8 : 4; }
+// threads per block of the y and last passes (more waves per CU to hide
+// the load -> FFT -> store latency of each tile)
+constexpr int NTY = 512;
+constexpr int NTZ = 512;
 
 // ================================================================= x forward
 template <typename T, int M>
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
 
 // ================================================================= y pass 3D
 template <typename T, int N, bool INV>
-__global__ __launch_bounds__(NT) void k_ypass(YArgs<T> a) {
+__global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
   constexpr int TX = y_tx<T>();
   __shared__ cpx<T> buf[N * TX];
   __shared__ cpx<T> tws[N];
@@ -187,19 +191,19 @@ __global__ __launch_bounds__(NT) void k_ypass(YArgs<T> a) {
   const int c = b / a.nz;
   const int s0 = tile * TX;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) tws[i] = a.tw[i];
+  for (int i = tid; i < N; i += NTY) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + ((long long)(c * a.nz + z) * a.ny) * M + s0;
-  for (int e = tid; e < N * TX; e += NT) {
+  for (int e = tid; e < N * TX; e += NTY) {
     const int y = e / TX, s = e - y * TX;
     buf[e] = (s0 + s < M) ? base[(long long)y * M + s] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
   if (INV && s0 == 0) {
     // remix column 0: c(k) = A(k) + i B(k)
-    cpx<T> v[(N + NT - 1) / NT];
+    cpx<T> v[(N + NTY - 1) / NTY];
 #pragma unroll
-    for (int q = 0; q < (N + NT - 1) / NT; ++q) {
-      const int k = tid + q * NT;
+    for (int q = 0; q < (N + NTY - 1) / NTY; ++q) {
+      const int k = tid + q * NTY;
       if (k < N) {
         const cpx<T> rk = buf[k * TX], rm = buf[((N - k) % N) * TX];
         if (k == 0) v[q] = {rk.re, buf[(N / 2) * TX].re};
@@ -210,19 +214,19 @@ __global__ __launch_bounds__(NT) void k_ypass(YArgs<T> a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < (N + NT - 1) / NT; ++q) {
-      const int k = tid + q * NT;
+    for (int q = 0; q < (N + NTY - 1) / NTY; ++q) {
+      const int k = tid + q * NTY;
       if (k < N) buf[k * TX] = v[q];
     }
     __syncthreads();
   }
-  fft_lds<T, N, INV, TX, NT, 1, ColTile<TX>>(buf, tws);
+  fft_lds<T, N, INV, TX, NTY, 1, ColTile<TX>>(buf, tws);
   if (!INV && s0 == 0) {
     // unmix column 0 into the X[0] field (rows < N/2) and X[nx/2] field
-    cpx<T> v[(N + NT - 1) / NT];
+    cpx<T> v[(N + NTY - 1) / NTY];
 #pragma unroll
-    for (int q = 0; q < (N + NT - 1) / NT; ++q) {
-      const int k = tid + q * NT;
+    for (int q = 0; q < (N + NTY - 1) / NTY; ++q) {
+      const int k = tid + q * NTY;
       if (k < N) {
         const cpx<T> ck = buf[k * TX], cm = buf[((N - k) % N) * TX];
         if (k == 0) v[q] = {ck.re, buf[(N / 2) * TX].re};
@@ -233,13 +237,13 @@ __global__ __launch_bounds__(NT) void k_ypass(YArgs<T> a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < (N + NT - 1) / NT; ++q) {
-      const int k = tid + q * NT;
+    for (int q = 0; q < (N + NTY - 1) / NTY; ++q) {
+      const int k = tid + q * NTY;
       if (k < N) buf[k * TX] = v[q];
     }
     __syncthreads();
   }
-  for (int e = tid; e < N * TX; e += NT) {
+  for (int e = tid; e < N * TX; e += NTY) {
     const int y = e / TX, s = e - y * TX;
     if (s0 + s < M) base[(long long)y * M + s] = buf[e];
   }
@@ -252,9 +256,9 @@ __global__ __launch_bounds__(NT) void k_ypass(YArgs<T> a) {
 //   K_cd = 2 w (lam + mu) sigma_c sigma_d [2 cos(th_c + th_d) + cos(th_c + th_d + 2 th_e)]  (3D)
 //   K_01 = 2 w (lam + mu) sigma_0 sigma_1 cos(th_0 + th_1)                                   (2D)
 // Applies z = K^{-1} r * inv_n to a complex 3-vector (2-vector).
+// Inverse of the symbol times inv_n, as (00, 11, 22, 01, 02, 12).
 template <typename T>
-__device__ __forceinline__ void sym_solve3(const PArgs<T>& P, int kx, int ky, int kz,
-                                           const cpx<T>* r, cpx<T>* z) {
+__device__ __forceinline__ void sym_inv3(const PArgs<T>& P, int kx, int ky, int kz, T* m) {
   const T sx = P.trig[0][2 * kx], cx = P.trig[0][2 * kx + 1];
   const T sy = P.trig[1][2 * ky], cy = P.trig[1][2 * ky + 1];
   const T sz = P.trig[2][2 * kz], cz = P.trig[2][2 * kz + 1];
@@ -286,9 +290,75 @@ __device__ __forceinline__ void sym_solve3(const PArgs<T>& P, int kx, int ky, in
   const T b12 = a01 * a02 - a00 * a12;
   const T det = a00 * b00 + a01 * b01 + a02 * b02;
   const T s = P.inv_n / det;
-  z[0] = (r[0] * b00 + r[1] * b01 + r[2] * b02) * s;
-  z[1] = (r[0] * b01 + r[1] * b11 + r[2] * b12) * s;
-  z[2] = (r[0] * b02 + r[1] * b12 + r[2] * b22) * s;
+  m[0] = b00 * s;
+  m[1] = b11 * s;
+  m[2] = b22 * s;
+  m[3] = b01 * s;
+  m[4] = b02 * s;
+  m[5] = b12 * s;
+}
+
+template <typename T>
+__device__ __forceinline__ void sym_apply3(const T* m, const cpx<T>* r, cpx<T>* z) {
+  z[0] = r[0] * m[0] + r[1] * m[3] + r[2] * m[4];
+  z[1] = r[0] * m[3] + r[1] * m[1] + r[2] * m[5];
+  z[2] = r[0] * m[4] + r[1] * m[5] + r[2] * m[2];
+}
+
+template <typename T>
+__device__ __forceinline__ void sym_solve3(const PArgs<T>& P, int kx, int ky, int kz,
+                                           const cpx<T>* r, cpx<T>* z) {
+  T m[6];
+  sym_inv3(P, kx, ky, kz, m);
+  sym_apply3(m, r, z);
+}
+
+// tabulated inverse (6 consecutive values)
+template <typename T>
+__device__ __forceinline__ void sym_load(const T* tab, long long idx, T* m) {
+  using T2 = typename V2<T>::type;
+  const T2* t2 = reinterpret_cast<const T2*>(tab + 6 * idx);
+  const T2 a = t2[0], b = t2[1], c = t2[2];
+  m[0] = a.x;
+  m[1] = a.y;
+  m[2] = b.x;
+  m[3] = b.y;
+  m[4] = c.x;
+  m[5] = c.y;
+}
+
+// Table of K_ref^{-1}/n in the stored spectrum order: entry (y, kz, slot)
+// holds the wavevector the z pass meets there (slot 0: the X[0] family for
+// y < ny/2, the X[nx/2] family for y > ny/2 and the first family of the two
+// real-pair rows); tabB holds the second family of the real-pair rows.
+// The zero frequency entry is 0.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_symtab(PArgs<T> a, T* tab, T* tabB) {
+  const int M = a.nx / 2;
+  const long long total = (long long)a.ny * a.nz * M;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < total + 2LL * a.nz;
+       i += (long long)gridDim.x * NT) {
+    T m[6];
+    if (i < total) {
+      const int slot = (int)(i % M);
+      const int kz = (int)((i / M) % a.nz);
+      const int y = (int)(i / ((long long)M * a.nz));
+      int kx = slot, ky = y;
+      if (slot == 0) kx = (y <= a.ny / 2) ? (y == a.ny / 2 ? M : 0) : M;
+      if (slot == 0 && (y == 0 || y == a.ny / 2)) ky = 0;
+      if (slot == 0 && y == 0 && kz == 0) {
+        for (int q = 0; q < 6; ++q) m[q] = T(0);
+      } else {
+        sym_inv3(a, kx, ky, kz, m);
+      }
+      for (int q = 0; q < 6; ++q) tab[6 * i + q] = m[q];
+    } else {
+      const long long j = i - total;
+      const int r = (int)(j / a.nz), kz = (int)(j % a.nz);
+      sym_inv3(a, r == 0 ? 0 : M, a.ny / 2, kz, m);
+      for (int q = 0; q < 6; ++q) tabB[6 * j + q] = m[q];
+    }
+  }
 }
 
 template <typename T>
@@ -318,49 +388,56 @@ __device__ __forceinline__ T redot(const cpx<T>* r, const cpx<T>* z) {
 
 // ===================================================== z pass (3D, last)
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
+__global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
   constexpr int TX = z_tx<T>();
   constexpr int NC = 3 * TX;  // columns: component-major, then slot
   __shared__ cpx<T> buf[N * NC];
   __shared__ cpx<T> tws[N];
-  __shared__ double sh[NT / WAVE];
-  // logical item = (load, y, slot tile), slot tile fastest: the two tiles
-  // sharing each 128-byte line run back to back on one XCD
+  __shared__ double sh[NTZ / WAVE];
+  // logical item = (y, slot tile, load), load fastest: the load cases of a
+  // tile share its symbol-table lines and neighbouring tiles (which share
+  // 128-byte spectrum lines) stay close, all on one XCD
   const int M = a.nx / 2;
   const int ntile = (M + TX - 1) / TX;
   const int per_load = ntile * a.ny;
   const int item = xcd_order(blockIdx.x, per_load * a.nload);
   if (item < 0) return;
-  const int l = item / per_load;
-  const int pb = item - l * per_load;  // partial index within the load
+  const int l = item % a.nload;
+  const int pb = item / a.nload;  // partial index within the load
   if (!load_live(a.st + l, true)) return;
   const int tile = pb % ntile;
   const int y = pb / ntile;
   const int s0 = tile * TX;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) tws[i] = a.tw[i];
+  for (int i = tid; i < N; i += NTZ) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
   const long long cstride = (long long)a.nz * a.ny * M;   // component
   const long long zstride = (long long)a.ny * M;          // z plane
-  for (int e = tid; e < N * NC; e += NT) {
+  for (int e = tid; e < N * NC; e += NTZ) {
     const int z = e / NC, rem = e - z * NC;
     const int c = rem / TX, s = rem - c * TX;
     buf[e] = (s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
-  fft_lds<T, N, false, NC, NT, 1, ColTile<NC>>(buf, tws);
+  fft_lds<T, N, false, NC, NTZ, 1, ColTile<NC>>(buf, tws);
   const bool pair_row = (s0 == 0) && (y == 0 || y == a.ny / 2);
   double acc = 0.0;
   // ordinary wavevectors (weight 2: each stands for itself and its conjugate)
-  for (int e = tid; e < N * TX; e += NT) {
+  for (int e = tid; e < N * TX; e += NTZ) {
     const int kz = e / TX, s = e - kz * TX;
     const int slot = s0 + s;
     if (slot >= M || (slot == 0 && pair_row)) continue;
-    const int kx = slot == 0 ? (y < a.ny / 2 ? 0 : M) : slot;
     cpx<T> r[3], z[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = buf[kz * NC + c * TX + s];
-    sym_solve3(a, kx, y, kz, r, z);
+    if (a.tab) {
+      T m[6];
+      sym_load(a.tab, ((long long)y * a.nz + kz) * M + slot, m);
+      sym_apply3(m, r, z);
+    } else {
+      const int kx = slot == 0 ? (y < a.ny / 2 ? 0 : M) : slot;
+      sym_solve3(a, kx, y, kz, r, z);
+    }
     acc += 2.0 * (double)redot<T, 3>(r, z);
 #pragma unroll
     for (int c = 0; c < 3; ++c) buf[kz * NC + c * TX + s] = z[c];
@@ -369,12 +446,12 @@ __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
     // column slot 0 of rows ky = 0, ny/2: w = A_hat + i B_hat with A, B real
     // along z; A: (kx, ky) = (0 | M, 0), B: (0 | M, ny/2).
     const int kxf = (y == 0) ? 0 : M;
-    constexpr int Q = (N + NT - 1) / NT;
+    constexpr int Q = (N + NTZ - 1) / NTZ;
     cpx<T> out[Q][3];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int kz = tid + q * NT;
+      const int kz = tid + q * NTZ;
       if (kz < N) {
         const int km = (N - kz) % N;
         cpx<T> A[3], B[3], zA[3], zB[3];
@@ -384,13 +461,21 @@ __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
           A[c] = {(wk.re + wm.re) * T(0.5), (wk.im - wm.im) * T(0.5)};
           B[c] = {(wk.im + wm.im) * T(0.5), (wm.re - wk.re) * T(0.5)};
         }
-        if (y == 0 && kz == 0) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) zA[c] = {T(0), T(0)};
+        if (a.tab) {
+          T mA[6], mB[6];
+          sym_load(a.tab, ((long long)y * a.nz + kz) * M, mA);
+          sym_load(a.tabB, (long long)(y == 0 ? 0 : 1) * a.nz + kz, mB);
+          sym_apply3(mA, A, zA);
+          sym_apply3(mB, B, zB);
         } else {
-          sym_solve3(a, kxf, 0, kz, A, zA);
+          if (y == 0 && kz == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) zA[c] = {T(0), T(0)};
+          } else {
+            sym_solve3(a, kxf, 0, kz, A, zA);
+          }
+          sym_solve3(a, kxf, a.ny / 2, kz, B, zB);
         }
-        sym_solve3(a, kxf, a.ny / 2, kz, B, zB);
         acc += (double)redot<T, 3>(A, zA) + (double)redot<T, 3>(B, zB);
 #pragma unroll
         for (int c = 0; c < 3; ++c) out[q][c] = {zA[c].re - zB[c].im, zA[c].im + zB[c].re};
@@ -399,7 +484,7 @@ __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int kz = tid + q * NT;
+      const int kz = tid + q * NTZ;
       if (kz < N) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) buf[kz * NC + c * TX] = out[q][c];
@@ -407,41 +492,41 @@ __global__ __launch_bounds__(NT) void k_zpass(PArgs<T> a) {
     }
   }
   __syncthreads();
-  fft_lds<T, N, true, NC, NT, 1, ColTile<NC>>(buf, tws);
-  for (int e = tid; e < N * NC; e += NT) {
+  fft_lds<T, N, true, NC, NTZ, 1, ColTile<NC>>(buf, tws);
+  for (int e = tid; e < N * NC; e += NTZ) {
     const int z = e / NC, rem = e - z * NC;
     const int c = rem / TX, s = rem - c * TX;
     if (s0 + s < M) base[c * cstride + z * zstride + s] = buf[e];
   }
-  const double bs = block_sum<NT>(acc, sh);
+  const double bs = block_sum<NTZ>(acc, sh);
   if (tid == 0) a.red.slot_parts(RED_RZ, l)[pb] = bs;
 }
 
 // ===================================================== y pass (2D, last)
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_ylast(PArgs<T> a) {
+__global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
   constexpr int TX = z_tx<T>();
   constexpr int NC = 2 * TX;
   __shared__ cpx<T> buf[N * NC];
   __shared__ cpx<T> tws[N];
-  __shared__ double sh[NT / WAVE];
+  __shared__ double sh[NTZ / WAVE];
   const int l = blockIdx.y;
   if (!load_live(a.st + l, true)) return;
   const int M = a.nx / 2;
   const int s0 = blockIdx.x * TX;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) tws[i] = a.tw[i];
+  for (int i = tid; i < N; i += NTZ) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + s0;
   const long long cstride = (long long)a.ny * M;
-  for (int e = tid; e < N * NC; e += NT) {
+  for (int e = tid; e < N * NC; e += NTZ) {
     const int y = e / NC, rem = e - y * NC;
     const int c = rem / TX, s = rem - c * TX;
     buf[e] = (s0 + s < M) ? base[c * cstride + (long long)y * M + s] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
-  fft_lds<T, N, false, NC, NT, 1, ColTile<NC>>(buf, tws);
+  fft_lds<T, N, false, NC, NTZ, 1, ColTile<NC>>(buf, tws);
   double acc = 0.0;
-  for (int e = tid; e < N * TX; e += NT) {
+  for (int e = tid; e < N * TX; e += NTZ) {
     const int ky = e / TX, s = e - ky * TX;
     const int slot = s0 + s;
     if (slot >= M || slot == 0) continue;
@@ -454,12 +539,12 @@ __global__ __launch_bounds__(NT) void k_ylast(PArgs<T> a) {
     for (int c = 0; c < 2; ++c) buf[ky * NC + c * TX + s] = z[c];
   }
   if (s0 == 0) {
-    constexpr int Q = (N + NT - 1) / NT;
+    constexpr int Q = (N + NTZ - 1) / NTZ;
     cpx<T> out[Q][2];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int ky = tid + q * NT;
+      const int ky = tid + q * NTZ;
       if (ky < N) {
         const int km = (N - ky) % N;
         cpx<T> A[2], B[2], zA[2], zB[2];
@@ -483,7 +568,7 @@ __global__ __launch_bounds__(NT) void k_ylast(PArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int ky = tid + q * NT;
+      const int ky = tid + q * NTZ;
       if (ky < N) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) buf[ky * NC + c * TX] = out[q][c];
@@ -491,13 +576,13 @@ __global__ __launch_bounds__(NT) void k_ylast(PArgs<T> a) {
     }
   }
   __syncthreads();
-  fft_lds<T, N, true, NC, NT, 1, ColTile<NC>>(buf, tws);
-  for (int e = tid; e < N * NC; e += NT) {
+  fft_lds<T, N, true, NC, NTZ, 1, ColTile<NC>>(buf, tws);
+  for (int e = tid; e < N * NC; e += NTZ) {
     const int y = e / NC, rem = e - y * NC;
     const int c = rem / TX, s = rem - c * TX;
     if (s0 + s < M) base[c * cstride + (long long)y * M + s] = buf[e];
   }
-  const double bs = block_sum<NT>(acc, sh);
+  const double bs = block_sum<NTZ>(acc, sh);
   if (tid == 0) a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
 }
 
@@ -632,8 +717,8 @@ hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, hipStream_t 
   switch (a.ny) {
 #define C_(n)                                                                  \
   case n:                                                                      \
-    if (inverse) hipLaunchKernelGGL((k_ypass<T, n, true>), grid, dim3(NT), 0, s, a); \
-    else hipLaunchKernelGGL((k_ypass<T, n, false>), grid, dim3(NT), 0, s, a);       \
+    if (inverse) hipLaunchKernelGGL((k_ypass<T, n, true>), grid, dim3(NTY), 0, s, a); \
+    else hipLaunchKernelGGL((k_ypass<T, n, false>), grid, dim3(NTY), 0, s, a);       \
     break;
     CELLFFT_NSIZES(C_)
 #undef C_
@@ -651,7 +736,7 @@ hipError_t launch_last(const PArgs<T>& a, int dim, int nload, hipStream_t s) {
   if (dim == 3) {
     dim3 grid(xcd_grid(ntile * a.ny * nload));
     switch (a.nz) {
-#define C_(n) case n: hipLaunchKernelGGL((k_zpass<T, n>), grid, dim3(NT), 0, s, a); break;
+#define C_(n) case n: hipLaunchKernelGGL((k_zpass<T, n>), grid, dim3(NTZ), 0, s, a); break;
       CELLFFT_NSIZES(C_)
 #undef C_
       default:
@@ -660,7 +745,7 @@ hipError_t launch_last(const PArgs<T>& a, int dim, int nload, hipStream_t s) {
   } else {
     dim3 grid(ntile, nload);
     switch (a.ny) {
-#define C_(n) case n: hipLaunchKernelGGL((k_ylast<T, n>), grid, dim3(NT), 0, s, a); break;
+#define C_(n) case n: hipLaunchKernelGGL((k_ylast<T, n>), grid, dim3(NTZ), 0, s, a); break;
       CELLFFT_NSIZES(C_)
 #undef C_
       default:
@@ -670,6 +755,14 @@ hipError_t launch_last(const PArgs<T>& a, int dim, int nload, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_symtab(const PArgs<T>& a, T* tab, T* tabB, hipStream_t s) {
+  hipLaunchKernelGGL(k_symtab<T>, dim3(2048), dim3(NT), 0, s, a, tab, tabB);
+  return hipGetLastError();
+}
+
+template hipError_t launch_symtab<float>(const PArgs<float>&, float*, float*, hipStream_t);
+template hipError_t launch_symtab<double>(const PArgs<double>&, double*, double*, hipStream_t);
 template hipError_t launch_xfwd<float>(const XArgs<float>&, int, int, hipStream_t);
 template hipError_t launch_xfwd<double>(const XArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_xinv<float>(const XArgs<float>&, int, int, hipStream_t);

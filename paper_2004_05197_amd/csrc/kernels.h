@@ -67,6 +67,9 @@ template <typename T> struct PArgs {
   T ih[3];              // 1 / h_a
   T inv_n;              // 1 / (nx ny nz): folds the unnormalised inverse DFT
   int nload;            // load cases in the launch
+  const T* tab;         // 3D: tabulated K_ref^{-1} / n per stored wavevector
+                        // ([ny][nz][nx/2][6]: 00,11,22,01,02,12), or nullptr
+  const T* tabB;        // 3D: second family of the two real-pair rows [2][nz][6]
   LoadState* st;
   RedBuf red;
 };
@@ -107,6 +110,8 @@ template <typename T> hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nloa
 template <typename T> hipError_t launch_xinv(const XArgs<T>& a, int nx, int nload, hipStream_t s);
 template <typename T> hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, hipStream_t s);
 template <typename T> hipError_t launch_last(const PArgs<T>& a, int dim, int nload, hipStream_t s);
+// fills a.tab / a.tabB (3D) from the closed-form symbol of the reference medium
+template <typename T> hipError_t launch_symtab(const PArgs<T>& a, T* tab, T* tabB, hipStream_t s);
 template <typename T> hipError_t launch_stencil(const KArgs<T>& a, hipStream_t s);
 hipError_t launch_residual_mixed(const KArgs<double>& a, float* out32, hipStream_t s);
 hipError_t launch_homog(const HArgs& a, hipStream_t s);
