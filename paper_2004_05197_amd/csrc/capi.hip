@@ -127,6 +127,8 @@ struct cell_s {
   int maxblk = 0;
   double* res2 = nullptr;
   double* res2_h = nullptr;
+  double* sparts = nullptr;  // per-block stress sums of the residual launch
+  double* sbar = nullptr;    // [max_loads][6] stress sums of the last residual per load
   double* hparts = nullptr;
   double* hres = nullptr;
   double* grad = nullptr;
@@ -384,6 +386,8 @@ cell_status residual(cell_s* c, int nload, int load, const double* u) {
   Fields<T>& F = fields<T>(c);
   KArgs<double> ka = kargs<double>(c, 1, u, nullptr, c->mat64, nload);
   ka.only_load = load;
+  ka.sparts = c->sparts;
+  ka.sbar = c->sbar;
   {
     ProfScope ps(c, CELL_K_RESIDUAL);
     if (sizeof(T) == 4) {
@@ -528,6 +532,8 @@ cell_status solve_loads(cell_s* c, int nload, const double* eps, cell_info* info
   return st;
 }
 
+// C* (energy form) and mean stresses of the solved loads; uses the final
+// residuals and stress sums left by the last FP64 residual of every load
 cell_status homogenize(cell_s* c, int nload, std::vector<double>& out) {
   HArgs h{};
   h.u = solution64(c);
@@ -537,6 +543,14 @@ cell_status homogenize(cell_s* c, int nload, std::vector<double>& out) {
   h.g = c->g;
   for (int l = 0; l < 6; ++l) voigt_to_tensor(c->d, c->eps_v[l], h.eps[l]);
   h.nload = nload;
+  if (c->precision == CELL_MIXED) {
+    h.r = c->f32.r;
+    h.r_fp64 = 0;
+  } else {
+    h.r = c->f64.r;
+    h.r_fp64 = 1;
+  }
+  h.sbar = c->sbar;
   h.parts = c->hparts;
   h.result = c->hres;
   h.nblk = c->hblk;
@@ -602,6 +616,8 @@ void cell_destroy(cell_t c) {
   fr(c->parts);
   fr(c->cnt);
   fr(c->res2);
+  fr(c->sparts);
+  fr(c->sbar);
   fr(c->hparts);
   fr(c->hres);
   fr(c->grad);
@@ -678,6 +694,8 @@ cell_status cell_create(const cell_config* cfg, cell_t* out) {
       !dmalloc((void**)&c->cnt, sizeof(unsigned) * RED_NSLOT * c->max_loads) ||
       !dmalloc((void**)&c->st, sizeof(LoadState) * c->max_loads) ||
       !dmalloc((void**)&c->res2, sizeof(double) * c->max_loads) ||
+      !dmalloc((void**)&c->sparts, sizeof(double) * 6 * (size_t)c->max_loads * mb) ||
+      !dmalloc((void**)&c->sbar, sizeof(double) * 6 * c->max_loads) ||
       !dmalloc((void**)&c->mat64, sizeof(double) * 2 * c->n) ||
       !dmalloc((void**)&c->mat32, sizeof(float) * 2 * c->n) ||
       !dmalloc((void**)&c->E64, sizeof(double) * c->n) ||

@@ -87,6 +87,10 @@ template <typename T> struct KArgs {
   LoadState* st;        // mode 0: per-load scalars (alpha = rz / pq)
   int only_load;        // mode 1: >= 0 restricts to one load
   double* res2;         // mode 1: per-load ||out||^2 (FP64)
+  double* sparts;       // mode 1 (optional): per-block sums of |s| sigma over the
+                        // block's own voxels, [load][6][maxblk] (tensor storage
+                        // 00,11,22,12,02,01); nullptr = not accumulated
+  double* sbar;         // mode 1 (optional): [load][6] finalised stress sums
   RedBuf red;
 };
 
@@ -101,6 +105,9 @@ struct HArgs {
   int nload;
   double a[6][6];       // gradient weights dJ/dC_IJ
   double* grad;         // per-voxel gradient output
+  const void* r;        // residual fields f - K u [nload][d][n] (float or double)
+  int r_fp64;           // 1: r is double
+  const double* sbar;   // [nload][6]: sum over simplices of |s| sigma (tensor storage)
   double* parts;        // per-block partials [nval][nblk]
   double* result;       // [nload*nload + nload*nv]: C (energy form), mean stress
   int nblk;

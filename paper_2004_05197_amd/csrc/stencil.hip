@@ -15,7 +15,8 @@
 //              mode 0: q = K p with p.q partials, alpha = rz / pq finalised
 //              mode 1: r = -B^T D (eps_bar + B u) with ||r||^2 (FP64)
 // k_stencil2   2D analogue (node-centric gather; the 2D grids are small)
-// k_homog      energy-form effective stiffness and mean stress partials
+// k_udotr      u^I . r^J products; with the residual launch's mean stresses
+//              they give the energy-form effective stiffness (k_homog_combine)
 // k_grad       per-voxel derivative of sum_IJ a_IJ C*_IJ w.r.t. E
 #include <algorithm>
 
@@ -48,7 +49,7 @@ __host__ __device__ constexpr int sym_idx(int i, int j) {
 // !UNI: G = differences / h_a, fluxes * 1/h_a, lw = lambda |s|, sb = |s| D eps_bar.
 template <typename T, int A0, int A1, int A2, bool MACRO, bool UNI>
 __device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw2, T mw, const T* ih,
-                                         const T* sb, T (&f)[8][3]) {
+                                         const T* sb, T (&f)[8][3], T* sacc) {
   constexpr int c0 = 0, c1 = 1 << A0, c2 = c1 | (1 << A1), c3 = 7;
   T G[3][3];
 #pragma unroll
@@ -72,7 +73,10 @@ __device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw2, T mw, 
   s[5] = mw * (G[0][1] + G[1][0]);
   if (MACRO) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) s[i] += sb[i];
+    for (int i = 0; i < 6; ++i) {
+      s[i] += sb[i];
+      sacc[i] += s[i];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -89,20 +93,22 @@ __device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw2, T mw, 
   }
 }
 
+// MACRO: sb added to every simplex stress and the 6 stresses (in the
+// caller's scaling) summed into sacc[6] (which the caller zeroes).
 template <typename T, bool MACRO, bool UNI>
 __device__ __forceinline__ void voxel3(const T (&u)[8][3], T lw, T mw, const T* ih, const T* sb,
-                                       T (&f)[8][3]) {
+                                       T (&f)[8][3], T* sacc) {
 #pragma unroll
   for (int c = 0; c < 8; ++c)
 #pragma unroll
     for (int k = 0; k < 3; ++k) f[c][k] = T(0);
   const T mw2 = mw + mw;
-  simplex3<T, 0, 1, 2, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
-  simplex3<T, 0, 2, 1, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
-  simplex3<T, 1, 0, 2, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
-  simplex3<T, 1, 2, 0, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
-  simplex3<T, 2, 0, 1, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
-  simplex3<T, 2, 1, 0, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f);
+  simplex3<T, 0, 1, 2, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
+  simplex3<T, 0, 2, 1, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
+  simplex3<T, 1, 0, 2, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
+  simplex3<T, 1, 2, 0, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
+  simplex3<T, 2, 0, 1, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
+  simplex3<T, 2, 1, 0, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
       mw = a.mat[2 * vid + 1] * w;
     };
     // computes voxel (vx, vy) of layer k from planes in slots s0 (k), s1 (k+1)
-    auto voxel = [&](int vx, int vy, int s0, int s1, T lw, T mw, T (&own)[2][3]) {
+    auto voxel = [&](int vx, int vy, int s0, int s1, T lw, T mw, T (&own)[2][3], T* sv) {
       const T* p0 = pl + s0 * 3 * PP;
       const T* p1 = pl + s1 * 3 * PP;
       T uu[8][3];
@@ -212,9 +218,9 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
       T sb[6];
       if (MODE == 1) {
         macro_stress(eb, lw, mw, msc, sb);
-        voxel3<T, true, UNI>(uu, lw, mw, ih, sb, f);
+        voxel3<T, true, UNI>(uu, lw, mw, ih, sb, f, sv);
       } else {
-        voxel3<T, false, UNI>(uu, lw, mw, ih, sb, f);
+        voxel3<T, false, UNI>(uu, lw, mw, ih, sb, f, sv);
       }
       const int vi = (vy + 1) * VW + (vx + 1);
 #pragma unroll
@@ -228,6 +234,7 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
         }
     };
     double acc = 0.0;
+    double sacc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     T carry[3] = {T(0), T(0), T(0)};
     fetch_plane(z0 - 1);
     store_plane(0);
@@ -259,13 +266,19 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
         const bool doit = pass == 0 ? worker : has_extra;
         if (!doit) continue;
         T o[2][3];
+        T sv[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         voxel(pass == 0 ? tx - 1 : ex, pass == 0 ? ty - 1 : ey, s0, s1, pass == 0 ? lw0 : lwe,
-              pass == 0 ? mw0 : mwe, o);
+              pass == 0 ? mw0 : mwe, o, sv);
         if (pass == 0) {
 #pragma unroll
           for (int z = 0; z < 2; ++z)
 #pragma unroll
             for (int c = 0; c < 3; ++c) own[z][c] = o[z][c];
+          // the voxel below-left-behind a valid node is owned exactly once
+          if (MODE == 1 && L < tz && z0 + L < nz && x0 + tx < nx && y0 + ty < ny) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) sacc[i] += (double)sv[i];
+          }
         }
       }
       __syncthreads();
@@ -307,6 +320,12 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
     }
     const double bs = block_sum<NT>(acc, sh);
     if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
+    if (MODE == 1 && a.sparts) {
+      for (int i = 0; i < 6; ++i) {
+        const double v = block_sum<NT>(sacc[i], sh);
+        if (tid == 0) a.sparts[((long long)l * 6 + i) * a.red.maxblk + blk] = v * (double)msc;
+      }
+    }
   }
 }
 
@@ -390,7 +409,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
       for (int q = 0; q < PF; ++q)
         if (poff[q] >= 0) pl[slot * 3 * PP + tid + q * NTH] = pf[q];
     };
-    auto voxel = [&](int base, int ci, int s0, int s1, T lw, T mw, T (&own)[2][3]) {
+    auto voxel = [&](int base, int ci, int s0, int s1, T lw, T mw, T (&own)[2][3], T* sv) {
       T uu[8][3];
 #pragma unroll
       for (int oz = 0; oz < 2; ++oz)
@@ -411,9 +430,9 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
         sb[3] = msc * (T(2) * mw * sbd[3]);
         sb[4] = msc * (T(2) * mw * sbd[4]);
         sb[5] = msc * (T(2) * mw * sbd[5]);
-        voxel3<T, true, UNI>(uu, lw, mw, ih, sb, f);
+        voxel3<T, true, UNI>(uu, lw, mw, ih, sb, f, sv);
       } else {
-        voxel3<T, false, UNI>(uu, lw, mw, ih, nullptr, f);
+        voxel3<T, false, UNI>(uu, lw, mw, ih, nullptr, f, sv);
       }
 #pragma unroll
       for (int oz = 0; oz < 2; ++oz)
@@ -426,6 +445,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
         }
     };
     double acc = 0.0;
+    double sacc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     T carry[3] = {T(0), T(0), T(0)};
     fetch_plane(z0 - 1);
     store_plane(0);
@@ -463,13 +483,18 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
       for (int pass = 0; pass < 2; ++pass) {
         if (pass == 1 && !has_extra) break;
         T o[2][3];
+        T sv[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         voxel(pass == 0 ? bown : bext, pass == 0 ? cown : cext, s0, s1, pass == 0 ? lw0 : lwe,
-              pass == 0 ? mw0 : mwe, o);
+              pass == 0 ? mw0 : mwe, o, sv);
         if (pass == 0) {
 #pragma unroll
           for (int z = 0; z < 2; ++z)
 #pragma unroll
             for (int c = 0; c < 3; ++c) own[z][c] = o[z][c];
+          if (MODE == 1 && L < tz && z0 + L < nz) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) sacc[i] += (double)sv[i];
+          }
         }
       }
       __syncthreads();
@@ -509,6 +534,12 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
     }
     const double bs = block_sum<NTH>(acc, sh);
     if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
+    if (MODE == 1 && a.sparts) {
+      for (int i = 0; i < 6; ++i) {
+        const double v = block_sum<NTH>(sacc[i], sh);
+        if (tid == 0) a.sparts[((long long)l * 6 + i) * a.red.maxblk + blk] = v * (double)msc;
+      }
+    }
   }
 }
 
@@ -516,7 +547,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
 // plane strain, 2 triangles per pixel: (0,0)->(1,0)->(1,1), (0,0)->(0,1)->(1,1)
 template <typename T, int A0, int A1, bool MACRO>
 __device__ __forceinline__ void simplex2(const T (&u)[4][2], T lw, T mw, const T* ih, const T* sb,
-                                         T (&f)[4][2]) {
+                                         T (&f)[4][2], T* sacc) {
   constexpr int c0 = 0, c1 = 1 << A0, c2 = 3;
   T G[2][2];
 #pragma unroll
@@ -533,6 +564,9 @@ __device__ __forceinline__ void simplex2(const T (&u)[4][2], T lw, T mw, const T
     s[0] += sb[0];
     s[1] += sb[1];
     s[2] += sb[2];
+    sacc[0] += s[0];
+    sacc[1] += s[1];
+    sacc[2] += s[2];
   }
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -560,6 +594,7 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
   const double* eb = a.eps[l];
   double acc = 0.0;
+  double sacc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const long long node = (long long)blockIdx.x * NT + threadIdx.x;
   if (node < n) {
     const int i = (int)(node % nx), j = (int)(node / nx);
@@ -589,10 +624,16 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
           sb[2] = T(2) * mw * (T)eb[5];
         }
         T f[4][2] = {};
-        simplex2<T, 0, 1, MODE == 1>(uu, lw, mw, ih, sb, f);
-        simplex2<T, 1, 0, MODE == 1>(uu, lw, mw, ih, sb, f);
+        T sv[3] = {T(0), T(0), T(0)};
+        simplex2<T, 0, 1, MODE == 1>(uu, lw, mw, ih, sb, f, sv);
+        simplex2<T, 1, 0, MODE == 1>(uu, lw, mw, ih, sb, f, sv);
         val[0] += f[ox + 2 * oy][0];
         val[1] += f[ox + 2 * oy][1];
+        if (MODE == 1 && ox == 0 && oy == 0) {  // pixel (i, j) is owned by node (i, j)
+          sacc[0] += (double)sv[0];
+          sacc[1] += (double)sv[1];
+          sacc[5] += (double)sv[2];
+        }
       }
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -608,6 +649,25 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   const int cslot = MODE == 0 ? RED_PQ : RED_RES;
   const double bs = block_sum<NT>(acc, sh);
   if (threadIdx.x == 0) a.red.slot_parts(cslot, l)[blockIdx.x] = bs;
+  if (MODE == 1 && a.sparts) {
+    for (int i = 0; i < 6; ++i) {
+      const double v = block_sum<NT>(sacc[i], sh);
+      if (threadIdx.x == 0) a.sparts[((long long)l * 6 + i) * a.red.maxblk + blockIdx.x] = v;
+    }
+  }
+}
+
+// fixed-order sums of the per-block stress partials: sbar[l][i]
+__global__ __launch_bounds__(NT) void k_stress_finalize(const double* sparts, int maxblk, int nparts,
+                                                        int only_load, double* sbar) {
+  __shared__ double sh[NT / WAVE];
+  const int i = blockIdx.x, l = blockIdx.y;
+  if (only_load >= 0 && l != only_load) return;
+  const double* row = sparts + ((long long)l * 6 + i) * maxblk;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += NT) v += row[b];
+  const double s = block_sum<NT>(v, sh);
+  if (threadIdx.x == 0) sbar[l * 6 + i] = s;
 }
 
 // ============================================== homogenisation (FP64, once)
@@ -668,52 +728,71 @@ __device__ __forceinline__ void gather_corners(const HArgs& a, int l, int i, int
   }
 }
 
-__global__ __launch_bounds__(NT) void k_homog(HArgs a) {
+// Effective stiffness without a second pass over the strains: for any
+// fluctuation u^I and residual r^J = f^J - K u^J,
+//   (1/|Y|) sum |s| eps^I : D eps^J = eps_bar^I . sigma_bar^J - (u^I . r^J) / |Y|,
+// because sum |s| (B u^I)^T D (eps_bar^J + B u^J) = -(u^I)^T r^J.  The
+// mean stresses sigma_bar come from the residual launch; this kernel forms
+// the nload x nload dot products u^I . r^J (FP64 accumulation).
+template <typename TR>
+__global__ __launch_bounds__(NT) void k_udotr(HArgs a) {
   __shared__ double sh[NT / WAVE];
-  const int D = a.g.dim;
   const int nl = a.nload;
-  const int nv = D == 3 ? 6 : 3;
-  const int nval = nl * nl + nl * nv;
-  const double ih[3] = {1.0 / a.g.h[0], 1.0 / a.g.h[1], 1.0 / a.g.h[2]};
-  const double w = D == 3 ? a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0 : a.g.h[0] * a.g.h[1] / 2.0;
-  const int nsimp = D == 3 ? 6 : 2;
-  const int perm2[2][2] = {{0, 1}, {1, 0}};
-  double C[6][6] = {};
-  double sb[6][6] = {};
-  for (long long v = (long long)blockIdx.x * NT + threadIdx.x; v < a.g.n; v += (long long)gridDim.x * NT) {
-    const int i = (int)(v % a.g.nx);
-    const int j = (int)((v / a.g.nx) % a.g.ny);
-    const int k = (int)(v / ((long long)a.g.nx * a.g.ny));
-    const double lam = a.mat[2 * v], mu = a.mat[2 * v + 1];
-    double uc[6][24];
-    for (int l = 0; l < nl; ++l) gather_corners(a, l, i, j, k, uc[l]);
-    for (int p = 0; p < nsimp; ++p) {
-      int path[3];
-      for (int q = 0; q < D; ++q) path[q] = D == 3 ? kPerm3[p][q] : perm2[p][q];
-      double e[6][6], s[6][6];
-      for (int l = 0; l < nl; ++l) {
-        if (D == 3) simplex_strain<3>(uc[l], path, ih, a.eps[l], e[l]);
-        else simplex_strain<2>(uc[l], path, ih, a.eps[l], e[l]);
-        stress_from_strain(e[l], lam, mu, s[l]);
-      }
-      for (int J = 0; J < nl; ++J) {
-        for (int I = 0; I < nl; ++I) C[I][J] += w * contract(e[I], s[J]);
-        if (D == 3) {
-          for (int q = 0; q < 6; ++q) sb[J][q] += w * s[J][q];
-        } else {
-          sb[J][0] += w * s[J][0];
-          sb[J][1] += w * s[J][1];
-          sb[J][2] += w * s[J][5];
-        }
-      }
+  const long long len = a.lstride;
+  const TR* r = reinterpret_cast<const TR*>(a.r);
+  double acc[6][6] = {};
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < len; i += (long long)gridDim.x * NT) {
+    double uu[6], rr[6];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+      uu[I] = I < nl ? a.u[I * len + i] : 0.0;
+      rr[I] = I < nl ? (double)r[I * len + i] : 0.0;
     }
+#pragma unroll
+    for (int I = 0; I < 6; ++I)
+#pragma unroll
+      for (int J = 0; J < 6; ++J) acc[I][J] += uu[I] * rr[J];
   }
-  for (int t = 0; t < nval; ++t) {
-    double v;
-    if (t < nl * nl) v = C[t / nl][t % nl];
-    else v = sb[(t - nl * nl) / nv][(t - nl * nl) % nv];
+  for (int t = 0; t < nl * nl; ++t) {
+    double v = 0.0;
+#pragma unroll
+    for (int I = 0; I < 6; ++I)
+#pragma unroll
+      for (int J = 0; J < 6; ++J)
+        if (I * nl + J == t) v = acc[I][J];
     const double bs = block_sum<NT>(v, sh);
     if (threadIdx.x == 0) a.parts[(long long)t * a.nblk + blockIdx.x] = bs;
+  }
+}
+
+// one block: C_IJ and the Voigt mean stresses from the dot products and
+// the stress sums (result layout [nl*nl] C then [nl][nv] mean stress)
+__global__ __launch_bounds__(NT) void k_homog_combine(HArgs a, double inv_vol) {
+  __shared__ double sh[NT / WAVE];
+  __shared__ double dots[36];
+  const int nl = a.nload;
+  for (int t = 0; t < nl * nl; ++t) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < a.nblk; b += NT) v += a.parts[(long long)t * a.nblk + b];
+    const double s = block_sum<NT>(v, sh);
+    if (threadIdx.x == 0) dots[t] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int D = a.g.dim;
+    const int nv = D == 3 ? 6 : 3;
+    for (int I = 0; I < nl; ++I)
+      for (int J = 0; J < nl; ++J) {
+        const double* e = a.eps[I];
+        const double* sg = a.sbar + 6 * J;
+        const double es = e[0] * sg[0] + e[1] * sg[1] + e[2] * sg[2] + 2.0 * (e[3] * sg[3] + e[4] * sg[4] + e[5] * sg[5]);
+        a.result[I * nl + J] = (es - dots[I * nl + J]) * inv_vol;
+      }
+    for (int J = 0; J < nl; ++J)
+      for (int q = 0; q < nv; ++q) {
+        const int src = D == 3 ? q : (q == 2 ? 5 : q);
+        a.result[nl * nl + J * nv + q] = a.sbar[6 * J + src] * inv_vol;
+      }
   }
 }
 
@@ -838,7 +917,11 @@ static hipError_t launch_stencil_impl(const KArgs<T>& a, hipStream_t s) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_finalize(a.red, a.st, a.res2, MODE == 0 ? RED_PQ : RED_RES, nparts, a.nload, a.only_load, s);
+  e = launch_finalize(a.red, a.st, a.res2, MODE == 0 ? RED_PQ : RED_RES, nparts, a.nload, a.only_load, s);
+  if (e != hipSuccess || MODE != 1 || !a.sparts) return e;
+  hipLaunchKernelGGL(k_stress_finalize, dim3(6, a.nload), dim3(NT), 0, s, (const double*)a.sparts, a.red.maxblk,
+                     nparts, a.only_load, a.sbar);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -859,12 +942,10 @@ int homog_blocks(const Geom& g) {
 }
 
 hipError_t launch_homog(const HArgs& a, hipStream_t s) {
-  const int nv = a.g.dim == 3 ? 6 : 3;
-  const int nval = a.nload * a.nload + a.nload * nv;
-  hipLaunchKernelGGL(k_homog, dim3(a.nblk), dim3(NT), 0, s, a);
+  if (a.r_fp64) hipLaunchKernelGGL(k_udotr<double>, dim3(a.nblk), dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL(k_udotr<float>, dim3(a.nblk), dim3(NT), 0, s, a);
   const double vol = a.g.h[0] * a.g.h[1] * (a.g.dim == 3 ? a.g.h[2] : 1.0) * a.g.n;
-  hipLaunchKernelGGL(k_sum_rows, dim3(nval), dim3(NT), 0, s, (const double*)a.parts, a.nblk, 1.0 / vol,
-                     a.result);
+  hipLaunchKernelGGL(k_homog_combine, dim3(1), dim3(NT), 0, s, a, 1.0 / vol);
   return hipGetLastError();
 }
 
