@@ -54,6 +54,32 @@ def byte_model(kind, n, prec_bytes):
     }[kind]
 
 
+def source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2004_05197_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind, workload):
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) recorded in
+    profiles/traffic_<workload>.json, or None if absent or taken on other
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != source_sha256() or kind not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kind]
+    return round(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
+
+
 def cpu_baseline(E, nu, sub=128, iters=3):
     from oracle import fem, matfree
     Es = np.ascontiguousarray(E[:sub, :sub, :sub])
@@ -160,7 +186,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dom, f"grf3d_{n1}"),
         "avg_launch_ms": round(ms_tot / launches, 4),
         "launches": launches,
         "bytes_per_launch": round(alg_bytes / launches),
