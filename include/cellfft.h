@@ -115,6 +115,16 @@ cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int o
  * component with zero nodal mean. */
 cell_status cell_get_displacement(cell_t c, int load, double* u_out, int on_device);
 
+/* Energy-form matrix (1/|Y|) sum |s| eps^I : D eps^J among the nload loads of
+ * the last cell_solve / cell_effective_stiffness, host [nload][nload]
+ * (for unit loads it is C*).  CELL_E_STATE before any solve. */
+cell_status cell_energy_matrix(cell_t c, double* C_out);
+
+/* Final residual f - K u of load `load` of the last solve, [d][n], as
+ * recomputed from the FP64 solution (mixed precision: rounded to FP32 on the
+ * device).  CELL_E_STATE before any solve. */
+cell_status cell_get_residual(cell_t c, int load, double* r_out, int on_device);
+
 void cell_destroy(cell_t c);
 
 const char* cell_last_error(void);

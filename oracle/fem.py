@@ -362,3 +362,42 @@ def dC_dE(grid, E, nu, u, eps_bar):
             for I in range(nl):
                 G[I, J] += vol * np.sum(strains[I][k] * sigJ, axis=1)
     return G / grid.volume
+
+
+def residual_at_nodes(grid, E, nu, u, eps_bar, nodes):
+    """Residual r = f - K u = -sum_v sum_s |s| B_s^T D_v (eps_bar + B_s u) at
+    selected nodes only (for spot checks of fields too large to assemble).
+
+    A node is vertex j of simplex s in the voxel at node - V_s[j]; summing the
+    vertex-j rows of -|s| B_s^T sigma over all (s, j) collects every element
+    term of that node.  u: (d*n,), eps_bar: (nv,), nodes: flat node indices.
+    Returns (len(nodes), d).
+    """
+    d = grid.d
+    nodes = np.asarray(nodes, dtype=np.int64)
+    lam, mu = lame(np.ravel(E), np.ravel(nu))
+    m = voigt_m(d)
+    s = voigt_s(d)
+    comps = []
+    idx = nodes.copy()
+    for N in grid.shape:
+        comps.append(idx % N)
+        idx = idx // N
+    out = np.zeros((len(nodes), d))
+    eb = np.asarray(eps_bar, dtype=np.float64)
+    for V, vol, B in element_data(grid):
+        nvert = d + 1
+        for j in range(nvert):
+            vox = [comps[a] - V[j, a] for a in range(d)]
+            vflat = grid.flat(vox)
+            ue = np.zeros((len(nodes), d * nvert))
+            for k in range(nvert):
+                nk = grid.flat([vox[a] + V[k, a] for a in range(d)])
+                for c in range(d):
+                    ue[:, c * nvert + k] = u[c * grid.n + nk]
+            e = eb[None, :] + ue @ B.T
+            sig = lam[vflat][:, None] * (e @ m)[:, None] * m[None, :] + mu[vflat][:, None] * e * s[None, :]
+            contrib = -vol * sig @ B
+            for c in range(d):
+                out[:, c] += contrib[:, c * nvert + j]
+    return out

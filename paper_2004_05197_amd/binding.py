@@ -73,6 +73,8 @@ _SIGS = {
     "cell_apply_operator": (ct.c_int, [_P, ct.c_int, _P, _P]),
     "cell_apply_preconditioner": (ct.c_int, [_P, ct.c_int, _P, _P]),
     "cell_reference_medium": (ct.c_int, [_P, _D, _D]),
+    "cell_energy_matrix": (ct.c_int, [_P, _P]),
+    "cell_get_residual": (ct.c_int, [_P, ct.c_int, _P, ct.c_int]),
     "cell_profile": (ct.c_int, [_P, ct.c_int]),
     "cell_profile_read": (ct.c_int, [_P, _P, _P]),
 }
@@ -149,6 +151,7 @@ class Cell:
         self.n = int(np.prod(shape))
         self.nv = 3 if self.dim == 2 else 6
         self.precision = int(precision)
+        self.solves = 0  # incremented by every solve (autograd consistency check)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -179,12 +182,14 @@ class Cell:
         info = CellInfo()
         st = _check(_lib.cell_solve(self._h, nl, eb.ctypes.data_as(ct.c_void_p),
                                     out.ctypes.data_as(ct.c_void_p), ct.byref(info)))
+        self.solves += 1
         return out, dict(info.as_dict(), status=STATUS_NAMES[st])
 
     def effective_stiffness(self):
         C = np.zeros((self.nv, self.nv))
         info = CellInfo()
         st = _check(_lib.cell_effective_stiffness(self._h, C.ctypes.data_as(ct.c_void_p), ct.byref(info)))
+        self.solves += 1
         return C, dict(info.as_dict(), status=STATUS_NAMES[st])
 
     def adjoint(self, dJ_dC, out=None):
@@ -200,6 +205,16 @@ class Cell:
         u = np.zeros((self.dim, self.n))
         _check(_lib.cell_get_displacement(self._h, int(load), u.ctypes.data_as(ct.c_void_p), 0))
         return u
+
+    def energy_matrix(self, nload):
+        C = np.zeros((nload, nload))
+        _check(_lib.cell_energy_matrix(self._h, C.ctypes.data_as(ct.c_void_p)))
+        return C
+
+    def residual(self, load=0):
+        r = np.zeros((self.dim, self.n))
+        _check(_lib.cell_get_residual(self._h, int(load), r.ctypes.data_as(ct.c_void_p), 0))
+        return r
 
     def apply_operator(self, u, precision=None):
         u = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()

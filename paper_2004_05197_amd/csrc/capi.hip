@@ -135,6 +135,7 @@ struct cell_s {
   double* scratch = nullptr;  // small device scratch (means)
   int hblk = 0;
   int nload_solved = 0;
+  double energy[36] = {};  // energy-form C among the loads of the last solve
   double eps_v[6][6] = {};
   bool solved = false;
   bool solved_unit = false;
@@ -786,6 +787,7 @@ cell_status cell_solve(cell_t c, int nload, const double* macro_strain, double* 
   if (st < 0) return st;
   std::vector<double> h;
   STCHK(homogenize(c, nload, h));
+  for (int i = 0; i < nload * nload; ++i) c->energy[i] = h[i];
   if (mean_stress_out)
     for (int J = 0; J < nload; ++J)
       for (int q = 0; q < c->nv; ++q) mean_stress_out[J * c->nv + q] = h[nload * nload + J * c->nv + q];
@@ -817,6 +819,7 @@ cell_status cell_effective_stiffness(cell_t c, double* C_out, cell_info* info) {
   if (st < 0) return st;
   std::vector<double> h;
   STCHK(homogenize(c, nv, h));
+  for (int i = 0; i < nv * nv; ++i) c->energy[i] = h[i];
   double cmax = 0.0, smax = 0.0, sgap = 0.0, hgap = 0.0;
   for (int I = 0; I < nv; ++I)
     for (int J = 0; J < nv; ++J) {
@@ -925,6 +928,37 @@ cell_status cell_profile_read(cell_t c, double* ms_out, long long* launches_out)
   for (int k = 0; k < CELL_NKERNEL; ++k) {
     ms_out[k] = c->prof_ms[k];
     launches_out[k] = c->prof_cnt[k];
+  }
+  return CELL_OK;
+}
+
+cell_status cell_energy_matrix(cell_t c, double* C_out) {
+  if (!c || !C_out) return fail(CELL_E_ARG, "null argument");
+  if (!c->solved) return fail(CELL_E_STATE, "no solution available");
+  for (int i = 0; i < c->nload_solved * c->nload_solved; ++i) C_out[i] = c->energy[i];
+  return CELL_OK;
+}
+
+cell_status cell_get_residual(cell_t c, int load, double* r_out, int on_device) {
+  if (!c || !r_out) return fail(CELL_E_ARG, "null argument");
+  if (!c->solved) return fail(CELL_E_STATE, "no solution available");
+  if (load < 0 || load >= c->nload_solved) return fail(CELL_E_ARG, "load index out of range");
+  DevGuard dg(c->dev);
+  const long long off = (long long)load * c->lstride;
+  if (c->precision == CELL_MIXED) {
+    std::vector<float> h(c->lstride);
+    HIPCHK(hipMemcpyAsync(h.data(), c->f32.r + off, sizeof(float) * c->lstride, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (on_device) {
+      std::vector<double> d(h.begin(), h.end());
+      HIPCHK(hipMemcpy(r_out, d.data(), sizeof(double) * c->lstride, hipMemcpyHostToDevice));
+    } else {
+      for (long long i = 0; i < c->lstride; ++i) r_out[i] = (double)h[i];
+    }
+  } else {
+    HIPCHK(hipMemcpyAsync(r_out, c->f64.r + off, sizeof(double) * c->lstride,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
   }
   return CELL_OK;
 }

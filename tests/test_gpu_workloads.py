@@ -1,0 +1,185 @@
+"""GPU checks at the full sizes of the named workloads, in the launch
+configuration bench.py times, against what the oracle can compute at that
+size (the residual of the GPU solution, node by node or as a whole; the
+energy form evaluated on the GPU solution) and against properties that hold
+at any size (bounds, symmetry, Hill-Mandel, Euler identity, sign).
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, matfree
+from paper_2004_05197_amd import microstructures as ms
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def voigt_reuss(E, nu, d):
+    lam, mu = fem.lame(np.ravel(E), np.ravel(nu))
+    phases = {}
+    for l, m in zip(lam, mu):
+        phases[(l, m)] = phases.get((l, m), 0) + 1
+    tot = sum(phases.values())
+    V = sum(c * fem.D_voigt(l, m, d) for (l, m), c in phases.items()) / tot
+    R = np.linalg.inv(sum(c * np.linalg.inv(fem.D_voigt(l, m, d)) for (l, m), c in phases.items()) / tot)
+    return V, R
+
+
+def check_bounds(C, E, nu, d, tol):
+    V, R = voigt_reuss(E, nu, d)
+    s = np.abs(C).max()
+    assert np.linalg.eigvalsh(V - C).min() >= -tol * s
+    assert np.linalg.eigvalsh(C - R).min() >= -tol * s
+
+
+def test_spheres64_fp64_and_mixed(lib):
+    """3D 64^3 RSA spheres (r 4-8, vf 0.3, seed 2), E 1:100, nu 0.3, 6 unit loads."""
+    n = 64
+    E, nu, vf = ms.spheres_cell(n, 0.3, seed=2, contrast=100.0)
+    grid = fem.Grid((n, n, n))
+    lam, mu = fem.lame(E, nu)
+    with lib.Cell((n, n, n), precision=lib.FP64, tol=1e-10) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C64, info = c.effective_stiffness()
+        U = np.stack([c.displacement(J).reshape((3,) + grid.nshape) for J in range(6)])
+    assert info["status"] == "CELL_OK"
+    # the oracle's residual of every GPU solution (matrix-free numpy operator)
+    for J in range(6):
+        eb = np.eye(6)[J]
+        f = matfree.neg_divergence_stress(grid, lam, mu, np.zeros_like(U[J]), eb)
+        r = matfree.neg_divergence_stress(grid, lam, mu, U[J], eb)
+        assert np.linalg.norm(r) <= 1.5e-10 * np.linalg.norm(f), J
+    # the oracle's energy form on the GPU solutions equals the GPU's C*
+    h = matfree.homogenize(grid, E, nu, U, np.eye(6))
+    assert relerr(C64, h["C_energy"]) < 1e-10
+    check_bounds(C64, E, nu, 3, 1e-10)
+    assert info["sym_gap"] < 1e-8
+    # mixed precision at tol 1e-7: C* within 1e-6 of FP64
+    with lib.Cell((n, n, n), precision=lib.MIXED, tol=1e-7) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        Cm, infom = c.effective_stiffness()
+    assert infom["status"] == "CELL_OK"
+    assert relerr(Cm, C64) < 1e-6
+    # classical PCG bound with kappa <= 100: at most ~119 iterations at 1e-10
+    assert max(info["iters"]) <= 119
+
+
+def test_grf256_mixed_bench_configuration(lib):
+    """3D 256^3 thresholded GRF (ell 8, seed 3), E 1:1000, nu .25/.35, 6 loads
+    batched, mixed precision tol 1e-6: the bench workload."""
+    n = 256
+    E, nu = ms.two_phase_grf(n, seed=3)
+    grid = fem.Grid((n, n, n))
+    with lib.Cell((n, n, n), precision=lib.MIXED, tol=1e-6) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+        assert info["status"] == "CELL_OK"
+        assert max(info["relres"]) <= 1e-6
+        rng = np.random.default_rng(7)
+        nodes = rng.choice(grid.n, 2000, replace=False)
+        for J in (0, 3):
+            u = c.displacement(J).ravel()
+            rg = c.residual(J)
+            ro = fem.residual_at_nodes(grid, E, nu, u, np.eye(6)[J], nodes)
+            rgs = np.stack([rg[k][nodes] for k in range(3)], axis=1)
+            # GPU residual = FP32 rounding of the FP64 residual of the returned
+            # solution; the oracle recomputes it node by node in FP64
+            scale = np.abs(rg).max()
+            assert np.abs(ro - rgs).max() <= 1e-6 * scale + 1e-12, J
+    check_bounds(C, E, nu, 3, 1e-8)
+    assert info["sym_gap"] < 1e-5
+    assert abs(info["hill_mandel_gap"]) < 1e-6
+    # classical bound: kappa <= 1667 with the geometric-mean reference -> <= 296
+    assert max(info["iters"]) <= 296
+    with lib.Cell((n, n, n), precision=lib.FP64, tol=1e-10) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        Cref, _ = c.effective_stiffness()
+    assert relerr(C, Cref) < 1e-6
+
+
+def test_lognormal128_gradient(lib):
+    """128^3 log-normal E (ell 6, seed 5), nu 0.3, J = C*_1111 + C*_2323:
+    adjoint gradient through the autograd function, Euler identity over all
+    voxels, sign, and central finite differences (step 1e-6) on random voxels."""
+    import torch
+    from paper_2004_05197_amd.autograd import effective_stiffness
+    n = 128
+    E, nu = ms.lognormal_field(n, seed=5)
+    Et = torch.tensor(E.ravel(), dtype=torch.float64, device="cuda", requires_grad=True)
+    nut = torch.tensor(nu.ravel(), dtype=torch.float64, device="cuda")
+    with lib.Cell((n, n, n), precision=lib.FP64, tol=1e-12) as c:
+        C = effective_stiffness(Et, nut, c)
+        J = C[0, 0] + C[3, 3]
+        J.backward()
+        g = Et.grad.cpu().numpy()
+        Jv = float(J)
+        # Euler: C* is 1-homogeneous in E at fixed nu
+        assert abs(float(np.dot(g, E.ravel())) - Jv) <= 1e-10 * Jv
+        assert g.min() >= 0.0
+        rng = np.random.default_rng(6)
+        vox = rng.choice(n ** 3, 8, replace=False)
+        step = 1e-6
+        eb = np.stack([np.eye(6)[0], np.eye(6)[3]])
+        for v in vox:
+            vals = []
+            for sgn in (1.0, -1.0):
+                Ep = E.ravel().copy()
+                Ep[v] += sgn * step
+                c.set_material(Ep, nu.ravel())
+                c.solve(eb)
+                Ce = c.energy_matrix(2)
+                vals.append(Ce[0, 0] + Ce[1, 1])
+            fd = (vals[0] - vals[1]) / (2 * step)
+            # J/n ~ 1e-6 J: the FP64 difference keeps ~3-4 digits
+            assert abs(fd - g[v]) <= 2e-2 * abs(g[v]), (v, fd, g[v])
+
+
+def test_autograd_small_against_differences(lib):
+    """dL/dE of L = sum_IJ W_IJ C*_IJ through the autograd function, against
+    central differences of the forward on every voxel of a 4^3 cell, and
+    against the oracle's closed-form derivative."""
+    import torch
+    from paper_2004_05197_amd.autograd import EffectiveStiffness
+    shape = (4, 4, 4)
+    rng = np.random.default_rng(3)
+    E0 = rng.uniform(1, 5, 64)
+    nu0 = rng.uniform(0.1, 0.4, 64)
+    W = rng.standard_normal((6, 6))
+    E = torch.tensor(E0, dtype=torch.float64, requires_grad=True)
+    nu = torch.tensor(nu0, dtype=torch.float64)
+    with lib.Cell(shape, precision=lib.FP64, tol=1e-13) as c:
+        L = (EffectiveStiffness.apply(E, nu, c) * torch.tensor(W)).sum()
+        L.backward()
+        g = E.grad.numpy().copy()
+        step = 1e-5
+        fd = np.zeros(64)
+        for v in range(64):
+            vals = []
+            for sgn in (1.0, -1.0):
+                Ep = E0.copy()
+                Ep[v] += sgn * step
+                c.set_material(Ep, nu0)
+                C, _ = c.effective_stiffness()
+                vals.append(float((C * W).sum()))
+            fd[v] = (vals[0] - vals[1]) / (2 * step)
+    assert relerr(g, fd) < 1e-6
+    grid = fem.Grid(shape)
+    Cr, _, u = fem.effective_stiffness(grid, E0.reshape(grid.nshape), nu0.reshape(grid.nshape))
+    G = fem.dC_dE(grid, E0.reshape(grid.nshape), nu0.reshape(grid.nshape), u, fem.unit_loads(3))
+    assert relerr(g, np.einsum("ij,ijv->v", W, G)) < 1e-9
+
+
+def test_autograd_detects_interleaved_solve(lib):
+    import torch
+    from paper_2004_05197_amd.autograd import EffectiveStiffness
+    E = torch.full((64,), 2.0, dtype=torch.float64, requires_grad=True)
+    nu = torch.full((64,), 0.3, dtype=torch.float64)
+    E.data[::3] = 5.0
+    with lib.Cell((4, 4, 4), precision=lib.FP64) as c:
+        C = EffectiveStiffness.apply(E, nu, c)
+        c.effective_stiffness()
+        with pytest.raises(RuntimeError):
+            C.sum().backward()

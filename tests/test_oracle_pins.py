@@ -351,3 +351,18 @@ def test_generators():
     assert abs(g.mean()) < 1e-12 and abs(g.std() - 1) < 1e-12
     g2 = ms.gaussian_random_field((16, 16, 16), 3.0, seed=3)
     assert np.array_equal(g, g2)
+
+
+@pytest.mark.parametrize("shape", [(5, 4), (4, 3, 5)])
+def test_residual_at_nodes_matches_assembled(shape):
+    grid = fem.Grid(shape, lengths=[1.0 + 0.1 * a for a in range(len(shape))])
+    E, nu = rand_material(grid, 91)
+    rng = np.random.default_rng(92)
+    u = rng.standard_normal(grid.d * grid.n)
+    e = rng.standard_normal(grid.nv)
+    K = fem.assemble_K(grid, E, nu)
+    r = fem.assemble_rhs(grid, E, nu, e[None, :])[0] - K @ u
+    nodes = rng.choice(grid.n, 7, replace=False)
+    rl = fem.residual_at_nodes(grid, E, nu, u, e, nodes)
+    ref = np.stack([r[c * grid.n + nodes] for c in range(grid.d)], axis=1)
+    assert np.abs(rl - ref).max() < 1e-12 * np.abs(r).max()
