@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -144,6 +145,11 @@ def main():
     # ---------------------------------------------------------------- mixed
     cell = B.Cell((n1, n1, n1), precision=B.MIXED, tol=1e-6)
     cell.set_material(Ed, nud)
+    sched = cell.schedule
+    if not args.no_tune:
+        t_tune = time.perf_counter()
+        sched = cell.autotune()
+        progress(f"autotune: schedule {sched} in {time.perf_counter() - t_tune:.2f} s")
     for i in range(args.warmup):
         C_mixed, info = cell.effective_stiffness()
         progress(f"warmup {i}: iters {info['iters']} {info['seconds']:.2f} s")
@@ -249,6 +255,7 @@ def main():
             "loads": 6,
             "iters_per_step": per_step[-1]["iters"],
             "refinements_per_step": per_step[-1]["refinements"],
+            "schedule": list(sched),
         },
         "roofline": roofline,
         "iteration_byte_model_frac": round(all_bytes / (loop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

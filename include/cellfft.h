@@ -42,6 +42,7 @@ extern "C" {
 #endif
 
 typedef struct cell_s* cell_t;
+typedef struct cell_batch_s* cell_batch_t;
 
 typedef enum {
   CELL_OK = 0,
@@ -166,6 +167,69 @@ cell_status cell_profile(cell_t c, int enable);
 /* Accumulated milliseconds and launch counts per kernel kind
  * (CELL_NKERNEL entries each, host). */
 cell_status cell_profile_read(cell_t c, double* ms_out, long long* launches_out);
+
+/* ---- autotuner ------------------------------------------------------------
+ *
+ * A schedule picks the compiled variant of each iteration kernel; all
+ * variants compute the same operator (sums inside a block may be ordered
+ * differently).  Six ints: stencil tile (0..4: fp32 64x4, 32x8, 16x16,
+ * 64x8, 32x16; fp64 32x8, 16x16, 64x4, 32x16, 16x32 threads; a tile that
+ * does not divide the grid falls back to the first one that does, or to the
+ * runtime tile), stencil z
+ * extent (8, 16, 32, 64), x-pass rows per block (0: 2048/(N_x/2) complex
+ * values, 1: half; fp64 half of these), y-pass columns per block (0: 16,
+ * 1: 8; fp64 8, 4), last-pass columns per block (0: 8, 1: 4; fp64 4, 2),
+ * last-pass radix order (0: radix 8 first, 1: radix 4 first).  Default
+ * {0, 32, 0, 0, 0, 0}.
+ *
+ * cell_autotune times every variant on the handle's own buffers (material
+ * must be set; the last solve is discarded) and keeps the fastest.  If the
+ * environment variable CELLFFT_TUNE_CACHE names a file, schedules are
+ * cached there (JSON object: key "arch|dim|grid|precision|slots" -> six
+ * ints); force = 0 takes a cached schedule when one exists, and handles
+ * created later with a cached key start from it. */
+cell_status cell_autotune(cell_t c, int force);
+cell_status cell_get_schedule(cell_t c, int* sched_out /* [6] */);
+/* CELL_E_ARG for values outside the ranges above. */
+cell_status cell_set_schedule(cell_t c, const int* sched /* [6] */);
+
+/* ---- batches of independent cells ---------------------------------------
+ *
+ * ncell independent cells (microstructures), possibly of different grid
+ * sizes, each solved for the same macro strains.  Cells of the same grid
+ * (n and len) share one set of kernel launches: with lpc = max_loads slots
+ * per cell, a launch covers ncell_g * lpc independent load cases, each with
+ * its own material, reference medium and CG scalars.  Groups of different
+ * grids advance in lockstep on one stream, each group replaying a captured
+ * HIP graph of a chunk of iterations.  Results equal those of one
+ * single-cell handle per cell (the same kernels on the same data). */
+
+/* cfgs[ncell]: per-cell configurations; dim, precision, tol, max_iter,
+ * max_loads, stream and device must agree (else CELL_E_ARG). */
+cell_status cell_batch_create(const cell_config* cfgs, int ncell, cell_batch_t* out);
+
+/* Material of cell i (0 <= i < ncell), as cell_set_material. */
+cell_status cell_batch_set_material(cell_batch_t b, int i, const double* E, const double* nu, int on_device);
+
+/* Solve every cell for macro_strain[nload][nv]; mean_stress_out (host, may
+ * be NULL) receives [ncell][nload][nv]; infos (may be NULL) [ncell]. */
+cell_status cell_batch_solve(cell_batch_t b, int nload, const double* macro_strain, double* mean_stress_out,
+                             cell_info* infos);
+
+/* C* of every cell, C_out host [ncell][nv][nv]; infos (may be NULL) [ncell]. */
+cell_status cell_batch_effective_stiffness(cell_batch_t b, double* C_out, cell_info* infos);
+
+/* Per-kernel timing summed over the batch's groups (as cell_profile). */
+cell_status cell_batch_profile(cell_batch_t b, int enable);
+cell_status cell_batch_profile_read(cell_batch_t b, double* ms_out, long long* launches_out);
+
+/* Number of distinct grids (kernel-launch groups) in the batch. */
+int cell_batch_groups(cell_batch_t b);
+
+/* cell_autotune for every group of the batch. */
+cell_status cell_batch_autotune(cell_batch_t b, int force);
+
+void cell_batch_destroy(cell_batch_t b);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,18 @@ _SIGS = {
     "cell_get_residual": (ct.c_int, [_P, ct.c_int, _P, ct.c_int]),
     "cell_profile": (ct.c_int, [_P, ct.c_int]),
     "cell_profile_read": (ct.c_int, [_P, _P, _P]),
+    "cell_batch_create": (ct.c_int, [ct.POINTER(CellConfig), ct.c_int, ct.POINTER(_P)]),
+    "cell_batch_set_material": (ct.c_int, [_P, ct.c_int, _P, _P, ct.c_int]),
+    "cell_batch_solve": (ct.c_int, [_P, ct.c_int, _P, _P, _P]),
+    "cell_batch_effective_stiffness": (ct.c_int, [_P, _P, _P]),
+    "cell_batch_profile": (ct.c_int, [_P, ct.c_int]),
+    "cell_batch_profile_read": (ct.c_int, [_P, _P, _P]),
+    "cell_batch_groups": (ct.c_int, [_P]),
+    "cell_batch_destroy": (None, [_P]),
+    "cell_batch_autotune": (ct.c_int, [_P, ct.c_int]),
+    "cell_autotune": (ct.c_int, [_P, ct.c_int]),
+    "cell_get_schedule": (ct.c_int, [_P, _P]),
+    "cell_set_schedule": (ct.c_int, [_P, _P]),
 }
 
 KERNEL_KINDS = ["k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv", "residual", "merge", "homog"]
@@ -126,6 +138,23 @@ def _in_ptr(x, count):
     return a.ctypes.data_as(ct.c_void_p), 0, a
 
 
+def _config(shape, precision, tol, max_iter, max_loads, lengths, stream, device):
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    cfg = CellConfig()
+    cfg.dim = dim
+    for a in range(3):
+        cfg.n[a] = shape[a] if a < dim else 1
+        cfg.len[a] = (lengths[a] if lengths is not None and a < dim else 0.0)
+    cfg.precision = int(precision)
+    cfg.tol = float(tol)
+    cfg.max_iter = int(max_iter)
+    cfg.max_loads = int(max_loads)
+    cfg.stream = None if stream is None else ct.c_void_p(getattr(stream, "cuda_stream", stream))
+    cfg.device = int(device)
+    return cfg
+
+
 class Cell:
     """One periodic cell grid on the GPU (wraps a ``cell_t`` handle)."""
 
@@ -133,17 +162,7 @@ class Cell:
                  lengths=None, stream=None, device=-1):
         shape = tuple(int(s) for s in shape)
         self.dim = len(shape)
-        cfg = CellConfig()
-        cfg.dim = self.dim
-        for a in range(3):
-            cfg.n[a] = shape[a] if a < self.dim else 1
-            cfg.len[a] = (lengths[a] if lengths is not None and a < self.dim else 0.0)
-        cfg.precision = int(precision)
-        cfg.tol = float(tol)
-        cfg.max_iter = int(max_iter)
-        cfg.max_loads = int(max_loads)
-        cfg.stream = None if stream is None else ct.c_void_p(getattr(stream, "cuda_stream", stream))
-        cfg.device = int(device)
+        cfg = _config(shape, precision, tol, max_iter, max_loads, lengths, stream, device)
         h = ct.c_void_p()
         _check(_lib.cell_create(ct.byref(cfg), ct.byref(h)))
         self._h = h
@@ -241,11 +260,102 @@ class Cell:
         _check(_lib.cell_profile_read(self._h, ms.ctypes.data_as(ct.c_void_p), cnt.ctypes.data_as(ct.c_void_p)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
 
+    def autotune(self, force=False):
+        _check(_lib.cell_autotune(self._h, int(bool(force))))
+        return self.schedule
+
+    @property
+    def schedule(self):
+        v = (ct.c_int * 6)()
+        _check(_lib.cell_get_schedule(self._h, v))
+        return tuple(v)
+
+    @schedule.setter
+    def schedule(self, sched):
+        v = (ct.c_int * 6)(*[int(x) for x in sched])
+        _check(_lib.cell_set_schedule(self._h, v))
+
     def reference_medium(self):
         lam = ct.c_double()
         mu = ct.c_double()
         _check(_lib.cell_reference_medium(self._h, ct.byref(lam), ct.byref(mu)))
         return lam.value, mu.value
+
+
+class Batch:
+    """Independent cells, possibly of different grid sizes, solved together
+    (wraps a ``cell_batch_t`` handle): cells of one grid share every kernel
+    launch, and the grids advance in lockstep on one stream."""
+
+    def __init__(self, shapes, precision=FP64, tol=0.0, max_iter=0, max_loads=0,
+                 stream=None, device=-1):
+        shapes = [tuple(int(s) for s in sh) for sh in shapes]
+        if not shapes:
+            raise ValueError("a batch needs at least one cell")
+        self.dim = len(shapes[0])
+        cfgs = (CellConfig * len(shapes))()
+        for i, sh in enumerate(shapes):
+            cfgs[i] = _config(sh, precision, tol, max_iter, max_loads, None, stream, device)
+        h = ct.c_void_p()
+        _check(_lib.cell_batch_create(cfgs, len(shapes), ct.byref(h)))
+        self._h = h
+        self.shapes = shapes
+        self.ncell = len(shapes)
+        self.nv = 3 if self.dim == 2 else 6
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cell_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def groups(self):
+        return _lib.cell_batch_groups(self._h)
+
+    def autotune(self, force=False):
+        _check(_lib.cell_batch_autotune(self._h, int(bool(force))))
+
+    def set_material(self, i, E, nu):
+        n = int(np.prod(self.shapes[i]))
+        pe, de, ke = _in_ptr(E, n)
+        pn, dn, kn = _in_ptr(nu, n)
+        if de != dn:
+            raise ValueError("E and nu must both be on the host or both on the device")
+        _check(_lib.cell_batch_set_material(self._h, int(i), pe, pn, de))
+
+    def solve(self, macro_strains):
+        eb = np.ascontiguousarray(np.atleast_2d(np.asarray(macro_strains, dtype=np.float64)))
+        nl = eb.shape[0]
+        out = np.zeros((self.ncell, nl, self.nv))
+        infos = (CellInfo * self.ncell)()
+        st = _check(_lib.cell_batch_solve(self._h, nl, eb.ctypes.data_as(ct.c_void_p),
+                                          out.ctypes.data_as(ct.c_void_p), infos))
+        return out, [dict(i.as_dict(), status=STATUS_NAMES[st]) for i in infos]
+
+    def effective_stiffness(self):
+        C = np.zeros((self.ncell, self.nv, self.nv))
+        infos = (CellInfo * self.ncell)()
+        st = _check(_lib.cell_batch_effective_stiffness(self._h, C.ctypes.data_as(ct.c_void_p), infos))
+        return C, [dict(i.as_dict(), status=STATUS_NAMES[st]) for i in infos]
+
+    def profile(self, enable=True):
+        _check(_lib.cell_batch_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        ms = np.zeros(len(KERNEL_KINDS))
+        cnt = np.zeros(len(KERNEL_KINDS), dtype=np.int64)
+        _check(_lib.cell_batch_profile_read(self._h, ms.ctypes.data_as(ct.c_void_p),
+                                            cnt.ctypes.data_as(ct.c_void_p)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
 
 
 def exported_symbols():

@@ -153,9 +153,11 @@ template <typename T, bool INV> struct Dft<T, 8, INV> {
   }
 };
 
-// radix schedule: 8 first (except 16 = 4*4), then 4, 2, 3
-__host__ __device__ constexpr int pick_radix(int n) {
-  return (n % 8 == 0 && n != 16) ? 8 : (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : n;
+// radix schedules: RP = 0: 8 first (except 16 = 4*4), then 4, 2, 3;
+// RP = 1: 4 first, then 2, 3 (more, cheaper stages)
+__host__ __device__ constexpr int pick_radix(int n, int rp = 0) {
+  return rp == 0 ? ((n % 8 == 0 && n != 16) ? 8 : (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : n)
+                 : ((n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : n);
 }
 
 // Tile layouts.  ColMajorTile: element (n, c) at n*CS + c (columns fastest,
@@ -215,21 +217,22 @@ __device__ __forceinline__ void fft_stage(cpx<T>* buf, const cpx<T>* __restrict_
   __syncthreads();
 }
 
-template <typename T, int N, int REM, int NS, bool INV, int NCOL, int NT, int TWS, class L>
+template <typename T, int N, int REM, int NS, bool INV, int NCOL, int NT, int TWS, class L, int RP>
 __device__ __forceinline__ void fft_stages(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
   if constexpr (REM > 1) {
-    constexpr int R = pick_radix(REM);
+    constexpr int R = pick_radix(REM, RP);
     static_assert(REM % R == 0, "length must be 2^a 3^b");
     fft_stage<T, N, R, NS, INV, NCOL, NT, TWS, L>(buf, tw);
-    fft_stages<T, N, REM / R, NS * R, INV, NCOL, NT, TWS, L>(buf, tw);
+    fft_stages<T, N, REM / R, NS * R, INV, NCOL, NT, TWS, L, RP>(buf, tw);
   }
 }
 
 // In-place FFT (unnormalised; INV uses the +i sign) of NCOL columns of length
-// N held in LDS.  Must be called by all NT threads; ends with a barrier.
-template <typename T, int N, bool INV, int NCOL, int NT, int TWS, class L>
+// N held in LDS, radix schedule RP.  Must be called by all NT threads; ends
+// with a barrier.
+template <typename T, int N, bool INV, int NCOL, int NT, int TWS, class L, int RP = 0>
 __device__ __forceinline__ void fft_lds(cpx<T>* buf, const cpx<T>* __restrict__ tw) {
-  fft_stages<T, N, N, 1, INV, NCOL, NT, TWS, L>(buf, tw);
+  fft_stages<T, N, N, 1, INV, NCOL, NT, TWS, L, RP>(buf, tw);
 }
 
 }  // namespace cellfft

@@ -35,21 +35,23 @@ __device__ __forceinline__ bool load_live(const LoadState* st, bool allow_conver
 }
 
 // rows per block of the x passes: about 2048 (fp32) / 1024 (fp64) complex
-template <typename T, int M> constexpr int x_rpb() {
-  constexpr int tgt = sizeof(T) == 4 ? 2048 : 1024;
+// values, halved by schedule variant V = 1
+template <typename T, int M, int V> constexpr int x_rpb() {
+  constexpr int tgt = (sizeof(T) == 4 ? 2048 : 1024) >> V;
   return (tgt / M) < 1 ? 1 : (tgt / M);
 }
-template <typename T> constexpr int y_tx() { return sizeof(T) == 4 ? 16 : 8; }
-template <typename T> constexpr int z_tx() { return sizeof(T) == 4 ? 8 : 4; }
+// columns per block of the y pass and of the last pass (variant V halves them)
+template <typename T, int V> constexpr int y_tx() { return (sizeof(T) == 4 ? 16 : 8) >> V; }
+template <typename T, int V> constexpr int z_tx() { return (sizeof(T) == 4 ? 8 : 4) >> V; }
 // threads per block of the y and last passes (more waves per CU to hide
 // the load -> FFT -> store latency of each tile)
 constexpr int NTY = 512;
 constexpr int NTZ = 512;
 
 // ================================================================= x forward
-template <typename T, int M>
+template <typename T, int M, int V>
 __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
-  constexpr int RPB = x_rpb<T, M>();
+  constexpr int RPB = x_rpb<T, M, V>();
   constexpr int RS = M + 1;
   using T2 = typename V2<T>::type;
   __shared__ cpx<T> buf[RPB * RS];
@@ -114,9 +116,9 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
 }
 
 // ================================================================= x inverse
-template <typename T, int M>
+template <typename T, int M, int V>
 __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
-  constexpr int RPB = x_rpb<T, M>();
+  constexpr int RPB = x_rpb<T, M, V>();
   constexpr int RS = M + 1;
   using T2 = typename V2<T>::type;
   __shared__ cpx<T> buf[RPB * RS];
@@ -175,9 +177,9 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
 }
 
 // ================================================================= y pass 3D
-template <typename T, int N, bool INV>
+template <typename T, int N, bool INV, int V>
 __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
-  constexpr int TX = y_tx<T>();
+  constexpr int TX = y_tx<T, V>();
   __shared__ cpx<T> buf[N * TX];
   __shared__ cpx<T> tws[N];
   const int l = blockIdx.y;
@@ -362,16 +364,16 @@ __global__ __launch_bounds__(NT) void k_symtab(PArgs<T> a, T* tab, T* tabB) {
 }
 
 template <typename T>
-__device__ __forceinline__ void sym_solve2(const PArgs<T>& P, int kx, int ky,
+__device__ __forceinline__ void sym_solve2(const PArgs<T>& P, T lam0, T mu0, int kx, int ky,
                                            const cpx<T>* r, cpx<T>* z) {
   const T sx = P.trig[0][2 * kx], cx = P.trig[0][2 * kx + 1];
   const T sy = P.trig[1][2 * ky], cy = P.trig[1][2 * ky + 1];
   const T gx = T(2) * sx * P.ih[0], gy = T(2) * sy * P.ih[1];
   const T gx2 = gx * gx, gy2 = gy * gy, ss = gx2 + gy2;
   const T c2w = T(2) * P.w;
-  const T a00 = c2w * (P.lam0 * gx2 + P.mu0 * (ss + gx2));
-  const T a11 = c2w * (P.lam0 * gy2 + P.mu0 * (ss + gy2));
-  const T a01 = c2w * (P.lam0 + P.mu0) * gx * gy * (cx * cy - sx * sy);
+  const T a00 = c2w * (lam0 * gx2 + mu0 * (ss + gx2));
+  const T a11 = c2w * (lam0 * gy2 + mu0 * (ss + gy2));
+  const T a01 = c2w * (lam0 + mu0) * gx * gy * (cx * cy - sx * sy);
   const T det = a00 * a11 - a01 * a01;
   const T s = P.inv_n / det;
   z[0] = (r[0] * a11 - r[1] * a01) * s;
@@ -387,9 +389,9 @@ __device__ __forceinline__ T redot(const cpx<T>* r, const cpx<T>* z) {
 }
 
 // ===================================================== z pass (3D, last)
-template <typename T, int N>
+template <typename T, int N, int V, int RP>
 __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
-  constexpr int TX = z_tx<T>();
+  constexpr int TX = z_tx<T, V>();
   constexpr int NC = 3 * TX;  // columns: component-major, then slot
   __shared__ cpx<T> buf[N * NC];
   __shared__ cpx<T> tws[N];
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
     buf[e] = (s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
-  fft_lds<T, N, false, NC, NTZ, 1, ColTile<NC>>(buf, tws);
+  fft_lds<T, N, false, NC, NTZ, 1, ColTile<NC>, RP>(buf, tws);
   const bool pair_row = (s0 == 0) && (y == 0 || y == a.ny / 2);
   double acc = 0.0;
   // ordinary wavevectors (weight 2: each stands for itself and its conjugate)
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
     for (int c = 0; c < 3; ++c) r[c] = buf[kz * NC + c * TX + s];
     if (a.tab) {
       T m[6];
-      sym_load(a.tab, ((long long)y * a.nz + kz) * M + slot, m);
+      sym_load(a.tab + (long long)(l / a.lpc) * a.tab_stride, ((long long)y * a.nz + kz) * M + slot, m);
       sym_apply3(m, r, z);
     } else {
       const int kx = slot == 0 ? (y < a.ny / 2 ? 0 : M) : slot;
@@ -463,8 +465,8 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
         }
         if (a.tab) {
           T mA[6], mB[6];
-          sym_load(a.tab, ((long long)y * a.nz + kz) * M, mA);
-          sym_load(a.tabB, (long long)(y == 0 ? 0 : 1) * a.nz + kz, mB);
+          sym_load(a.tab + (long long)(l / a.lpc) * a.tab_stride, ((long long)y * a.nz + kz) * M, mA);
+          sym_load(a.tabB + (long long)(l / a.lpc) * a.tabB_stride, (long long)(y == 0 ? 0 : 1) * a.nz + kz, mB);
           sym_apply3(mA, A, zA);
           sym_apply3(mB, B, zB);
         } else {
@@ -492,7 +494,7 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
     }
   }
   __syncthreads();
-  fft_lds<T, N, true, NC, NTZ, 1, ColTile<NC>>(buf, tws);
+  fft_lds<T, N, true, NC, NTZ, 1, ColTile<NC>, RP>(buf, tws);
   for (int e = tid; e < N * NC; e += NTZ) {
     const int z = e / NC, rem = e - z * NC;
     const int c = rem / TX, s = rem - c * TX;
@@ -503,9 +505,9 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
 }
 
 // ===================================================== y pass (2D, last)
-template <typename T, int N>
+template <typename T, int N, int V>
 __global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
-  constexpr int TX = z_tx<T>();
+  constexpr int TX = z_tx<T, V>();
   constexpr int NC = 2 * TX;
   __shared__ cpx<T> buf[N * NC];
   __shared__ cpx<T> tws[N];
@@ -514,6 +516,9 @@ __global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
   if (!load_live(a.st + l, true)) return;
   const int M = a.nx / 2;
   const int s0 = blockIdx.x * TX;
+  // reference medium of the slot's cell
+  const T* md = a.med ? a.med + 2 * (l / a.lpc) : nullptr;
+  const T lam0 = md ? md[0] : a.lam0, mu0 = md ? md[1] : a.mu0;
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NTZ) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + s0;
@@ -533,7 +538,7 @@ __global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
     cpx<T> r[2], z[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) r[c] = buf[ky * NC + c * TX + s];
-    sym_solve2(a, slot, ky, r, z);
+    sym_solve2(a, lam0, mu0, slot, ky, r, z);
     acc += 2.0 * (double)redot<T, 2>(r, z);
 #pragma unroll
     for (int c = 0; c < 2; ++c) buf[ky * NC + c * TX + s] = z[c];
@@ -557,9 +562,9 @@ __global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
         if (ky == 0) {
           zA[0] = zA[1] = {T(0), T(0)};
         } else {
-          sym_solve2(a, 0, ky, A, zA);
+          sym_solve2(a, lam0, mu0, 0, ky, A, zA);
         }
-        sym_solve2(a, M, ky, B, zB);
+        sym_solve2(a, lam0, mu0, M, ky, B, zB);
         acc += (double)redot<T, 2>(A, zA) + (double)redot<T, 2>(B, zB);
 #pragma unroll
         for (int c = 0; c < 2; ++c) out[q][c] = {zA[c].re - zB[c].im, zA[c].im + zB[c].re};
@@ -590,7 +595,7 @@ __global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
 // One block per load: fixed-order sum of the per-block partials written by
 // the producing kernel, then the scalar update of that reduction.
 __global__ __launch_bounds__(NT) void k_finalize(RedBuf red, LoadState* st, double* res2, int slot,
-                                                 int nparts, int only_load) {
+                                                 int nparts, int only_load, const int* mask) {
   __shared__ double sh[NT / WAVE];
   const int l = blockIdx.x;
   LoadState* S = st + l;
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(NT) void k_finalize(RedBuf red, LoadState* st, doub
     case RED_PQ: live = S->state == ST_ACTIVE || S->state == ST_CONVERGED; break;
     case RED_RR: live = S->state == ST_ACTIVE; break;
     case RED_RZ: live = S->state == ST_ACTIVE || S->state == ST_CONVERGED; break;
-    default: live = only_load < 0 || only_load == l; break;
+    default: live = mask ? mask[l] != 0 : (only_load < 0 || only_load == l); break;
   }
   if (!live) return;
   if (slot == RED_PQ && S->state == ST_CONVERGED) {
@@ -647,13 +652,13 @@ __global__ __launch_bounds__(NT) void k_finalize(RedBuf red, LoadState* st, doub
 }
 
 hipError_t launch_finalize(const RedBuf& red, LoadState* st, double* res2, int slot, int nparts, int nload,
-                           int only_load, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(nload), dim3(NT), 0, s, red, st, res2, slot, nparts, only_load);
+                           int only_load, const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(nload), dim3(NT), 0, s, red, st, res2, slot, nparts, only_load, mask);
   return hipGetLastError();
 }
 
-int last_pass_blocks(int dim, int nx, int ny, bool fp64) {
-  const int TX = fp64 ? z_tx<double>() : z_tx<float>();
+int last_pass_blocks(int dim, int nx, int ny, bool fp64, const Sched& sc) {
+  const int TX = (fp64 ? 4 : 8) >> (sc.z_var ? 1 : 0);
   const int ntile = (nx / 2 + TX - 1) / TX;
   return dim == 3 ? ntile * ny : ntile;
 }
@@ -673,19 +678,29 @@ bool fft_size_ok(int n) {
   }
 }
 
-int xpass_blocks(int nx, int nrows, bool fp64) {
+int xpass_blocks(int nx, int nrows, bool fp64, const Sched& sc) {
   const int M = nx / 2;
-  const int tgt = fp64 ? 1024 : 2048;
+  const int tgt = (fp64 ? 1024 : 2048) >> (sc.x_var ? 1 : 0);
   const int rpb = (tgt / M) < 1 ? 1 : tgt / M;
   return (nrows + rpb - 1) / rpb;
 }
 
-template <typename T>
-hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, hipStream_t s) {
-  const int nb = xpass_blocks(nx, a.nrows, sizeof(T) == 8);
-  dim3 grid(nb, nload);
+template <typename T, int V>
+static hipError_t launch_xfwd_v(const XArgs<T>& a, int nx, dim3 grid, hipStream_t s) {
   switch (nx / 2) {
-#define C_(m) case m: hipLaunchKernelGGL((k_xfwd<T, m>), grid, dim3(NT), 0, s, a); break;
+#define C_(m) case m: hipLaunchKernelGGL((k_xfwd<T, m, V>), grid, dim3(NT), 0, s, a); break;
+    CELLFFT_MSIZES(C_)
+#undef C_
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int V>
+static hipError_t launch_xinv_v(const XArgs<T>& a, int nx, dim3 grid, hipStream_t s) {
+  switch (nx / 2) {
+#define C_(m) case m: hipLaunchKernelGGL((k_xinv<T, m, V>), grid, dim3(NT), 0, s, a); break;
     CELLFFT_MSIZES(C_)
 #undef C_
     default:
@@ -695,30 +710,28 @@ hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_xinv(const XArgs<T>& a, int nx, int nload, hipStream_t s) {
-  const int nb = xpass_blocks(nx, a.nrows, sizeof(T) == 8);
-  dim3 grid(nb, nload);
-  switch (nx / 2) {
-#define C_(m) case m: hipLaunchKernelGGL((k_xinv<T, m>), grid, dim3(NT), 0, s, a); break;
-    CELLFFT_MSIZES(C_)
-#undef C_
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, const Sched& sc, hipStream_t s) {
+  const dim3 grid(xpass_blocks(nx, a.nrows, sizeof(T) == 8, sc), nload);
+  return sc.x_var ? launch_xfwd_v<T, 1>(a, nx, grid, s) : launch_xfwd_v<T, 0>(a, nx, grid, s);
 }
 
 template <typename T>
-hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, hipStream_t s) {
-  constexpr int TX = y_tx<T>();
+hipError_t launch_xinv(const XArgs<T>& a, int nx, int nload, const Sched& sc, hipStream_t s) {
+  const dim3 grid(xpass_blocks(nx, a.nrows, sizeof(T) == 8, sc), nload);
+  return sc.x_var ? launch_xinv_v<T, 1>(a, nx, grid, s) : launch_xinv_v<T, 0>(a, nx, grid, s);
+}
+
+template <typename T, int V>
+static hipError_t launch_ypass_v(const YArgs<T>& a, bool inverse, int nload, hipStream_t s) {
+  constexpr int TX = y_tx<T, V>();
   const int M = a.nx / 2;
   const int ntile = (M + TX - 1) / TX;
   dim3 grid(ntile * a.nz * a.ncomp, nload);
   switch (a.ny) {
-#define C_(n)                                                                  \
-  case n:                                                                      \
-    if (inverse) hipLaunchKernelGGL((k_ypass<T, n, true>), grid, dim3(NTY), 0, s, a); \
-    else hipLaunchKernelGGL((k_ypass<T, n, false>), grid, dim3(NTY), 0, s, a);       \
+#define C_(n)                                                                     \
+  case n:                                                                         \
+    if (inverse) hipLaunchKernelGGL((k_ypass<T, n, true, V>), grid, dim3(NTY), 0, s, a); \
+    else hipLaunchKernelGGL((k_ypass<T, n, false, V>), grid, dim3(NTY), 0, s, a);       \
     break;
     CELLFFT_NSIZES(C_)
 #undef C_
@@ -729,30 +742,47 @@ hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, hipStream_t 
 }
 
 template <typename T>
-hipError_t launch_last(const PArgs<T>& a, int dim, int nload, hipStream_t s) {
-  constexpr int TX = z_tx<T>();
-  const int M = a.nx / 2;
-  const int ntile = (M + TX - 1) / TX;
-  if (dim == 3) {
-    dim3 grid(xcd_grid(ntile * a.ny * nload));
-    switch (a.nz) {
-#define C_(n) case n: hipLaunchKernelGGL((k_zpass<T, n>), grid, dim3(NTZ), 0, s, a); break;
-      CELLFFT_NSIZES(C_)
+hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, const Sched& sc, hipStream_t s) {
+  return sc.y_var ? launch_ypass_v<T, 1>(a, inverse, nload, s) : launch_ypass_v<T, 0>(a, inverse, nload, s);
+}
+
+template <typename T, int V, int RP>
+static hipError_t launch_zpass_v(const PArgs<T>& a, int nload, hipStream_t s) {
+  constexpr int TX = z_tx<T, V>();
+  const int ntile = (a.nx / 2 + TX - 1) / TX;
+  dim3 grid(xcd_grid(ntile * a.ny * nload));
+  switch (a.nz) {
+#define C_(n) case n: hipLaunchKernelGGL((k_zpass<T, n, V, RP>), grid, dim3(NTZ), 0, s, a); break;
+    CELLFFT_NSIZES(C_)
 #undef C_
-      default:
-        return hipErrorInvalidValue;
-    }
-  } else {
-    dim3 grid(ntile, nload);
-    switch (a.ny) {
-#define C_(n) case n: hipLaunchKernelGGL((k_ylast<T, n>), grid, dim3(NTZ), 0, s, a); break;
-      CELLFFT_NSIZES(C_)
-#undef C_
-      default:
-        return hipErrorInvalidValue;
-    }
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, int V>
+static hipError_t launch_ylast_v(const PArgs<T>& a, int nload, hipStream_t s) {
+  constexpr int TX = z_tx<T, V>();
+  const int ntile = (a.nx / 2 + TX - 1) / TX;
+  dim3 grid(ntile, nload);
+  switch (a.ny) {
+#define C_(n) case n: hipLaunchKernelGGL((k_ylast<T, n, V>), grid, dim3(NTZ), 0, s, a); break;
+    CELLFFT_NSIZES(C_)
+#undef C_
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_last(const PArgs<T>& a, int dim, int nload, const Sched& sc, hipStream_t s) {
+  if (dim == 3) {
+    if (sc.z_var) return sc.z_radix ? launch_zpass_v<T, 1, 1>(a, nload, s) : launch_zpass_v<T, 1, 0>(a, nload, s);
+    return sc.z_radix ? launch_zpass_v<T, 0, 1>(a, nload, s) : launch_zpass_v<T, 0, 0>(a, nload, s);
+  }
+  return sc.z_var ? launch_ylast_v<T, 1>(a, nload, s) : launch_ylast_v<T, 0>(a, nload, s);
 }
 
 template <typename T>
@@ -763,13 +793,13 @@ hipError_t launch_symtab(const PArgs<T>& a, T* tab, T* tabB, hipStream_t s) {
 
 template hipError_t launch_symtab<float>(const PArgs<float>&, float*, float*, hipStream_t);
 template hipError_t launch_symtab<double>(const PArgs<double>&, double*, double*, hipStream_t);
-template hipError_t launch_xfwd<float>(const XArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_xfwd<double>(const XArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_xinv<float>(const XArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_xinv<double>(const XArgs<double>&, int, int, hipStream_t);
-template hipError_t launch_ypass<float>(const YArgs<float>&, bool, int, hipStream_t);
-template hipError_t launch_ypass<double>(const YArgs<double>&, bool, int, hipStream_t);
-template hipError_t launch_last<float>(const PArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_last<double>(const PArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_xfwd<float>(const XArgs<float>&, int, int, const Sched&, hipStream_t);
+template hipError_t launch_xfwd<double>(const XArgs<double>&, int, int, const Sched&, hipStream_t);
+template hipError_t launch_xinv<float>(const XArgs<float>&, int, int, const Sched&, hipStream_t);
+template hipError_t launch_xinv<double>(const XArgs<double>&, int, int, const Sched&, hipStream_t);
+template hipError_t launch_ypass<float>(const YArgs<float>&, bool, int, const Sched&, hipStream_t);
+template hipError_t launch_ypass<double>(const YArgs<double>&, bool, int, const Sched&, hipStream_t);
+template hipError_t launch_last<float>(const PArgs<float>&, int, int, const Sched&, hipStream_t);
+template hipError_t launch_last<double>(const PArgs<double>&, int, int, const Sched&, hipStream_t);
 
 }  // namespace cellfft

@@ -25,6 +25,26 @@ struct RedBuf {
   }
 };
 
+// Launch schedule of an instance: which compiled variant of each kernel
+// runs.  Chosen by the autotuner (or left at the defaults); every variant
+// computes the same result up to the order of floating-point sums inside a
+// block, and the tests check each against the oracle.
+struct Sched {
+  int st_tile = 0;  // 3D stencil tile (BX x BY threads): fp32 {64x4, 32x8, 16x16,
+                    // 64x8, 32x16}, fp64 {32x8, 16x16, 64x4, 32x16, 16x32}; a tile
+                    // that does not divide the grid falls back to the first that
+                    // does, else to the runtime-tile kernel
+  int st_tz = 32;   // z extent of a stencil tile (8, 16, 32 or 64)
+  int x_var = 0;    // x passes: rows per block = 2048 / (nx/2) (0) or 1024 / (nx/2) (1)
+                    // complex values (fp64: 1024, 512)
+  int y_var = 0;    // y pass columns per block: 16 (0) or 8 (1) (fp64: 8, 4)
+  int z_var = 0;    // last pass columns per block: 8 (0) or 4 (1) (fp64: 4, 2)
+  int z_radix = 0;  // last pass radix order: radix 8 first (0) or radix 4 first (1)
+};
+constexpr int SCHED_NFIELD = 6;
+constexpr int ST_NTILE = 5;
+constexpr int ST_TZ_MIN = 8;
+
 struct Geom {
   int dim;
   int nx, ny, nz;      // nz = 1 in 2D
@@ -66,10 +86,15 @@ template <typename T> struct PArgs {
   T w;                  // simplex weight |s| = h_x h_y (h_z) / d!
   T ih[3];              // 1 / h_a
   T inv_n;              // 1 / (nx ny nz): folds the unnormalised inverse DFT
-  int nload;            // load cases in the launch
+  int nload;            // slots in the launch (cells x loads per cell)
+  int lpc;              // load slots per cell
+  long long tab_stride;  // symbol-table values per cell (tab, tabB)
+  long long tabB_stride;
   const T* tab;         // 3D: tabulated K_ref^{-1} / n per stored wavevector
                         // ([ny][nz][nx/2][6]: 00,11,22,01,02,12), or nullptr
   const T* tabB;        // 3D: second family of the two real-pair rows [2][nz][6]
+  const T* med;         // 2D: per-cell (lambda0, mu0) pairs [ncell][2]; nullptr =
+                        // every slot uses (lam0, mu0)
   LoadState* st;
   RedBuf red;
 };
@@ -82,10 +107,14 @@ template <typename T> struct KArgs {
   long long lstride;    // reals per load
   Geom g;
   double eps[6][6];     // macro strains per load, tensor order (00,11,22,12,02,01)
-  int nload;
+  int nload;            // slots in the launch (cells x loads per cell)
+  int lpc;              // load slots per cell: slot l belongs to cell l / lpc and
+                        // uses macro strain eps[l % lpc]
+  long long mat_stride; // material values (2 per voxel) per cell
   int mode;             // 0: out = K u, partial u.out ; 1: out = -B^T D (eps + B u), partial out.out
   LoadState* st;        // mode 0: per-load scalars (alpha = rz / pq)
-  int only_load;        // mode 1: >= 0 restricts to one load
+  int only_load;        // mode 1: >= 0 restricts to one slot
+  const int* mask;      // mode 1: if set, the slots with mask[l] != 0 (overrides only_load)
   double* res2;         // mode 1: per-load ||out||^2 (FP64)
   double* sparts;       // mode 1 (optional): per-block sums of |s| sigma over the
                         // block's own voxels, [load][6][maxblk] (tensor storage
@@ -102,7 +131,8 @@ struct HArgs {
   long long lstride;
   Geom g;
   double eps[6][6];
-  int nload;
+  int nload;            // solved loads per cell
+  int lpc;              // load slots per cell (slot of load j of cell c: c lpc + j)
   double a[6][6];       // gradient weights dJ/dC_IJ
   double* grad;         // per-voxel gradient output
   const void* r;        // residual fields f - K u [nload][d][n] (float or double)
@@ -113,26 +143,32 @@ struct HArgs {
   int nblk;
 };
 
-template <typename T> hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, hipStream_t s);
-template <typename T> hipError_t launch_xinv(const XArgs<T>& a, int nx, int nload, hipStream_t s);
-template <typename T> hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, hipStream_t s);
-template <typename T> hipError_t launch_last(const PArgs<T>& a, int dim, int nload, hipStream_t s);
+template <typename T> hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, const Sched& sc, hipStream_t s);
+template <typename T> hipError_t launch_xinv(const XArgs<T>& a, int nx, int nload, const Sched& sc, hipStream_t s);
+template <typename T>
+hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, const Sched& sc, hipStream_t s);
+template <typename T> hipError_t launch_last(const PArgs<T>& a, int dim, int nload, const Sched& sc, hipStream_t s);
 // fills a.tab / a.tabB (3D) from the closed-form symbol of the reference medium
 template <typename T> hipError_t launch_symtab(const PArgs<T>& a, T* tab, T* tabB, hipStream_t s);
-template <typename T> hipError_t launch_stencil(const KArgs<T>& a, hipStream_t s);
-hipError_t launch_residual_mixed(const KArgs<double>& a, float* out32, hipStream_t s);
-hipError_t launch_homog(const HArgs& a, hipStream_t s);
+template <typename T> hipError_t launch_stencil(const KArgs<T>& a, const Sched& sc, hipStream_t s);
+hipError_t launch_residual_mixed(const KArgs<double>& a, float* out32, const Sched& sc, hipStream_t s);
+hipError_t launch_homog(const HArgs& a, int ncell, hipStream_t s);
 hipError_t launch_grad(const HArgs& a, hipStream_t s);
 
 // fixed-order sum of per-block partials and the scalar update of `slot`
 // (one block per load)
 hipError_t launch_finalize(const RedBuf& red, LoadState* st, double* res2, int slot, int nparts, int nload,
-                           int only_load, hipStream_t s);
-int last_pass_blocks(int dim, int nx, int ny, bool fp64);
+                           int only_load, const int* mask, hipStream_t s);
+int last_pass_blocks(int dim, int nx, int ny, bool fp64, const Sched& sc);
 
-// blocks used by each kernel (for sizing the partials buffer)
-int xpass_blocks(int nx, int nrows, bool fp64);
-int stencil_blocks(const Geom& g);
+// blocks used by each kernel under a schedule (reduction parts), and the
+// most over every schedule (for sizing the partials buffers)
+int xpass_blocks(int nx, int nrows, bool fp64, const Sched& sc);
+int stencil_blocks(const Geom& g, const Sched& sc, bool fp64);
+int max_reduction_blocks(const Geom& g);
+// stencil tile variant t of a precision: (BX, BY), and whether it fits the grid
+void stencil_tile_dims(bool fp64, int t, int* bx, int* by);
+bool stencil_tile_fits(const Geom& g, bool fp64, int t);
 int homog_blocks(const Geom& g);
 bool fft_size_ok(int n);      // y/z length (and x length)
 

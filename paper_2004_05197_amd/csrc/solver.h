@@ -1,0 +1,162 @@
+// Solver instance shared by the single-cell and the batch C ABI.
+//
+// An instance owns one grid shape and ncell cells of that shape; every cell
+// has lpc load slots, so the kernels see nslot = ncell * lpc independent
+// "loads" (slot l = cell l / lpc, macro strain l % lpc).  A single-cell handle
+// is an instance with ncell = 1.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cellfft.h"
+#include "kernels.h"
+
+namespace cellfft {
+
+template <typename T> struct Fields {
+  T* x = nullptr;  // [nslot][d n] each
+  T* r = nullptr;
+  T* p = nullptr;
+  T* q = nullptr;
+  cpx<T>* S = nullptr;
+  cpx<T>* tw[3] = {nullptr, nullptr, nullptr};
+  T* trig[3] = {nullptr, nullptr, nullptr};
+  T* symtab = nullptr;   // 3D: [ncell][ny][nz][nx/2][6]
+  T* symtabB = nullptr;  // 3D: [ncell][2][nz][6]
+  T* med = nullptr;      // 2D: per-cell (lambda0, mu0) [ncell][2]
+  std::vector<T> med_h;  // host copy of med (source of its upload)
+  std::vector<double> sym_lam0, sym_mu0;  // reference medium of each cell's table
+  bool ready = false;
+};
+
+}  // namespace cellfft
+
+struct cell_s {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  cellfft::Geom g{};
+  int d = 3, nv = 6;
+  long long n = 0, lstride = 0;
+  int precision = CELL_FP64;
+  double tol = 1e-10;
+  int max_iter = 10000;
+  int lpc = 6;    // load slots per cell
+  int ncell = 1;  // cells of this grid
+  int nslot = 6;  // ncell * lpc
+  bool use_graphs = true;
+  cellfft::Sched sched{};  // kernel variants (autotuner)
+  bool tuned = false;
+  // material, per cell
+  double* mat64 = nullptr;  // [ncell][n][2] (lambda, mu)
+  float* mat32 = nullptr;
+  double* E64 = nullptr;    // [ncell][n]
+  std::vector<char> have_mat;
+  std::vector<double> lam0, mu0, maxmod;
+  cellfft::Fields<float> f32;
+  cellfft::Fields<double> f64;
+  double* x64 = nullptr;  // mixed precision FP64 solution [nslot][d n]
+  // scalars, reductions
+  cellfft::LoadState* st = nullptr;
+  cellfft::LoadState* st_h = nullptr;
+  double* parts = nullptr;
+  unsigned* cnt = nullptr;
+  int maxblk = 0;
+  double* res2 = nullptr;
+  double* res2_h = nullptr;
+  double* sparts = nullptr;
+  double* sbar = nullptr;  // [nslot][6]
+  int* mask = nullptr;     // [nslot] slots of a masked residual / merge launch
+  int* mask_h = nullptr;
+  double* hparts = nullptr;
+  double* hres = nullptr;
+  double* grad = nullptr;
+  double* scratch = nullptr;
+  int hblk = 0;
+  // last solve
+  int nload_solved = 0;
+  double eps_v[6][6] = {};
+  bool solved = false;
+  bool solved_unit = false;
+  std::vector<double> homog;  // [ncell][nval] from the last solve
+  // per-kernel event timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
+  int ev_used = 0;
+  double prof_ms[CELL_NKERNEL] = {};
+  long long prof_cnt[CELL_NKERNEL] = {};
+};
+
+struct cell_batch_s {
+  std::vector<cell_s*> cls;           // one instance per distinct grid configuration
+  std::vector<int> cls_of, idx_of;    // cell i -> (instance, index within it)
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int dev = 0;
+  int nv = 6;
+};
+
+namespace cellfft {
+
+cell_status fail(cell_status s, const std::string& m);
+const char* last_error_message();
+
+// instance lifecycle (ncell cells of one grid, all on one stream)
+cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t shared_stream, cell_s** out);
+void instance_destroy(cell_s* c);
+cell_status instance_set_material(cell_s* c, int cell, const double* E, const double* nu, int on_device);
+// solves nload macro strains (host [nload][nv]) for every cell; infos: ncell entries or nullptr;
+// afterwards c->homog holds [ncell][nload*nload + nload*nv]
+cell_status instance_solve(cell_s* c, int nload, const double* eps, cell_info* infos);
+// single steps on slot 0 of cell 0 (host vectors [d][n]); invalidate the last solve
+cell_status instance_apply_operator(cell_s* c, int precision, const double* u, double* q);
+cell_status instance_apply_precond(cell_s* c, int precision, const double* r, double* z);
+cell_status instance_profile(cell_s* c, int enable);
+cell_status instance_profile_read(cell_s* c, double* ms_out, long long* launches_out);
+// autotuner: schedule from the cache (unless force) or by timing the variants
+cell_status instance_autotune(cell_s* c, int force);
+void instance_get_schedule(cell_s* c, int* out);            // SCHED_NFIELD ints
+cell_status instance_set_schedule(cell_s* c, const int* in);
+
+// An in-flight solve of one instance.  Phases: solve_begin, then
+// { solve_launch; synchronise the instance's stream; solve_poll } until
+// done, then solve_end (statuses, homogenisation).  Several instances on one
+// stream can interleave their launches and share one synchronisation.
+struct SolveRun {
+  cell_s* c = nullptr;
+  int nload = 0;
+  cell_info* infos = nullptr;  // ncell entries or nullptr
+  std::vector<double> fn2, rr_ru;
+  std::vector<int> fin, nref, active;
+  hipGraphExec_t gexec = nullptr;  // CHUNK iterations, captured at the first launch
+  cell_status result = CELL_OK;
+  bool done = false;
+  SolveRun() = default;
+  SolveRun(const SolveRun&) = delete;
+  SolveRun& operator=(const SolveRun&) = delete;
+  ~SolveRun() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+  }
+};
+cell_status solve_begin(SolveRun& R, cell_s* c, int nload, const double* eps, cell_info* infos);
+cell_status solve_launch(SolveRun& R);
+cell_status solve_poll(SolveRun& R);
+cell_status solve_end(SolveRun& R);
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+double now_s();
+
+}  // namespace cellfft

@@ -1,0 +1,1266 @@
+// Solver instance: device state, the PCG loop, reliable updates and the
+// homogenisation, for ncell cells of one grid (see solver.h).
+//
+// One PCG iteration is the kernel sequence
+//   K-apply (q = K p)                 -> finalize (alpha = rz / pq)
+//   -> x forward pass (r -= alpha q, ||r||^2, FFT_x)       -> finalize (rr)
+//   -> y pass (FFT_y)                                       [3D]
+//   -> last pass (FFT, z_hat = K_ref^{-1} r_hat, r.z, inverse FFT) -> finalize (beta)
+//   -> y pass (inverse FFT_y)                               [3D]
+//   -> x inverse pass (inverse FFT_x, x += alpha p, p = z + beta p)
+// over all slots at once, with every scalar on the device.  The host reads
+// the per-slot states once per chunk of iterations; the chunk is captured
+// once per solve as a HIP graph and replayed.  Mixed precision: the bulk
+// runs in FP32 and the FP32 iterate is a correction to an FP64 solution;
+// whenever a slot's iterated residual has dropped by DELTA since its last
+// FP64 residual (or the iterated test passes), the correction is merged and
+// the residual recomputed in FP64 (reliable update), batched over slots.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+
+#include "solver.h"
+
+namespace cellfft {
+
+namespace {
+
+thread_local std::string g_err;
+
+#define HIPCHK(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(CELL_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define STCHK(call)          \
+  do {                       \
+    cell_status s_ = (call); \
+    if (s_ < 0) return s_;   \
+  } while (0)
+
+constexpr int CHUNK = 8;         // iterations between host polls
+constexpr double DELTA = 0.05;   // reliable-update trigger (residual reduction)
+constexpr int PROF_PAIRS = 256;  // event pairs before a forced collection
+
+// x64[slot] += x32[slot], x32[slot] = 0 for the masked slots
+__global__ void k_merge(double* x64, float* x32, long long len, const int* mask) {
+  const int l = blockIdx.y;
+  if (!mask[l]) return;
+  double* a = x64 + (long long)l * len;
+  float* b = x32 + (long long)l * len;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (long long)gridDim.x * blockDim.x) {
+    a[i] += (double)b[i];
+    b[i] = 0.0f;
+  }
+}
+
+}  // namespace
+
+cell_status fail(cell_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+const char* last_error_message() { return g_err.c_str(); }
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+namespace {
+
+RedBuf red_of(cell_s* c) { return RedBuf{c->parts, c->cnt, c->maxblk, c->nslot}; }
+
+template <typename T> Fields<T>& fields(cell_s* c);
+template <> Fields<float>& fields<float>(cell_s* c) { return c->f32; }
+template <> Fields<double>& fields<double>(cell_s* c) { return c->f64; }
+
+template <typename T> const T* mat_of(cell_s* c);
+template <> const float* mat_of<float>(cell_s* c) { return c->mat32; }
+template <> const double* mat_of<double>(cell_s* c) { return c->mat64; }
+
+// ------------------------------------------------------------- profiling
+// Adds the elapsed times of the recorded event pairs (all complete: called
+// after a stream synchronisation) and recycles the pool.
+cell_status prof_collect(cell_s* c) {
+  for (int i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    c->prof_ms[c->ev_kind[i]] += ms;
+    c->prof_cnt[c->ev_kind[i]] += 1;
+  }
+  c->ev_used = 0;
+  return CELL_OK;
+}
+
+// brackets one kernel launch with an event pair on the instance's stream
+struct ProfScope {
+  cell_s* c;
+  int slot = -1;
+  ProfScope(cell_s* c_, int kind) : c(c_) {
+    if (!c->prof) return;
+    if (c->ev_used == PROF_PAIRS) {
+      (void)hipStreamSynchronize(c->stream);
+      (void)prof_collect(c);
+    }
+    slot = c->ev_used++;
+    c->ev_kind[slot] = kind;
+    (void)hipEventRecord(c->ev[2 * slot], c->stream);
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+  }
+};
+
+// ------------------------------------------------------------- buffers
+template <typename T>
+cell_status ensure_fields(cell_s* c) {
+  Fields<T>& F = fields<T>(c);
+  if (F.ready) return CELL_OK;
+  const size_t bytes = sizeof(T) * (size_t)c->lstride * c->nslot;
+  T** bufs[4] = {&F.x, &F.r, &F.p, &F.q};
+  for (T** b : bufs) {
+    if (hipMalloc((void**)b, bytes) != hipSuccess) return fail(CELL_E_NOMEM, "device allocation of a field failed");
+    HIPCHK(hipMemset(*b, 0, bytes));
+  }
+  if (hipMalloc((void**)&F.S, bytes) != hipSuccess) return fail(CELL_E_NOMEM, "device allocation of the spectrum failed");
+  const int N[3] = {c->g.nx, c->g.ny, c->g.nz};
+  for (int a = 0; a < c->d; ++a) {
+    std::vector<cpx<T>> tw(N[a]);
+    std::vector<T> tr(2 * N[a]);
+    for (int m = 0; m < N[a]; ++m) {
+      const double ang = -2.0 * M_PI * (double)m / N[a];
+      tw[m] = cpx<T>{(T)std::cos(ang), (T)std::sin(ang)};
+    }
+    // (sin, cos) of theta = pi k / N, exactly mirrored: k -> N - k keeps the
+    // sine and flips the cosine, so the symbol is bitwise symmetric under
+    // wavevector negation
+    for (int k = 0; k <= N[a] / 2; ++k) {
+      double s = std::sin(M_PI * k / N[a]), co = std::cos(M_PI * k / N[a]);
+      if (2 * k == N[a]) {
+        s = 1.0;
+        co = 0.0;
+      }
+      tr[2 * k] = (T)s;
+      tr[2 * k + 1] = (T)co;
+      if (k > 0 && k < N[a] - k) {
+        tr[2 * (N[a] - k)] = (T)s;
+        tr[2 * (N[a] - k) + 1] = (T)(-co);
+      }
+    }
+    HIPCHK(hipMalloc((void**)&F.tw[a], sizeof(cpx<T>) * N[a]));
+    HIPCHK(hipMalloc((void**)&F.trig[a], sizeof(T) * 2 * N[a]));
+    HIPCHK(hipMemcpy(F.tw[a], tw.data(), sizeof(cpx<T>) * N[a], hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(F.trig[a], tr.data(), sizeof(T) * 2 * N[a], hipMemcpyHostToDevice));
+  }
+  if (c->d == 2) {  // unused third axis: a one-entry table keeps kernel args valid
+    HIPCHK(hipMalloc((void**)&F.trig[2], sizeof(T) * 2));
+    T z2[2] = {T(0), T(1)};
+    HIPCHK(hipMemcpy(F.trig[2], z2, sizeof(T) * 2, hipMemcpyHostToDevice));
+  }
+  F.sym_lam0.assign(c->ncell, -1.0);
+  F.sym_mu0.assign(c->ncell, -1.0);
+  F.ready = true;
+  return CELL_OK;
+}
+
+template <typename T> void free_fields(Fields<T>& F) {
+  auto fr = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  fr(F.x);
+  fr(F.r);
+  fr(F.p);
+  fr(F.q);
+  fr(F.S);
+  fr(F.symtab);
+  fr(F.symtabB);
+  fr(F.med);
+  for (int a = 0; a < 3; ++a) {
+    fr(F.tw[a]);
+    fr(F.trig[a]);
+  }
+  F = Fields<T>();
+}
+
+void voigt_to_tensor(int d, const double* v, double* t) {
+  for (int i = 0; i < 6; ++i) t[i] = 0.0;
+  if (d == 3) {
+    t[0] = v[0];
+    t[1] = v[1];
+    t[2] = v[2];
+    t[3] = 0.5 * v[3];
+    t[4] = 0.5 * v[4];
+    t[5] = 0.5 * v[5];
+  } else {
+    t[0] = v[0];
+    t[1] = v[1];
+    t[5] = 0.5 * v[2];
+  }
+}
+
+template <typename T>
+KArgs<T> kargs(cell_s* c, int mode, const T* u, void* out, const T* mat) {
+  KArgs<T> a{};
+  a.u = u;
+  a.out = out;
+  a.mat = mat;
+  a.lstride = c->lstride;
+  a.g = c->g;
+  for (int l = 0; l < 6; ++l) voigt_to_tensor(c->d, c->eps_v[l], a.eps[l]);
+  a.nload = c->nslot;
+  a.lpc = c->lpc;
+  a.mat_stride = 2 * c->n;
+  a.mode = mode;
+  a.st = c->st;
+  a.only_load = -1;
+  a.mask = nullptr;
+  a.res2 = c->res2;
+  a.sparts = nullptr;
+  a.sbar = nullptr;
+  a.red = red_of(c);
+  return a;
+}
+
+// last-pass arguments for the reference medium of cell 0 (the symbol
+// table carries the per-cell media)
+template <typename T>
+PArgs<T> make_pargs(cell_s* c, int cell) {
+  Fields<T>& F = fields<T>(c);
+  PArgs<T> pa{};
+  pa.S = F.S;
+  pa.lstrideC = c->lstride / 2;
+  pa.nx = c->g.nx;
+  pa.ny = c->g.ny;
+  pa.nz = c->g.nz;
+  pa.tw = F.tw[c->d - 1];
+  for (int a = 0; a < 3; ++a) pa.trig[a] = F.trig[a];
+  pa.lam0 = (T)c->lam0[cell];
+  pa.mu0 = (T)c->mu0[cell];
+  pa.w = (T)(c->d == 3 ? c->g.h[0] * c->g.h[1] * c->g.h[2] / 6.0 : c->g.h[0] * c->g.h[1] / 2.0);
+  for (int a = 0; a < 3; ++a) pa.ih[a] = (T)(1.0 / c->g.h[a]);
+  pa.inv_n = (T)(1.0 / (double)c->n);
+  pa.nload = c->nslot;
+  pa.lpc = c->lpc;
+  pa.tab = nullptr;
+  pa.tabB = nullptr;
+  pa.tab_stride = 0;
+  pa.tabB_stride = 0;
+  pa.med = nullptr;
+  pa.st = c->st;
+  pa.red = red_of(c);
+  return pa;
+}
+
+// 3D: (re)builds each cell's tabulated inverse symbol when its reference
+// medium changed; 2D: uploads the per-cell media.  Points pa at the tables.
+template <typename T>
+cell_status ensure_symtab(cell_s* c, PArgs<T>& pa) {
+  Fields<T>& F = fields<T>(c);
+  if (c->d == 2) {
+    bool changed = !F.med;
+    if (!F.med) {
+      if (hipMalloc((void**)&F.med, sizeof(T) * 2 * c->ncell) != hipSuccess)
+        return fail(CELL_E_NOMEM, "device allocation of the reference media failed");
+      F.med_h.assign(2 * c->ncell, T(0));
+    }
+    for (int cell = 0; cell < c->ncell; ++cell)
+      if (F.sym_lam0[cell] != c->lam0[cell] || F.sym_mu0[cell] != c->mu0[cell]) {
+        F.med_h[2 * cell] = (T)c->lam0[cell];
+        F.med_h[2 * cell + 1] = (T)c->mu0[cell];
+        F.sym_lam0[cell] = c->lam0[cell];
+        F.sym_mu0[cell] = c->mu0[cell];
+        changed = true;
+      }
+    if (changed)
+      HIPCHK(hipMemcpyAsync(F.med, F.med_h.data(), sizeof(T) * 2 * c->ncell, hipMemcpyHostToDevice, c->stream));
+    pa.med = F.med;
+    return CELL_OK;
+  }
+  const long long entries = (long long)c->g.ny * c->g.nz * (c->g.nx / 2);
+  const long long stride = 6 * entries, strideB = 6 * 2 * (long long)c->g.nz;
+  if (!F.symtab) {
+    if (hipMalloc((void**)&F.symtab, sizeof(T) * stride * c->ncell) != hipSuccess ||
+        hipMalloc((void**)&F.symtabB, sizeof(T) * strideB * c->ncell) != hipSuccess)
+      return fail(CELL_E_NOMEM, "device allocation of the symbol table failed");
+  }
+  for (int cell = 0; cell < c->ncell; ++cell) {
+    if (!c->have_mat[cell]) continue;
+    if (F.sym_lam0[cell] != c->lam0[cell] || F.sym_mu0[cell] != c->mu0[cell]) {
+      PArgs<T> pc = make_pargs<T>(c, cell);
+      HIPCHK(launch_symtab<T>(pc, F.symtab + cell * stride, F.symtabB + cell * strideB, c->stream));
+      F.sym_lam0[cell] = c->lam0[cell];
+      F.sym_mu0[cell] = c->mu0[cell];
+    }
+  }
+  pa.tab = F.symtab;
+  pa.tabB = F.symtabB;
+  pa.tab_stride = stride;
+  pa.tabB_stride = strideB;
+  return CELL_OK;
+}
+
+// one PCG iteration over all slots (or the initial preconditioning if !kapply)
+template <typename T>
+cell_status iteration(cell_s* c, bool kapply) {
+  Fields<T>& F = fields<T>(c);
+  hipStream_t s = c->stream;
+  const int ns = c->nslot;
+  if (kapply) {
+    KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c));
+    ProfScope ps(c, CELL_K_APPLY);
+    HIPCHK(launch_stencil<T>(ka, c->sched, s));
+  }
+  XArgs<T> xa{};
+  xa.r = F.r;
+  xa.q = F.q;
+  xa.S = F.S;
+  xa.x = F.x;
+  xa.p = F.p;
+  xa.lstride = c->lstride;
+  xa.nrows = (int)(c->lstride / c->g.nx);
+  xa.tw = F.tw[0];
+  xa.st = c->st;
+  xa.red = red_of(c);
+  {
+    ProfScope ps(c, CELL_K_XFWD);
+    HIPCHK(launch_xfwd<T>(xa, c->g.nx, ns, c->sched, s));
+  }
+  HIPCHK(launch_finalize(xa.red, c->st, c->res2, RED_RR, xpass_blocks(c->g.nx, xa.nrows, sizeof(T) == 8, c->sched),
+                         ns, -1, nullptr, s));
+  YArgs<T> ya{};
+  ya.S = F.S;
+  ya.lstrideC = c->lstride / 2;
+  ya.nx = c->g.nx;
+  ya.ny = c->g.ny;
+  ya.nz = c->g.nz;
+  ya.ncomp = c->d;
+  ya.tw = F.tw[1];
+  ya.st = c->st;
+  PArgs<T> pa = make_pargs<T>(c, 0);
+  STCHK(ensure_symtab<T>(c, pa));
+  if (c->d == 3) {
+    ProfScope ps(c, CELL_K_YFWD);
+    HIPCHK(launch_ypass<T>(ya, false, ns, c->sched, s));
+  }
+  {
+    ProfScope ps(c, CELL_K_LAST);
+    HIPCHK(launch_last<T>(pa, c->d, ns, c->sched, s));
+  }
+  HIPCHK(launch_finalize(pa.red, c->st, c->res2, RED_RZ,
+                         last_pass_blocks(c->d, c->g.nx, c->g.ny, sizeof(T) == 8, c->sched), ns, -1, nullptr, s));
+  if (c->d == 3) {
+    ProfScope ps(c, CELL_K_YINV);
+    HIPCHK(launch_ypass<T>(ya, true, ns, c->sched, s));
+  }
+  {
+    ProfScope ps(c, CELL_K_XINV);
+    HIPCHK(launch_xinv<T>(xa, c->g.nx, ns, c->sched, s));
+  }
+  return CELL_OK;
+}
+
+// r = f - K u in FP64 for the masked slots (mask == nullptr: all); the
+// launch also sums |s| sigma per slot (mean stresses); ||r||^2 -> res2_h
+template <typename T>
+cell_status residual(cell_s* c, const double* u, const int* mask) {
+  Fields<T>& F = fields<T>(c);
+  KArgs<double> ka = kargs<double>(c, 1, u, nullptr, c->mat64);
+  ka.mask = mask;
+  ka.sparts = c->sparts;
+  ka.sbar = c->sbar;
+  {
+    ProfScope ps(c, CELL_K_RESIDUAL);
+    if (sizeof(T) == 4) {
+      HIPCHK(launch_residual_mixed(ka, reinterpret_cast<float*>(F.r), c->sched, c->stream));
+    } else {
+      ka.out = F.r;
+      HIPCHK(launch_stencil<double>(ka, c->sched, c->stream));
+    }
+  }
+  HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * c->nslot, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CELL_OK;
+}
+
+template <typename T>
+cell_status begin_t(SolveRun& R) {
+  cell_s* c = R.c;
+  STCHK(ensure_fields<T>(c));
+  Fields<T>& F = fields<T>(c);
+  hipStream_t s = c->stream;
+  const int ns = c->nslot;
+  const size_t fb = sizeof(T) * (size_t)c->lstride * ns;
+  HIPCHK(hipMemsetAsync(F.x, 0, fb, s));
+  HIPCHK(hipMemsetAsync(F.p, 0, fb, s));
+  HIPCHK(hipMemsetAsync(F.q, 0, fb, s));
+  if (c->precision == CELL_MIXED) HIPCHK(hipMemsetAsync(c->x64, 0, sizeof(double) * (size_t)c->lstride * ns, s));
+  // load vectors f = -B^T D eps_bar and ||f||^2 for every slot
+  STCHK(residual<T>(c, nullptr, nullptr));
+  R.fn2.assign(ns, 0.0);
+  R.rr_ru.assign(ns, 0.0);
+  R.fin.assign(ns, 1);
+  R.nref.assign(ns, 0);
+  R.active.assign(ns, 0);
+  double emax = 0.0;
+  for (int l = 0; l < R.nload; ++l)
+    for (int i = 0; i < c->nv; ++i) emax = std::max(emax, std::fabs(c->eps_v[l][i]));
+  const double hmin = std::min(c->g.h[0], std::min(c->g.h[1], c->d == 3 ? c->g.h[2] : c->g.h[1]));
+  const double wvol = c->d == 3 ? c->g.h[0] * c->g.h[1] * c->g.h[2] : c->g.h[0] * c->g.h[1];
+  R.done = true;
+  for (int l = 0; l < ns; ++l) {
+    LoadState& S = c->st_h[l];
+    std::memset(&S, 0, sizeof(S));
+    S.state = ST_IDLE;
+    S.maxit = c->max_iter;
+    S.first = 1;
+    const int cell = l / c->lpc, j = l % c->lpc;
+    if (j >= R.nload) continue;
+    R.active[l] = 1;
+    R.fn2[l] = c->res2_h[l];
+    R.rr_ru[l] = R.fn2[l];
+    S.rr = R.fn2[l];
+    S.thr = c->tol * c->tol * R.fn2[l];
+    // scale of the load vector without cancellation (homogeneous-cell test)
+    const double fscale = std::sqrt((double)c->n) * wvol * c->maxmod[cell] * emax / hmin;
+    if (std::sqrt(R.fn2[l]) <= 1e-13 * fscale) {  // homogeneous: f = 0 up to round-off, u = 0
+      S.state = ST_DONE;
+    } else {
+      S.state = ST_ACTIVE;
+      R.fin[l] = 0;
+      R.done = false;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * ns, hipMemcpyHostToDevice, s));
+  STCHK(iteration<T>(c, false));
+  return CELL_OK;
+}
+
+// queues CHUNK iterations and the copy of the slot states to the host
+template <typename T>
+cell_status launch_t(SolveRun& R) {
+  cell_s* c = R.c;
+  hipStream_t s = c->stream;
+  // per-launch event timing needs eager launches (events recorded inside a
+  // captured graph carry no timestamps)
+  if (!c->use_graphs || c->prof) {
+    for (int i = 0; i < CHUNK; ++i) STCHK(iteration<T>(c, true));
+  } else {
+    if (!R.gexec) {  // capture once per solve: the launch arguments are fixed for its duration
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      cell_status st = CELL_OK;
+      for (int i = 0; i < CHUNK && st >= 0; ++i) st = iteration<T>(c, true);
+      hipError_t e = hipStreamEndCapture(s, &graph);
+      if (st < 0) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (e != hipSuccess) return fail(CELL_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&R.gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        R.gexec = nullptr;
+        return fail(CELL_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+    }
+    HIPCHK(hipGraphLaunch(R.gexec, s));
+  }
+  HIPCHK(hipMemcpyAsync(c->st_h, c->st, sizeof(LoadState) * c->nslot, hipMemcpyDeviceToHost, s));
+  return CELL_OK;
+}
+
+// after the stream has drained: reliable updates (FP64 residual, plus the
+// merge of the FP32 correction in mixed precision) of the slots that need
+// one, batched in one masked launch; sets R.done when every slot is final
+template <typename T>
+cell_status poll_t(SolveRun& R) {
+  cell_s* c = R.c;
+  Fields<T>& F = fields<T>(c);
+  const bool mixed = sizeof(T) == 4;
+  hipStream_t s = c->stream;
+  const int ns = c->nslot;
+  if (c->prof) STCHK(prof_collect(c));
+  bool any = false;
+  for (int l = 0; l < ns; ++l) {
+    c->mask_h[l] = 0;
+    if (R.fin[l]) continue;
+    LoadState& S = c->st_h[l];
+    if (S.state == ST_BREAKDOWN) {
+      R.fin[l] = 1;
+      R.result = fail(CELL_E_BREAKDOWN, "CG breakdown in slot " + std::to_string(l));
+      continue;
+    }
+    // CONVERGED: the converging iteration has completed (its operator
+    // finalisation, which marks DONE, has not run yet)
+    const bool finished = S.state == ST_DONE || S.state == ST_CONVERGED;
+    if (finished || (mixed && S.state == ST_ACTIVE && S.rr < DELTA * DELTA * R.rr_ru[l])) {
+      c->mask_h[l] = 1;
+      any = true;
+    }
+  }
+  if (any) {
+    HIPCHK(hipMemcpyAsync(c->mask, c->mask_h, sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    const double* u64 = reinterpret_cast<const double*>(F.x);
+    if (mixed) {
+      ProfScope ps(c, CELL_K_MERGE);
+      hipLaunchKernelGGL(k_merge, dim3(256, ns), dim3(256), 0, s, c->x64, reinterpret_cast<float*>(F.x), c->lstride,
+                         (const int*)c->mask);
+      HIPCHK(hipGetLastError());
+      u64 = c->x64;
+    }
+    STCHK(residual<T>(c, u64, c->mask));
+    for (int l = 0; l < ns; ++l) {
+      if (!c->mask_h[l]) continue;
+      LoadState& S = c->st_h[l];
+      const bool finished = S.state == ST_DONE || S.state == ST_CONVERGED;
+      const double rt = c->res2_h[l];
+      R.rr_ru[l] = rt;
+      R.nref[l] += 1;
+      if (!(rt == rt)) {
+        R.fin[l] = 1;
+        S.state = ST_DONE;
+        R.result = fail(CELL_E_BREAKDOWN, "non-finite residual in slot " + std::to_string(l));
+        continue;
+      }
+      if (rt <= S.thr || (finished && S.maxit_hit) || S.iters >= c->max_iter) {
+        R.fin[l] = 1;
+        S.state = ST_DONE;
+      } else {
+        S.state = ST_ACTIVE;
+      }
+      S.rr = rt;
+    }
+    HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * ns, hipMemcpyHostToDevice, s));
+  }
+  R.done = true;
+  for (int l = 0; l < ns; ++l)
+    if (!R.fin[l]) R.done = false;
+  return CELL_OK;
+}
+
+cell_status end_t(SolveRun& R) {
+  cell_s* c = R.c;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->prof) STCHK(prof_collect(c));
+  if (R.gexec) {
+    (void)hipGraphExecDestroy(R.gexec);
+    R.gexec = nullptr;
+  }
+  bool all_conv = true;
+  for (int l = 0; l < c->nslot; ++l) {
+    if (!R.active[l]) continue;
+    const double rel = (R.fn2[l] > 0 && R.nref[l] > 0) ? std::sqrt(R.rr_ru[l] / R.fn2[l]) : 0.0;
+    if (R.infos) {
+      cell_info& I = R.infos[l / c->lpc];
+      const int j = l % c->lpc;
+      I.iters[j] = c->st_h[l].iters;
+      I.refinements[j] = R.nref[l];
+      I.relres[j] = rel;
+      I.nload = R.nload;
+    }
+    if (rel > c->tol) all_conv = false;
+  }
+  if (R.result < 0) return R.result;
+  return all_conv ? CELL_OK : CELL_NOT_CONVERGED;
+}
+
+// C* (energy form) and mean stresses of every cell from the final
+// residuals and stress sums left by the last FP64 residual of every slot
+cell_status homogenize(cell_s* c, int nload) {
+  HArgs h{};
+  h.u = c->precision == CELL_MIXED ? c->x64 : c->f64.x;
+  h.mat = c->mat64;
+  h.E = c->E64;
+  h.lstride = c->lstride;
+  h.g = c->g;
+  for (int l = 0; l < 6; ++l) voigt_to_tensor(c->d, c->eps_v[l], h.eps[l]);
+  h.nload = nload;
+  h.lpc = c->lpc;
+  if (c->precision == CELL_MIXED) {
+    h.r = c->f32.r;
+    h.r_fp64 = 0;
+  } else {
+    h.r = c->f64.r;
+    h.r_fp64 = 1;
+  }
+  h.sbar = c->sbar;
+  h.parts = c->hparts;
+  h.result = c->hres;
+  h.nblk = c->hblk;
+  {
+    ProfScope ps(c, CELL_K_HOMOG);
+    HIPCHK(launch_homog(h, c->ncell, c->stream));
+  }
+  const int nval = nload * nload + nload * c->nv;
+  c->homog.assign((size_t)nval * c->ncell, 0.0);
+  HIPCHK(hipMemcpyAsync(c->homog.data(), c->hres, sizeof(double) * nval * c->ncell, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->prof) STCHK(prof_collect(c));
+  return CELL_OK;
+}
+
+}  // namespace
+
+void apply_cached_schedule(cell_s* c);
+
+// =================================================================== instance
+void instance_destroy(cell_s* c) {
+  if (!c) return;
+  DevGuard dg(c->dev);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  auto fr = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  fr(c->mat64);
+  fr(c->mat32);
+  fr(c->E64);
+  free_fields(c->f32);
+  free_fields(c->f64);
+  fr(c->x64);
+  fr(c->st);
+  fr(c->parts);
+  fr(c->cnt);
+  fr(c->res2);
+  fr(c->sparts);
+  fr(c->sbar);
+  fr(c->mask);
+  fr(c->hparts);
+  fr(c->hres);
+  fr(c->grad);
+  fr(c->scratch);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->st_h) (void)hipHostFree(c->st_h);
+  if (c->res2_h) (void)hipHostFree(c->res2_h);
+  if (c->mask_h) (void)hipHostFree(c->mask_h);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t shared_stream, cell_s** out) {
+  if (!cfg || !out) return fail(CELL_E_ARG, "null argument");
+  *out = nullptr;
+  if (ncell < 1) return fail(CELL_E_ARG, "ncell must be positive");
+  if (cfg->dim != 2 && cfg->dim != 3) return fail(CELL_E_ARG, "dim must be 2 or 3");
+  for (int a = 0; a < cfg->dim; ++a) {
+    if (cfg->n[a] < 1) return fail(CELL_E_ARG, "grid sizes must be positive");
+    if (!fft_size_ok(cfg->n[a]))
+      return fail(CELL_E_UNSUPPORTED, "grid size " + std::to_string(cfg->n[a]) +
+                                          " has no FFT plan (supported: 4,6,8,12,16,24,32,48,64,96,128,192,256)");
+    if (!(cfg->len[a] >= 0.0) || !std::isfinite(cfg->len[a])) return fail(CELL_E_ARG, "invalid cell length");
+  }
+  if (cfg->precision != CELL_FP64 && cfg->precision != CELL_MIXED) return fail(CELL_E_ARG, "invalid precision");
+  if (cfg->tol < 0.0 || !std::isfinite(cfg->tol)) return fail(CELL_E_ARG, "invalid tolerance");
+  if (cfg->max_iter < 0) return fail(CELL_E_ARG, "invalid max_iter");
+  const int nv = cfg->dim == 3 ? 6 : 3;
+  if (cfg->max_loads < 0 || cfg->max_loads > nv) return fail(CELL_E_ARG, "max_loads must be in [0, nv]");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(CELL_E_DEVICE, "no HIP device");
+  int dev = cfg->device;
+  if (dev < 0) HIPCHK(hipGetDevice(&dev));
+  if (dev >= ndev) return fail(CELL_E_ARG, "device ordinal out of range");
+  DevGuard dg(dev);
+  cell_s* c = new cell_s();
+  c->dev = dev;
+  c->d = cfg->dim;
+  c->nv = nv;
+  c->g.dim = cfg->dim;
+  c->g.nx = cfg->n[0];
+  c->g.ny = cfg->n[1];
+  c->g.nz = cfg->dim == 3 ? cfg->n[2] : 1;
+  c->n = (long long)c->g.nx * c->g.ny * c->g.nz;
+  c->g.n = c->n;
+  for (int a = 0; a < 3; ++a) {
+    const double L = (a < cfg->dim && cfg->len[a] > 0.0) ? cfg->len[a] : 1.0;
+    const int N = a == 0 ? c->g.nx : a == 1 ? c->g.ny : c->g.nz;
+    c->g.h[a] = L / N;
+  }
+  c->lstride = (long long)c->d * c->n;
+  c->precision = cfg->precision;
+  c->tol = cfg->tol > 0.0 ? cfg->tol : (cfg->precision == CELL_MIXED ? 1e-6 : 1e-10);
+  c->max_iter = cfg->max_iter > 0 ? cfg->max_iter : 10000;
+  c->lpc = cfg->max_loads > 0 ? cfg->max_loads : nv;
+  c->ncell = ncell;
+  c->nslot = ncell * c->lpc;
+  const char* ge = std::getenv("CELLFFT_GRAPHS");
+  c->use_graphs = !(ge && ge[0] == '0');
+  c->have_mat.assign(ncell, 0);
+  c->lam0.assign(ncell, 0.0);
+  c->mu0.assign(ncell, 0.0);
+  c->maxmod.assign(ncell, 0.0);
+  auto bail = [&](cell_status s) {
+    instance_destroy(c);
+    return s;
+  };
+  if (shared_stream) {
+    c->stream = shared_stream;
+  } else if (cfg->stream) {
+    c->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) return bail(fail(CELL_E_DEVICE, "hipStreamCreate failed"));
+    c->own_stream = true;
+  }
+  // reduction buffers sized for the largest grid of any reducing kernel
+  // under any schedule
+  const int mb = max_reduction_blocks(c->g);
+  c->maxblk = mb;
+  const int ns = c->nslot;
+  auto dmalloc = [&](void** p, size_t bytes) -> bool { return hipMalloc(p, bytes) == hipSuccess; };
+  if (!dmalloc((void**)&c->parts, sizeof(double) * (size_t)RED_NSLOT * ns * mb) ||
+      !dmalloc((void**)&c->cnt, sizeof(unsigned) * RED_NSLOT * ns) ||
+      !dmalloc((void**)&c->st, sizeof(LoadState) * ns) || !dmalloc((void**)&c->res2, sizeof(double) * ns) ||
+      !dmalloc((void**)&c->sparts, sizeof(double) * 6 * (size_t)ns * mb) ||
+      !dmalloc((void**)&c->sbar, sizeof(double) * 6 * ns) || !dmalloc((void**)&c->mask, sizeof(int) * ns) ||
+      !dmalloc((void**)&c->mat64, sizeof(double) * 2 * c->n * ncell) ||
+      !dmalloc((void**)&c->mat32, sizeof(float) * 2 * c->n * ncell) ||
+      !dmalloc((void**)&c->E64, sizeof(double) * c->n * ncell) || !dmalloc((void**)&c->grad, sizeof(double) * c->n) ||
+      !dmalloc((void**)&c->scratch, sizeof(double) * 64 * 1024))
+    return bail(fail(CELL_E_NOMEM, "device allocation failed"));
+  c->hblk = homog_blocks(c->g);
+  const int nvalmax = c->lpc * c->lpc + c->lpc * nv;
+  if (!dmalloc((void**)&c->hparts, sizeof(double) * (size_t)c->lpc * c->lpc * c->hblk * ncell) ||
+      !dmalloc((void**)&c->hres, sizeof(double) * (size_t)nvalmax * ncell))
+    return bail(fail(CELL_E_NOMEM, "device allocation failed"));
+  if (c->precision == CELL_MIXED && !dmalloc((void**)&c->x64, sizeof(double) * (size_t)c->lstride * ns))
+    return bail(fail(CELL_E_NOMEM, "device allocation failed"));
+  if (hipHostMalloc((void**)&c->st_h, sizeof(LoadState) * ns) != hipSuccess ||
+      hipHostMalloc((void**)&c->res2_h, sizeof(double) * ns) != hipSuccess ||
+      hipHostMalloc((void**)&c->mask_h, sizeof(int) * ns) != hipSuccess)
+    return bail(fail(CELL_E_NOMEM, "pinned host allocation failed"));
+  if (hipMemset(c->cnt, 0, sizeof(unsigned) * RED_NSLOT * ns) != hipSuccess ||
+      hipMemset(c->st, 0, sizeof(LoadState) * ns) != hipSuccess ||
+      hipMemset(c->mask, 0, sizeof(int) * ns) != hipSuccess)
+    return bail(fail(CELL_E_DEVICE, "hipMemset failed"));
+  cell_status st = c->precision == CELL_MIXED ? ensure_fields<float>(c) : ensure_fields<double>(c);
+  if (st < 0) return bail(st);
+  apply_cached_schedule(c);
+  *out = c;
+  return CELL_OK;
+}
+
+cell_status instance_set_material(cell_s* c, int cell, const double* E, const double* nu, int on_device) {
+  if (!c || !E || !nu) return fail(CELL_E_ARG, "null argument");
+  if (cell < 0 || cell >= c->ncell) return fail(CELL_E_ARG, "cell index out of range");
+  DevGuard dg(c->dev);
+  const long long n = c->n;
+  std::vector<double> Eh(n), nh(n);
+  if (on_device) {
+    HIPCHK(hipMemcpyAsync(Eh.data(), E, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(nh.data(), nu, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } else {
+    std::memcpy(Eh.data(), E, sizeof(double) * n);
+    std::memcpy(nh.data(), nu, sizeof(double) * n);
+  }
+  std::vector<double> m64(2 * n);
+  std::vector<float> m32(2 * n);
+  double kmin = INFINITY, kmax = 0, mmin = INFINITY, mmax = 0, modmax = 0;
+  for (long long v = 0; v < n; ++v) {
+    const double e = Eh[v], p = nh[v];
+    if (!std::isfinite(e) || !(e > 0.0))
+      return fail(CELL_E_NONFINITE, "Young's modulus must be finite and positive (voxel " + std::to_string(v) + ")");
+    if (!std::isfinite(p) || !(p > -1.0) || !(p < 0.5))
+      return fail(CELL_E_ARG, "Poisson ratio must lie in (-1, 0.5) (voxel " + std::to_string(v) + ")");
+    const double lam = p * e / ((1.0 + p) * (1.0 - 2.0 * p));
+    const double mu = e / (2.0 * (1.0 + p));
+    m64[2 * v] = lam;
+    m64[2 * v + 1] = mu;
+    m32[2 * v] = (float)lam;
+    m32[2 * v + 1] = (float)mu;
+    const double bulk = lam + (c->d == 3 ? 2.0 * mu / 3.0 : mu);
+    kmin = std::min(kmin, bulk);
+    kmax = std::max(kmax, bulk);
+    mmin = std::min(mmin, mu);
+    mmax = std::max(mmax, mu);
+    modmax = std::max(modmax, std::fabs(lam) + 2.0 * mu);
+  }
+  const long long off = (long long)cell * n;
+  HIPCHK(hipMemcpyAsync(c->mat64 + 2 * off, m64.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->mat32 + 2 * off, m32.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->E64 + off, Eh.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double K0 = std::sqrt(kmin * kmax), mu0 = std::sqrt(mmin * mmax);
+  c->mu0[cell] = mu0;
+  c->lam0[cell] = K0 - (c->d == 3 ? 2.0 * mu0 / 3.0 : mu0);
+  c->maxmod[cell] = modmax;
+  c->have_mat[cell] = 1;
+  c->solved = false;
+  c->solved_unit = false;
+  return CELL_OK;
+}
+
+cell_status solve_begin(SolveRun& R, cell_s* c, int nload, const double* eps, cell_info* infos) {
+  for (int cell = 0; cell < c->ncell; ++cell)
+    if (!c->have_mat[cell]) return fail(CELL_E_STATE, "material not set for cell " + std::to_string(cell));
+  for (int l = 0; l < 6; ++l)
+    for (int i = 0; i < 6; ++i) c->eps_v[l][i] = (l < nload && i < c->nv) ? eps[l * c->nv + i] : 0.0;
+  c->solved = false;
+  c->solved_unit = false;
+  if (infos) std::memset(infos, 0, sizeof(cell_info) * c->ncell);
+  R.c = c;
+  R.nload = nload;
+  R.infos = infos;
+  R.result = CELL_OK;
+  return c->precision == CELL_MIXED ? begin_t<float>(R) : begin_t<double>(R);
+}
+
+cell_status solve_launch(SolveRun& R) {
+  return R.c->precision == CELL_MIXED ? launch_t<float>(R) : launch_t<double>(R);
+}
+
+cell_status solve_poll(SolveRun& R) {
+  return R.c->precision == CELL_MIXED ? poll_t<float>(R) : poll_t<double>(R);
+}
+
+cell_status solve_end(SolveRun& R) {
+  cell_s* c = R.c;
+  const cell_status st = end_t(R);
+  if (st < 0) return st;
+  STCHK(homogenize(c, R.nload));
+  c->solved = true;
+  c->nload_solved = R.nload;
+  return st;
+}
+
+cell_status instance_solve(cell_s* c, int nload, const double* eps, cell_info* infos) {
+  SolveRun R;
+  STCHK(solve_begin(R, c, nload, eps, infos));
+  while (!R.done) {
+    STCHK(solve_launch(R));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    STCHK(solve_poll(R));
+  }
+  return solve_end(R);
+}
+
+// ============================================ single-step entry points (tests)
+namespace {
+
+template <typename T>
+cell_status upload_field(cell_s* c, T* dst, const double* src) {
+  std::vector<T> h(c->lstride);
+  for (long long i = 0; i < c->lstride; ++i) h[i] = (T)src[i];
+  HIPCHK(hipMemcpyAsync(dst, h.data(), sizeof(T) * c->lstride, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CELL_OK;
+}
+
+template <typename T>
+cell_status download_field(cell_s* c, double* dst, const T* src) {
+  std::vector<T> h(c->lstride);
+  HIPCHK(hipMemcpyAsync(h.data(), src, sizeof(T) * c->lstride, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (long long i = 0; i < c->lstride; ++i) dst[i] = (double)h[i];
+  return CELL_OK;
+}
+
+// slot 0 active, the others idle
+void diag_state(cell_s* c) {
+  for (int l = 0; l < c->nslot; ++l) {
+    LoadState& S = c->st_h[l];
+    std::memset(&S, 0, sizeof(S));
+    S.state = l == 0 ? ST_ACTIVE : ST_IDLE;
+    S.thr = -1.0;
+    S.maxit = 1 << 30;
+    S.first = 1;
+  }
+}
+
+template <typename T>
+cell_status apply_operator_t(cell_s* c, const double* u, double* q) {
+  STCHK(ensure_fields<T>(c));
+  Fields<T>& F = fields<T>(c);
+  c->solved = c->solved_unit = false;
+  STCHK(upload_field<T>(c, F.p, u));
+  diag_state(c);
+  HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * c->nslot, hipMemcpyHostToDevice, c->stream));
+  for (int l = 0; l < 6; ++l)
+    for (int i = 0; i < 6; ++i) c->eps_v[l][i] = 0.0;
+  KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c));
+  HIPCHK(launch_stencil<T>(ka, c->sched, c->stream));
+  return download_field<T>(c, q, F.q);
+}
+
+template <typename T>
+cell_status apply_precond_t(cell_s* c, const double* r, double* z) {
+  STCHK(ensure_fields<T>(c));
+  Fields<T>& F = fields<T>(c);
+  c->solved = c->solved_unit = false;
+  STCHK(upload_field<T>(c, F.r, r));
+  HIPCHK(hipMemsetAsync(F.p, 0, sizeof(T) * c->lstride, c->stream));
+  HIPCHK(hipMemsetAsync(F.q, 0, sizeof(T) * c->lstride, c->stream));
+  diag_state(c);
+  HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * c->nslot, hipMemcpyHostToDevice, c->stream));
+  STCHK(iteration<T>(c, false));
+  return download_field<T>(c, z, F.p);
+}
+
+}  // namespace
+
+cell_status instance_apply_operator(cell_s* c, int precision, const double* u, double* q) {
+  if (precision == CELL_FP64) return apply_operator_t<double>(c, u, q);
+  if (precision == CELL_MIXED) return apply_operator_t<float>(c, u, q);
+  return fail(CELL_E_ARG, "invalid precision");
+}
+
+cell_status instance_apply_precond(cell_s* c, int precision, const double* r, double* z) {
+  if (precision == CELL_FP64) return apply_precond_t<double>(c, r, z);
+  if (precision == CELL_MIXED) return apply_precond_t<float>(c, r, z);
+  return fail(CELL_E_ARG, "invalid precision");
+}
+
+cell_status instance_profile(cell_s* c, int enable) {
+  DevGuard dg(c->dev);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * PROF_PAIRS);
+    c->ev_kind.resize(PROF_PAIRS);
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+  }
+  if (c->prof) STCHK(prof_collect(c));
+  c->prof = enable != 0;
+  for (int k = 0; k < CELL_NKERNEL; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_cnt[k] = 0;
+  }
+  return CELL_OK;
+}
+
+cell_status instance_profile_read(cell_s* c, double* ms_out, long long* launches_out) {
+  DevGuard dg(c->dev);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->prof) STCHK(prof_collect(c));
+  for (int k = 0; k < CELL_NKERNEL; ++k) {
+    ms_out[k] = c->prof_ms[k];
+    launches_out[k] = c->prof_cnt[k];
+  }
+  return CELL_OK;
+}
+
+// ================================================================= autotuner
+// Times the compiled variants of each iteration kernel on the instance's own
+// buffers (every slot active, scalars harmless) and keeps the fastest:
+// stencil tile and z extent, rows per block of the x passes, columns per
+// block of the y pass, columns per block and radix order of the last pass.
+// Results are cached per (device architecture, grid, precision, slot count)
+// in the JSON file named by CELLFFT_TUNE_CACHE (none: no cache).  The
+// fields touched are the ones every solve reinitialises.
+namespace {
+
+constexpr int TUNE_REPS = 5;
+
+std::string tune_key(cell_s* c) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, c->dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  }
+  return arch + "|" + std::to_string(c->d) + "d|" + std::to_string(c->g.nx) + "x" + std::to_string(c->g.ny) + "x" +
+         std::to_string(c->g.nz) + "|" + (c->precision == CELL_MIXED ? "f32" : "f64") + "|" +
+         std::to_string(c->nslot);
+}
+
+void sched_to_ints(const Sched& sc, int* v) {
+  v[0] = sc.st_tile;
+  v[1] = sc.st_tz;
+  v[2] = sc.x_var;
+  v[3] = sc.y_var;
+  v[4] = sc.z_var;
+  v[5] = sc.z_radix;
+}
+
+bool sched_from_ints(const int* v, Sched* sc) {
+  const bool ok = v[0] >= 0 && v[0] < ST_NTILE && (v[1] == 8 || v[1] == 16 || v[1] == 32 || v[1] == 64) &&
+                  (v[2] == 0 || v[2] == 1) && (v[3] == 0 || v[3] == 1) && (v[4] == 0 || v[4] == 1) &&
+                  (v[5] == 0 || v[5] == 1);
+  if (!ok) return false;
+  sc->st_tile = v[0];
+  sc->st_tz = v[1];
+  sc->x_var = v[2];
+  sc->y_var = v[3];
+  sc->z_var = v[4];
+  sc->z_radix = v[5];
+  return true;
+}
+
+// cache file: {"<key>": [tile, tz, x, y, z, radix], ...}, one entry per line
+std::map<std::string, std::vector<int>> cache_read(const char* path) {
+  std::map<std::string, std::vector<int>> out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    const char* q0 = std::strchr(line, '"');
+    if (!q0) continue;
+    const char* q1 = std::strchr(q0 + 1, '"');
+    if (!q1) continue;
+    const char* br = std::strchr(q1, '[');
+    if (!br) continue;
+    std::vector<int> v(SCHED_NFIELD);
+    if (std::sscanf(br, "[%d , %d , %d , %d , %d , %d]", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == SCHED_NFIELD)
+      out[std::string(q0 + 1, q1)] = v;
+  }
+  std::fclose(f);
+  return out;
+}
+
+bool cache_write(const char* path, const std::map<std::string, std::vector<int>>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : m) {
+    std::fprintf(f, "  \"%s\": [%d, %d, %d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second[0], kv.second[1],
+                 kv.second[2], kv.second[3], kv.second[4], kv.second[5], ++i < m.size() ? "," : "");
+  }
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+struct TuneTimer {
+  cell_s* c;
+  hipEvent_t ev[2 * TUNE_REPS] = {};
+  explicit TuneTimer(cell_s* c_) : c(c_) {}
+  ~TuneTimer() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  cell_status init() {
+    for (hipEvent_t& e : ev) HIPCHK(hipEventCreate(&e));
+    return CELL_OK;
+  }
+  // mean milliseconds of one launch sequence; the slot states are reset
+  // before every repetition (outside the timed pair)
+  template <typename F>
+  cell_status time(F&& launch, double* ms_out) {
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * c->nslot, hipMemcpyHostToDevice, s));
+    STCHK(launch());  // warm-up
+    for (int r = 0; r < TUNE_REPS; ++r) {
+      HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * c->nslot, hipMemcpyHostToDevice, s));
+      HIPCHK(hipEventRecord(ev[2 * r], s));
+      STCHK(launch());
+      HIPCHK(hipEventRecord(ev[2 * r + 1], s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    double tot = 0.0;
+    for (int r = 0; r < TUNE_REPS; ++r) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]));
+      tot += ms;
+    }
+    *ms_out = tot / TUNE_REPS;
+    return CELL_OK;
+  }
+};
+
+template <typename T>
+cell_status tune_t(cell_s* c) {
+  STCHK(ensure_fields<T>(c));
+  Fields<T>& F = fields<T>(c);
+  hipStream_t s = c->stream;
+  const int ns = c->nslot;
+  c->solved = c->solved_unit = false;
+  for (int l = 0; l < ns; ++l) {
+    LoadState& S = c->st_h[l];
+    std::memset(&S, 0, sizeof(S));
+    S.state = ST_ACTIVE;
+    S.rz = 1.0;
+    S.thr = -1.0;
+    S.maxit = 1 << 30;
+  }
+  // benign data: the fields start from zero
+  const size_t fb = sizeof(T) * (size_t)c->lstride * ns;
+  HIPCHK(hipMemsetAsync(F.x, 0, fb, s));
+  HIPCHK(hipMemsetAsync(F.r, 0, fb, s));
+  HIPCHK(hipMemsetAsync(F.p, 0, fb, s));
+  HIPCHK(hipMemsetAsync(F.q, 0, fb, s));
+  HIPCHK(hipMemsetAsync(F.S, 0, fb, s));
+  PArgs<T> pa = make_pargs<T>(c, 0);
+  STCHK(ensure_symtab<T>(c, pa));
+  XArgs<T> xa{};
+  xa.r = F.r;
+  xa.q = F.q;
+  xa.S = F.S;
+  xa.x = F.x;
+  xa.p = F.p;
+  xa.lstride = c->lstride;
+  xa.nrows = (int)(c->lstride / c->g.nx);
+  xa.tw = F.tw[0];
+  xa.st = c->st;
+  xa.red = red_of(c);
+  YArgs<T> ya{};
+  ya.S = F.S;
+  ya.lstrideC = c->lstride / 2;
+  ya.nx = c->g.nx;
+  ya.ny = c->g.ny;
+  ya.nz = c->g.nz;
+  ya.ncomp = c->d;
+  ya.tw = F.tw[1];
+  ya.st = c->st;
+  KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c));
+  TuneTimer tm(c);
+  STCHK(tm.init());
+  Sched best = c->sched;
+  const bool fp64 = sizeof(T) == 8;
+  double ms, bms;
+  // stencil: tiles that fit the grid (or the runtime tile) x z extents
+  bms = 1e300;
+  bool any_tile = false;
+  for (int t = 0; t < ST_NTILE; ++t) {
+    if (!stencil_tile_fits(c->g, fp64, t)) continue;
+    any_tile = true;
+    for (int tz = ST_TZ_MIN; tz <= 64; tz *= 2) {
+      if (tz > c->g.nz && tz > ST_TZ_MIN) continue;  // clamps to nz: already timed
+      Sched sc = best;
+      sc.st_tile = t;
+      sc.st_tz = tz;
+      STCHK(tm.time([&]() -> cell_status {
+        HIPCHK(launch_stencil<T>(ka, sc, s));
+        return CELL_OK;
+      }, &ms));
+      if (ms < bms) {
+        bms = ms;
+        best.st_tile = t;
+        best.st_tz = tz;
+      }
+    }
+  }
+  if (!any_tile && c->d == 3) {
+    for (int tz = ST_TZ_MIN; tz <= 64; tz *= 2) {
+      if (tz > c->g.nz && tz > ST_TZ_MIN) continue;  // clamps to nz: already timed
+      Sched sc = best;
+      sc.st_tz = tz;
+      STCHK(tm.time([&]() -> cell_status {
+        HIPCHK(launch_stencil<T>(ka, sc, s));
+        return CELL_OK;
+      }, &ms));
+      if (ms < bms) {
+        bms = ms;
+        best.st_tz = tz;
+      }
+    }
+  }
+  // x passes (forward and inverse together)
+  bms = 1e300;
+  for (int v = 0; v < 2; ++v) {
+    Sched sc = best;
+    sc.x_var = v;
+    STCHK(tm.time([&]() -> cell_status {
+      HIPCHK(launch_xfwd<T>(xa, c->g.nx, ns, sc, s));
+      HIPCHK(launch_xinv<T>(xa, c->g.nx, ns, sc, s));
+      return CELL_OK;
+    }, &ms));
+    if (ms < bms) {
+      bms = ms;
+      best.x_var = v;
+    }
+  }
+  // y pass (3D; forward and inverse)
+  if (c->d == 3) {
+    bms = 1e300;
+    for (int v = 0; v < 2; ++v) {
+      Sched sc = best;
+      sc.y_var = v;
+      STCHK(tm.time([&]() -> cell_status {
+        HIPCHK(launch_ypass<T>(ya, false, ns, sc, s));
+        HIPCHK(launch_ypass<T>(ya, true, ns, sc, s));
+        return CELL_OK;
+      }, &ms));
+      if (ms < bms) {
+        bms = ms;
+        best.y_var = v;
+      }
+    }
+  }
+  // last pass: columns per block x radix order
+  bms = 1e300;
+  for (int v = 0; v < 2; ++v)
+    for (int rp = 0; rp < (c->d == 3 ? 2 : 1); ++rp) {
+      Sched sc = best;
+      sc.z_var = v;
+      sc.z_radix = rp;
+      STCHK(tm.time([&]() -> cell_status {
+        HIPCHK(launch_last<T>(pa, c->d, ns, sc, s));
+        return CELL_OK;
+      }, &ms));
+      if (ms < bms) {
+        bms = ms;
+        best.z_var = v;
+        best.z_radix = rp;
+      }
+    }
+  c->sched = best;
+  return CELL_OK;
+}
+
+}  // namespace
+
+cell_status instance_autotune(cell_s* c, int force) {
+  for (int cell = 0; cell < c->ncell; ++cell)
+    if (!c->have_mat[cell]) return fail(CELL_E_STATE, "material not set for cell " + std::to_string(cell));
+  DevGuard dg(c->dev);
+  const char* path = std::getenv("CELLFFT_TUNE_CACHE");
+  const std::string key = tune_key(c);
+  std::map<std::string, std::vector<int>> cache;
+  if (path && *path) cache = cache_read(path);
+  if (!force) {
+    auto it = cache.find(key);
+    Sched sc;
+    if (it != cache.end() && sched_from_ints(it->second.data(), &sc)) {
+      c->sched = sc;
+      c->tuned = true;
+      return CELL_OK;
+    }
+  }
+  const bool prof = c->prof;
+  c->prof = false;
+  cell_status st = c->precision == CELL_MIXED ? tune_t<float>(c) : tune_t<double>(c);
+  c->prof = prof;
+  if (st < 0) return st;
+  c->tuned = true;
+  if (path && *path) {
+    std::vector<int> v(SCHED_NFIELD);
+    sched_to_ints(c->sched, v.data());
+    cache = cache_read(path);  // merge with entries written meanwhile
+    cache[key] = v;
+    if (!cache_write(path, cache)) return fail(CELL_E_ARG, std::string("cannot write the tuning cache ") + path);
+  }
+  return CELL_OK;
+}
+
+// the cached schedule of the instance's key, if CELLFFT_TUNE_CACHE names a
+// cache that has one
+void apply_cached_schedule(cell_s* c) {
+  const char* path = std::getenv("CELLFFT_TUNE_CACHE");
+  if (!path || !*path) return;
+  const auto cache = cache_read(path);
+  auto it = cache.find(tune_key(c));
+  Sched sc;
+  if (it != cache.end() && sched_from_ints(it->second.data(), &sc)) {
+    c->sched = sc;
+    c->tuned = true;
+  }
+}
+
+void instance_get_schedule(cell_s* c, int* out) { sched_to_ints(c->sched, out); }
+
+cell_status instance_set_schedule(cell_s* c, const int* in) {
+  Sched sc;
+  if (!sched_from_ints(in, &sc)) return fail(CELL_E_ARG, "invalid schedule");
+  c->sched = sc;
+  return CELL_OK;
+}
+
+}  // namespace cellfft

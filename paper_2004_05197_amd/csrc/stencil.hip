@@ -177,11 +177,12 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
   for (int l = 0; l < a.nload; ++l) {
     bool live;
     if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
-    else live = a.only_load < 0 || a.only_load == l;
+    else live = a.mask ? a.mask[l] != 0 : (a.only_load < 0 || a.only_load == l);
     if (!live) continue;
     const T* u = a.u ? a.u + l * a.lstride : nullptr;
     TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
-    const double* eb = a.eps[l];
+    const double* eb = a.eps[l % a.lpc];
+    const T* matl = a.mat + (long long)(l / a.lpc) * a.mat_stride;
     T pf[PF_MAX];
     auto fetch_plane = [&](int zp) {
       const int zoff = wrapi(zp, nz) * (ny * nx);
@@ -197,8 +198,8 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
     };
     auto mat_of = [&](int vx, int vy, int k, T& lw, T& mw) {
       const long long vid = ((long long)wrapi(k, nz) * ny + wrapi(y0 + vy, ny)) * nx + wrapi(x0 + vx, nx);
-      lw = a.mat[2 * vid] * w;
-      mw = a.mat[2 * vid + 1] * w;
+      lw = matl[2 * vid] * w;
+      mw = matl[2 * vid + 1] * w;
     };
     // computes voxel (vx, vy) of layer k from planes in slots s0 (k), s1 (k+1)
     auto voxel = [&](int vx, int vy, int s0, int s1, T lw, T mw, T (&own)[2][3], T* sv) {
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
   {
     bool live;
     if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
-    else live = a.only_load < 0 || a.only_load == l;
+    else live = a.mask ? a.mask[l] != 0 : (a.only_load < 0 || a.only_load == l);
     if (!live) return;
   }
   const int bxi = blk % nxt, byi = (blk / nxt) % nyt, bzi = blk / (nxt * nyt);
@@ -391,9 +392,10 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
   {
     const T* u = a.u ? a.u + l * a.lstride : nullptr;
     TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
+    const T* matl = a.mat + (long long)(l / a.lpc) * a.mat_stride;
     T sbd[6];
     if (MODE == 1) {
-      const double* e = a.eps[l];
+      const double* e = a.eps[l % a.lpc];
 #pragma unroll
       for (int i = 0; i < 6; ++i) sbd[i] = (T)e[i];
     }
@@ -452,11 +454,11 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
     fetch_plane(z0);
     store_plane(1);
     int zm = wrapi(z0 - 1, nz) * nxy;
-    T lw0 = a.mat[2 * (zm + vown)] * w, mw0 = a.mat[2 * (zm + vown) + 1] * w;
+    T lw0 = matl[2 * (zm + vown)] * w, mw0 = matl[2 * (zm + vown) + 1] * w;
     T lwe = T(0), mwe = T(0);
     if (has_extra) {
-      lwe = a.mat[2 * (zm + vext)] * w;
-      mwe = a.mat[2 * (zm + vext) + 1] * w;
+      lwe = matl[2 * (zm + vext)] * w;
+      mwe = matl[2 * (zm + vext) + 1] * w;
     }
     __syncthreads();
     for (int L = 0; L <= tz; ++L) {
@@ -466,11 +468,11 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
       T lw1 = T(0), mw1 = T(0), lwe1 = T(0), mwe1 = T(0);
       if (L < tz) {
         const int zn = wrapi(k + 1, nz) * nxy;
-        lw1 = a.mat[2 * (zn + vown)] * w;
-        mw1 = a.mat[2 * (zn + vown) + 1] * w;
+        lw1 = matl[2 * (zn + vown)] * w;
+        mw1 = matl[2 * (zn + vown) + 1] * w;
         if (has_extra) {
-          lwe1 = a.mat[2 * (zn + vext)] * w;
-          mwe1 = a.mat[2 * (zn + vext) + 1] * w;
+          lwe1 = matl[2 * (zn + vext)] * w;
+          mwe1 = matl[2 * (zn + vext) + 1] * w;
         }
       }
       T pk[3] = {T(0), T(0), T(0)};
@@ -584,7 +586,7 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   const int l = blockIdx.y;
   bool live;
   if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
-  else live = a.only_load < 0 || a.only_load == l;
+  else live = a.mask ? a.mask[l] != 0 : (a.only_load < 0 || a.only_load == l);
   if (!live) return;
   const int nx = a.g.nx, ny = a.g.ny;
   const long long n = a.g.n;
@@ -592,7 +594,8 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   const T w = (T)(a.g.h[0] * a.g.h[1] / 2.0);
   const T* u = a.u ? a.u + l * a.lstride : nullptr;
   TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
-  const double* eb = a.eps[l];
+  const double* eb = a.eps[l % a.lpc];
+  const T* matl = a.mat + (long long)(l / a.lpc) * a.mat_stride;
   double acc = 0.0;
   double sacc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const long long node = (long long)blockIdx.x * NT + threadIdx.x;
@@ -615,7 +618,7 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
             for (int c = 0; c < 2; ++c) uu[cx + 2 * cy][c] = u ? u[c * n + nd] : T(0);
           }
         const long long vid = (long long)pj * nx + pi;
-        const T lw = a.mat[2 * vid] * w, mw = a.mat[2 * vid + 1] * w;
+        const T lw = matl[2 * vid] * w, mw = matl[2 * vid + 1] * w;
         T sb[3];
         if (MODE == 1) {
           const T tr = (T)(eb[0] + eb[1]);
@@ -659,10 +662,10 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
 
 // fixed-order sums of the per-block stress partials: sbar[l][i]
 __global__ __launch_bounds__(NT) void k_stress_finalize(const double* sparts, int maxblk, int nparts,
-                                                        int only_load, double* sbar) {
+                                                        int only_load, const int* mask, double* sbar) {
   __shared__ double sh[NT / WAVE];
   const int i = blockIdx.x, l = blockIdx.y;
-  if (only_load >= 0 && l != only_load) return;
+  if (mask ? mask[l] == 0 : (only_load >= 0 && l != only_load)) return;
   const double* row = sparts + ((long long)l * 6 + i) * maxblk;
   double v = 0.0;
   for (int b = threadIdx.x; b < nparts; b += NT) v += row[b];
@@ -739,13 +742,16 @@ __global__ __launch_bounds__(NT) void k_udotr(HArgs a) {
   __shared__ double sh[NT / WAVE];
   const int nl = a.nload;
   const long long len = a.lstride;
-  const TR* r = reinterpret_cast<const TR*>(a.r);
+  const int cell = blockIdx.y;
+  const TR* r = reinterpret_cast<const TR*>(a.r) + (long long)cell * a.lpc * len;
+  const double* u = a.u + (long long)cell * a.lpc * len;
+  double* parts = a.parts + (long long)cell * nl * nl * a.nblk;
   double acc[6][6] = {};
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < len; i += (long long)gridDim.x * NT) {
     double uu[6], rr[6];
 #pragma unroll
     for (int I = 0; I < 6; ++I) {
-      uu[I] = I < nl ? a.u[I * len + i] : 0.0;
+      uu[I] = I < nl ? u[I * len + i] : 0.0;
       rr[I] = I < nl ? (double)r[I * len + i] : 0.0;
     }
 #pragma unroll
@@ -761,7 +767,7 @@ __global__ __launch_bounds__(NT) void k_udotr(HArgs a) {
       for (int J = 0; J < 6; ++J)
         if (I * nl + J == t) v = acc[I][J];
     const double bs = block_sum<NT>(v, sh);
-    if (threadIdx.x == 0) a.parts[(long long)t * a.nblk + blockIdx.x] = bs;
+    if (threadIdx.x == 0) parts[(long long)t * a.nblk + blockIdx.x] = bs;
   }
 }
 
@@ -771,9 +777,13 @@ __global__ __launch_bounds__(NT) void k_homog_combine(HArgs a, double inv_vol) {
   __shared__ double sh[NT / WAVE];
   __shared__ double dots[36];
   const int nl = a.nload;
+  const int cell = blockIdx.x;
+  const double* parts = a.parts + (long long)cell * nl * nl * a.nblk;
+  const double* sbar = a.sbar + (long long)cell * a.lpc * 6;
+  double* result = a.result + (long long)cell * (nl * nl + nl * (a.g.dim == 3 ? 6 : 3));
   for (int t = 0; t < nl * nl; ++t) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < a.nblk; b += NT) v += a.parts[(long long)t * a.nblk + b];
+    for (int b = threadIdx.x; b < a.nblk; b += NT) v += parts[(long long)t * a.nblk + b];
     const double s = block_sum<NT>(v, sh);
     if (threadIdx.x == 0) dots[t] = s;
   }
@@ -784,14 +794,14 @@ __global__ __launch_bounds__(NT) void k_homog_combine(HArgs a, double inv_vol) {
     for (int I = 0; I < nl; ++I)
       for (int J = 0; J < nl; ++J) {
         const double* e = a.eps[I];
-        const double* sg = a.sbar + 6 * J;
+        const double* sg = sbar + 6 * J;
         const double es = e[0] * sg[0] + e[1] * sg[1] + e[2] * sg[2] + 2.0 * (e[3] * sg[3] + e[4] * sg[4] + e[5] * sg[5]);
-        a.result[I * nl + J] = (es - dots[I * nl + J]) * inv_vol;
+        result[I * nl + J] = (es - dots[I * nl + J]) * inv_vol;
       }
     for (int J = 0; J < nl; ++J)
       for (int q = 0; q < nv; ++q) {
         const int src = D == 3 ? q : (q == 2 ? 5 : q);
-        a.result[nl * nl + J * nv + q] = a.sbar[6 * J + src] * inv_vol;
+        result[nl * nl + J * nv + q] = sbar[6 * J + src] * inv_vol;
       }
   }
 }
@@ -845,27 +855,48 @@ struct Tile3 {
   int bx, by, tz;
 };
 
-// x extent: largest divisor of nx up to 64 (fp32) / 32 (fp64, LDS budget)
-static Tile3 pick_tile3(const Geom& g, bool fp64) {
+// runtime tile (any grid): x extent the largest divisor of nx up to 64
+// (fp32) / 32 (fp64, LDS budget), z extent from the schedule
+static Tile3 pick_tile3(const Geom& g, bool fp64, int tz) {
   Tile3 t;
   t.bx = 1;
   for (int d = fp64 ? 32 : 64; d >= 1; --d)
     if (g.nx % d == 0) { t.bx = d; break; }
   t.by = NT / t.bx;
   if (t.by > g.ny) t.by = g.ny;
-  t.tz = g.nz >= 32 ? 32 : g.nz;
+  t.tz = g.nz >= tz ? tz : g.nz;
   return t;
 }
 
-// compile-time tiles: fp32 64 x 4 (or 64 x 8), fp64 32 x 8
-template <typename T> struct FastTile;
-template <> struct FastTile<float> { static constexpr int BX = 64, BY = 4; };
-template <> struct FastTile<double> { static constexpr int BX = 32, BY = 8; };
+// compile-time tiles (BX x BY threads), in schedule order
+// (BX + BY + 1 halo voxels are computed twice, once here and once by the
+// neighbouring tile: the 512-thread tiles halve that share)
+void stencil_tile_dims(bool fp64, int t, int* bx, int* by) {
+  static const int f32[ST_NTILE][2] = {{64, 4}, {32, 8}, {16, 16}, {64, 8}, {32, 16}};
+  static const int f64[ST_NTILE][2] = {{32, 8}, {16, 16}, {64, 4}, {32, 16}, {16, 32}};
+  if (t < 0 || t >= ST_NTILE) t = 0;
+  *bx = (fp64 ? f64 : f32)[t][0];
+  *by = (fp64 ? f64 : f32)[t][1];
+}
 
-static bool use_fast3(const Geom& g, bool fp64) {
-  const int bx = fp64 ? FastTile<double>::BX : FastTile<float>::BX;
-  const int by = fp64 ? FastTile<double>::BY : FastTile<float>::BY;
+bool stencil_tile_fits(const Geom& g, bool fp64, int t) {
+  int bx, by;
+  stencil_tile_dims(fp64, t, &bx, &by);
   return g.dim == 3 && g.nx % bx == 0 && g.ny % by == 0 && g.n < (1LL << 29);
+}
+
+// the tile a schedule runs: its own if it fits the grid, else the first one
+// that fits, else -1 (runtime tile)
+static int effective_tile(const Geom& g, bool fp64, int t) {
+  if (stencil_tile_fits(g, fp64, t)) return t;
+  for (int u = 0; u < ST_NTILE; ++u)
+    if (stencil_tile_fits(g, fp64, u)) return u;
+  return -1;
+}
+
+static int sched_tz(const Geom& g, const Sched& sc) {
+  const int tz = sc.st_tz < ST_TZ_MIN ? ST_TZ_MIN : sc.st_tz;
+  return g.nz >= tz ? tz : g.nz;
 }
 
 template <typename T>
@@ -873,36 +904,83 @@ static size_t stencil3_lds(const Tile3& t) {
   return sizeof(T) * (6 * (t.bx + 2) * (t.by + 2) + 18 * (t.bx + 1) * (t.by + 1));
 }
 
-int stencil_blocks(const Geom& g) {
+int stencil_blocks(const Geom& g, const Sched& sc, bool fp64) {
   if (g.dim == 2) return (int)((g.n + NT - 1) / NT);
+  const int tz = sched_tz(g, sc);
+  const int nzt = (g.nz + tz - 1) / tz;
+  const int t = effective_tile(g, fp64, sc.st_tile);
+  if (t >= 0) {
+    int bx, by;
+    stencil_tile_dims(fp64, t, &bx, &by);
+    return (g.nx / bx) * (g.ny / by) * nzt;
+  }
+  const Tile3 rt = pick_tile3(g, fp64, tz);
+  return (g.nx / rt.bx) * ((g.ny + rt.by - 1) / rt.by) * nzt;
+}
+
+int max_reduction_blocks(const Geom& g) {
   int mb = 0;
+  const int nrows = g.dim * g.ny * g.nz;
   for (int fp64 = 0; fp64 < 2; ++fp64) {
-    const Tile3 t = pick_tile3(g, fp64);
-    mb = std::max(mb, (g.nx / t.bx) * ((g.ny + t.by - 1) / t.by) * ((g.nz + t.tz - 1) / t.tz));
-    const int bx = fp64 ? FastTile<double>::BX : FastTile<float>::BX;
-    const int by = fp64 ? FastTile<double>::BY : FastTile<float>::BY;
-    if (use_fast3(g, fp64)) mb = std::max(mb, (g.nx / bx) * (g.ny / by) * ((g.nz + t.tz - 1) / t.tz));
+    for (int v = 0; v < 2; ++v) {
+      Sched sc;
+      sc.x_var = v;
+      sc.z_var = v;
+      mb = std::max(mb, xpass_blocks(g.nx, nrows, fp64, sc));
+      mb = std::max(mb, last_pass_blocks(g.dim, g.nx, g.ny, fp64, sc));
+    }
+    for (int t = 0; t < ST_NTILE; ++t)
+      for (int tz = ST_TZ_MIN; tz <= 64; tz *= 2) {
+        Sched sc;
+        sc.st_tile = t;
+        sc.st_tz = tz;
+        mb = std::max(mb, stencil_blocks(g, sc, fp64));
+      }
   }
   return mb;
 }
 
-template <typename T, typename TO, int MODE>
-static hipError_t launch_stencil_impl(const KArgs<T>& a, hipStream_t s) {
+template <typename T, typename TO, int MODE, int BX, int BY>
+static void launch_tile3(const KArgs<T>& a, int tz, int& nparts, hipStream_t s) {
   const Geom& g = a.g;
-  int nparts;
-  if (g.dim == 3 && use_fast3(g, sizeof(T) == 8)) {
-    constexpr int BX = FastTile<T>::BX, BY = FastTile<T>::BY;
-    const int tz = pick_tile3(g, sizeof(T) == 8).tz;
-    const int nxt = g.nx / BX, nyt = g.ny / BY, nzt = (g.nz + tz - 1) / tz;
-    nparts = nxt * nyt * nzt;
-    dim3 grid(xcd_grid(nparts * a.nload));
-    const bool uni = g.h[0] == g.h[1] && g.h[1] == g.h[2];
-    if (uni)
-      hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, true, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz, nxt, nyt, nzt);
-    else
-      hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, false, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz, nxt, nyt, nzt);
+  const int nxt = g.nx / BX, nyt = g.ny / BY, nzt = (g.nz + tz - 1) / tz;
+  nparts = nxt * nyt * nzt;
+  dim3 grid(xcd_grid(nparts * a.nload));
+  const bool uni = g.h[0] == g.h[1] && g.h[1] == g.h[2];
+  if (uni)
+    hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, true, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz, nxt, nyt, nzt);
+  else
+    hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, false, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz, nxt, nyt, nzt);
+}
+
+template <typename T, typename TO, int MODE>
+static hipError_t launch_stencil_impl(const KArgs<T>& a, const Sched& sc, hipStream_t s) {
+  const Geom& g = a.g;
+  constexpr bool fp64 = sizeof(T) == 8;
+  int nparts = 0;
+  const int tile = g.dim == 3 ? effective_tile(g, fp64, sc.st_tile) : -1;
+  if (tile >= 0) {
+    const int tz = sched_tz(g, sc);
+    // tile order as in stencil_tile_dims
+    if constexpr (fp64) {
+      switch (tile) {
+        case 0: launch_tile3<T, TO, MODE, 32, 8>(a, tz, nparts, s); break;
+        case 1: launch_tile3<T, TO, MODE, 16, 16>(a, tz, nparts, s); break;
+        case 2: launch_tile3<T, TO, MODE, 64, 4>(a, tz, nparts, s); break;
+        case 3: launch_tile3<T, TO, MODE, 32, 16>(a, tz, nparts, s); break;
+        default: launch_tile3<T, TO, MODE, 16, 32>(a, tz, nparts, s); break;
+      }
+    } else {
+      switch (tile) {
+        case 0: launch_tile3<T, TO, MODE, 64, 4>(a, tz, nparts, s); break;
+        case 1: launch_tile3<T, TO, MODE, 32, 8>(a, tz, nparts, s); break;
+        case 2: launch_tile3<T, TO, MODE, 16, 16>(a, tz, nparts, s); break;
+        case 3: launch_tile3<T, TO, MODE, 64, 8>(a, tz, nparts, s); break;
+        default: launch_tile3<T, TO, MODE, 32, 16>(a, tz, nparts, s); break;
+      }
+    }
   } else if (g.dim == 3) {
-    const Tile3 t = pick_tile3(g, sizeof(T) == 8);
+    const Tile3 t = pick_tile3(g, fp64, sched_tz(g, sc));
     dim3 grid(g.nx / t.bx, (g.ny + t.by - 1) / t.by, (g.nz + t.tz - 1) / t.tz);
     nparts = grid.x * grid.y * grid.z;
     const size_t lds = stencil3_lds<T>(t);
@@ -917,23 +995,25 @@ static hipError_t launch_stencil_impl(const KArgs<T>& a, hipStream_t s) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_finalize(a.red, a.st, a.res2, MODE == 0 ? RED_PQ : RED_RES, nparts, a.nload, a.only_load, s);
+  if (nparts > a.red.maxblk) return hipErrorInvalidValue;
+  e = launch_finalize(a.red, a.st, a.res2, MODE == 0 ? RED_PQ : RED_RES, nparts, a.nload, a.only_load,
+                      MODE == 1 ? a.mask : nullptr, s);
   if (e != hipSuccess || MODE != 1 || !a.sparts) return e;
   hipLaunchKernelGGL(k_stress_finalize, dim3(6, a.nload), dim3(NT), 0, s, (const double*)a.sparts, a.red.maxblk,
-                     nparts, a.only_load, a.sbar);
+                     nparts, a.only_load, a.mask, a.sbar);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_stencil(const KArgs<T>& a, hipStream_t s) {
-  if (a.mode == 0) return launch_stencil_impl<T, T, 0>(a, s);
-  return launch_stencil_impl<T, T, 1>(a, s);
+hipError_t launch_stencil(const KArgs<T>& a, const Sched& sc, hipStream_t s) {
+  if (a.mode == 0) return launch_stencil_impl<T, T, 0>(a, sc, s);
+  return launch_stencil_impl<T, T, 1>(a, sc, s);
 }
 
-hipError_t launch_residual_mixed(const KArgs<double>& a, float* out32, hipStream_t s) {
+hipError_t launch_residual_mixed(const KArgs<double>& a, float* out32, const Sched& sc, hipStream_t s) {
   KArgs<double> b = a;
   b.out = out32;
-  return launch_stencil_impl<double, float, 1>(b, s);
+  return launch_stencil_impl<double, float, 1>(b, sc, s);
 }
 
 int homog_blocks(const Geom& g) {
@@ -941,11 +1021,11 @@ int homog_blocks(const Geom& g) {
   return (int)(nb < 1024 ? nb : 1024);
 }
 
-hipError_t launch_homog(const HArgs& a, hipStream_t s) {
-  if (a.r_fp64) hipLaunchKernelGGL(k_udotr<double>, dim3(a.nblk), dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL(k_udotr<float>, dim3(a.nblk), dim3(NT), 0, s, a);
+hipError_t launch_homog(const HArgs& a, int ncell, hipStream_t s) {
+  if (a.r_fp64) hipLaunchKernelGGL(k_udotr<double>, dim3(a.nblk, ncell), dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL(k_udotr<float>, dim3(a.nblk, ncell), dim3(NT), 0, s, a);
   const double vol = a.g.h[0] * a.g.h[1] * (a.g.dim == 3 ? a.g.h[2] : 1.0) * a.g.n;
-  hipLaunchKernelGGL(k_homog_combine, dim3(1), dim3(NT), 0, s, a, 1.0 / vol);
+  hipLaunchKernelGGL(k_homog_combine, dim3(ncell), dim3(NT), 0, s, a, 1.0 / vol);
   return hipGetLastError();
 }
 
@@ -954,7 +1034,7 @@ hipError_t launch_grad(const HArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t launch_stencil<float>(const KArgs<float>&, hipStream_t);
-template hipError_t launch_stencil<double>(const KArgs<double>&, hipStream_t);
+template hipError_t launch_stencil<float>(const KArgs<float>&, const Sched&, hipStream_t);
+template hipError_t launch_stencil<double>(const KArgs<double>&, const Sched&, hipStream_t);
 
 }  // namespace cellfft

@@ -59,42 +59,86 @@ def rsa_spheres(n: int, vf: float, seed: int, rmin: float = 4.0,
     Spheres are added until the inclusion voxel fraction reaches ``vf``.
     Returns (mask[bool, (n, n, n)], achieved_vf, list_of_(centre, r)).
     """
+    from scipy.spatial import cKDTree
     rng = np.random.default_rng(seed)
     mask = np.zeros((n, n, n), dtype=bool)
     spheres = []
+    cen = np.zeros((0, 3))
+    rad = np.zeros(0)
     rejects = 0
     target = vf * n ** 3
     count = 0
+    block = 64
     while count < target:
-        r = rng.uniform(rmin, rmax)
-        c = rng.uniform(0.0, n, size=3)
-        ok = True
-        for (c2, r2) in spheres:
-            dv = c - c2
+        # A block of candidates in the order of the sequential draws (r, then
+        # the centre's x, y, z): the same stream as one candidate at a time.
+        # Each candidate is tested against the spheres accepted before the
+        # block at once (neighbours from a periodic k-d tree, the decision by
+        # the minimum-image formula below), then one by one against the
+        # block's own acceptances -- the outcome of testing sequentially.
+        u = rng.random((block, 4))
+        rb = rmin + (rmax - rmin) * u[:, 0]
+        cb = n * u[:, 1:]
+        nb = len(rad)
+        clash = np.zeros(block, dtype=bool)
+        if nb:
+            kq = min(nb, 32)
+            tree = cKDTree(cen % n, boxsize=n)
+            dist, idx = tree.query(cb % n, k=kq)
+            dist = dist.reshape(block, kq)
+            idx = idx.reshape(block, kq)
+            dv = cb[:, None, :] - cen[idx]
             dv -= n * np.round(dv / n)
-            if np.dot(dv, dv) < (r + r2) ** 2:
-                ok = False
+            d2 = dv[..., 0] ** 2 + dv[..., 1] ** 2 + dv[..., 2] ** 2
+            clash = np.any(d2 < (rb[:, None] + rad[idx]) ** 2, axis=1)
+            # more than kq spheres may lie within reach: test those in full
+            full = (~clash) & (kq < nb) & (dist[:, -1] < rb + rmax + 1e-6)
+            for k in np.nonzero(full)[0]:
+                dv = cb[k][None, :] - cen
+                dv -= n * np.round(dv / n)
+                d2 = dv[:, 0] ** 2 + dv[:, 1] ** 2 + dv[:, 2] ** 2
+                clash[k] = np.any(d2 < (rb[k] + rad) ** 2)
+        accepted_here = 0
+        kend = block
+        for k in np.nonzero(~clash)[0]:
+            if count >= target:
+                kend = k
                 break
-        if not ok:
-            rejects += 1
-            if rejects > max_reject:
-                raise RuntimeError("rsa_spheres: too many rejections")
-            continue
-        spheres.append((c, r))
-        # voxels in the bounding box, wrapped periodically
-        lo = np.floor(c - r - 1).astype(int)
-        hi = np.ceil(c + r + 1).astype(int)
-        ix = np.arange(lo[0], hi[0])
-        iy = np.arange(lo[1], hi[1])
-        iz = np.arange(lo[2], hi[2])
-        dx = (ix + 0.5) - c[0]
-        dy = (iy + 0.5) - c[1]
-        dz = (iz + 0.5) - c[2]
-        d2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
-        sel = d2 < r * r
-        zz, yy, xx = np.nonzero(sel)
-        mask[iz[zz] % n, iy[yy] % n, ix[xx] % n] = True
-        count = int(mask.sum())
+            r, c = rb[k], cb[k]
+            ok = True
+            if len(rad) > nb:
+                dv = c[None, :] - cen[nb:]
+                dv -= n * np.round(dv / n)
+                d2 = dv[:, 0] ** 2 + dv[:, 1] ** 2 + dv[:, 2] ** 2
+                ok = not np.any(d2 < (r + rad[nb:]) ** 2)
+            if not ok:
+                rejects += 1
+                continue
+            accepted_here += 1
+            spheres.append((c, r))
+            cen = np.vstack([cen, c[None, :]])
+            rad = np.append(rad, r)
+            # voxels in the bounding box, wrapped periodically
+            lo = np.floor(c - r - 1).astype(int)
+            hi = np.ceil(c + r + 1).astype(int)
+            ix = np.arange(lo[0], hi[0])
+            iy = np.arange(lo[1], hi[1])
+            iz = np.arange(lo[2], hi[2])
+            dx = (ix + 0.5) - c[0]
+            dy = (iy + 0.5) - c[1]
+            dz = (iz + 0.5) - c[2]
+            d2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+            sel = d2 < r * r
+            zz, yy, xx = np.nonzero(sel)
+            flat = np.unique(((iz[zz] % n) * n + (iy[yy] % n)) * n + (ix[xx] % n))
+            count += int(np.count_nonzero(~mask.ravel()[flat]))
+            mask.ravel()[flat] = True
+        rejects += int(np.count_nonzero(clash[:kend]))
+        if rejects > max_reject:
+            raise RuntimeError("rsa_spheres: too many rejections")
+        # larger blocks once acceptances become rare
+        if accepted_here <= 1:
+            block = min(block * 2, 1 << 15)
     return mask, count / n ** 3, spheres
 
 
