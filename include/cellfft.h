@@ -219,6 +219,11 @@ cell_status cell_batch_solve(cell_batch_t b, int nload, const double* macro_stra
 /* C* of every cell, C_out host [ncell][nv][nv]; infos (may be NULL) [ncell]. */
 cell_status cell_batch_effective_stiffness(cell_batch_t b, double* C_out, cell_info* infos);
 
+/* Displacement / final residual of load `load` of cell i after the last
+ * batched solve, as cell_get_displacement / cell_get_residual ([d][n_i]). */
+cell_status cell_batch_get_displacement(cell_batch_t b, int i, int load, double* u_out, int on_device);
+cell_status cell_batch_get_residual(cell_batch_t b, int i, int load, double* r_out, int on_device);
+
 /* Per-kernel timing summed over the batch's groups (as cell_profile). */
 cell_status cell_batch_profile(cell_batch_t b, int enable);
 cell_status cell_batch_profile_read(cell_batch_t b, double* ms_out, long long* launches_out);

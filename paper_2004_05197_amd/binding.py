@@ -86,6 +86,8 @@ _SIGS = {
     "cell_batch_groups": (ct.c_int, [_P]),
     "cell_batch_destroy": (None, [_P]),
     "cell_batch_autotune": (ct.c_int, [_P, ct.c_int]),
+    "cell_batch_get_displacement": (ct.c_int, [_P, ct.c_int, ct.c_int, _P, ct.c_int]),
+    "cell_batch_get_residual": (ct.c_int, [_P, ct.c_int, ct.c_int, _P, ct.c_int]),
     "cell_autotune": (ct.c_int, [_P, ct.c_int]),
     "cell_get_schedule": (ct.c_int, [_P, _P]),
     "cell_set_schedule": (ct.c_int, [_P, _P]),
@@ -173,9 +175,9 @@ class Cell:
         self.solves = 0  # incremented by every solve (autograd consistency check)
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.cell_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -304,9 +306,9 @@ class Batch:
         self.nv = 3 if self.dim == 2 else 6
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.cell_batch_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -346,6 +348,16 @@ class Batch:
         infos = (CellInfo * self.ncell)()
         st = _check(_lib.cell_batch_effective_stiffness(self._h, C.ctypes.data_as(ct.c_void_p), infos))
         return C, [dict(i.as_dict(), status=STATUS_NAMES[st]) for i in infos]
+
+    def displacement(self, i, load=0):
+        u = np.zeros((self.dim, int(np.prod(self.shapes[i]))))
+        _check(_lib.cell_batch_get_displacement(self._h, int(i), int(load), u.ctypes.data_as(ct.c_void_p), 0))
+        return u
+
+    def residual(self, i, load=0):
+        r = np.zeros((self.dim, int(np.prod(self.shapes[i]))))
+        _check(_lib.cell_batch_get_residual(self._h, int(i), int(load), r.ctypes.data_as(ct.c_void_p), 0))
+        return r
 
     def profile(self, enable=True):
         _check(_lib.cell_batch_profile(self._h, int(bool(enable))))

@@ -112,6 +112,61 @@ cell_status check_strains(int nload, int nv, const double* eps) {
   return CELL_OK;
 }
 
+// mean-zero displacement of load `load` of cell `cell` of the last solve
+cell_status slot_displacement(cell_s* c, int cell, int load, double* u_out, int on_device) {
+  if (!c->solved) return fail(CELL_E_STATE, "no solution available");
+  if (load < 0 || load >= c->nload_solved) return fail(CELL_E_ARG, "load index out of range");
+  DevGuard dg(c->dev);
+  const double* u = solution64(c) + ((long long)cell * c->lpc + load) * c->lstride;
+  const int nblk = 256;
+  double* parts = c->scratch;
+  double* mean = c->scratch + 8 * nblk;
+  hipLaunchKernelGGL(k_colsum, dim3(nblk), dim3(NT), 0, c->stream, u, c->n, c->d, parts, nblk);
+  hipLaunchKernelGGL(k_sum_rows2, dim3(c->d), dim3(NT), 0, c->stream, (const double*)parts, nblk,
+                     1.0 / (double)c->n, mean);
+  if (on_device) {
+    hipLaunchKernelGGL(k_sub_mean, dim3(1024), dim3(256), 0, c->stream, u, (const double*)mean, c->n, c->d, u_out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CELL_OK;
+  }
+  // host output: subtract the means on the device into a temporary buffer
+  double* tmp = nullptr;
+  if (hipMalloc((void**)&tmp, sizeof(double) * c->lstride) != hipSuccess)
+    return fail(CELL_E_NOMEM, "device allocation failed");
+  hipLaunchKernelGGL(k_sub_mean, dim3(1024), dim3(256), 0, c->stream, u, (const double*)mean, c->n, c->d, tmp);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(u_out, tmp, sizeof(double) * c->lstride, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(CELL_E_DEVICE, hipGetErrorString(e));
+  return CELL_OK;
+}
+
+// final residual of load `load` of cell `cell` (FP32 rounding in mixed mode)
+cell_status slot_residual(cell_s* c, int cell, int load, double* r_out, int on_device) {
+  if (!c->solved) return fail(CELL_E_STATE, "no solution available");
+  if (load < 0 || load >= c->nload_solved) return fail(CELL_E_ARG, "load index out of range");
+  DevGuard dg(c->dev);
+  const long long off = ((long long)cell * c->lpc + load) * c->lstride;
+  if (c->precision == CELL_MIXED) {
+    std::vector<float> h(c->lstride);
+    HIPCHK(hipMemcpyAsync(h.data(), c->f32.r + off, sizeof(float) * c->lstride, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (on_device) {
+      std::vector<double> d(h.begin(), h.end());
+      HIPCHK(hipMemcpy(r_out, d.data(), sizeof(double) * c->lstride, hipMemcpyHostToDevice));
+    } else {
+      for (long long i = 0; i < c->lstride; ++i) r_out[i] = (double)h[i];
+    }
+  } else {
+    HIPCHK(hipMemcpyAsync(r_out, c->f64.r + off, sizeof(double) * c->lstride,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return CELL_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -202,33 +257,7 @@ cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int o
 
 cell_status cell_get_displacement(cell_t c, int load, double* u_out, int on_device) {
   if (!c || !u_out) return fail(CELL_E_ARG, "null argument");
-  if (!c->solved) return fail(CELL_E_STATE, "no solution available");
-  if (load < 0 || load >= c->nload_solved) return fail(CELL_E_ARG, "load index out of range");
-  DevGuard dg(c->dev);
-  const double* u = solution64(c) + (long long)load * c->lstride;
-  const int nblk = 256;
-  double* parts = c->scratch;
-  double* mean = c->scratch + 8 * nblk;
-  hipLaunchKernelGGL(k_colsum, dim3(nblk), dim3(NT), 0, c->stream, u, c->n, c->d, parts, nblk);
-  hipLaunchKernelGGL(k_sum_rows2, dim3(c->d), dim3(NT), 0, c->stream, (const double*)parts, nblk,
-                     1.0 / (double)c->n, mean);
-  if (on_device) {
-    hipLaunchKernelGGL(k_sub_mean, dim3(1024), dim3(256), 0, c->stream, u, (const double*)mean, c->n, c->d, u_out);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
-    return CELL_OK;
-  }
-  // host output: subtract the means on the device into a temporary buffer
-  double* tmp = nullptr;
-  if (hipMalloc((void**)&tmp, sizeof(double) * c->lstride) != hipSuccess)
-    return fail(CELL_E_NOMEM, "device allocation failed");
-  hipLaunchKernelGGL(k_sub_mean, dim3(1024), dim3(256), 0, c->stream, u, (const double*)mean, c->n, c->d, tmp);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(u_out, tmp, sizeof(double) * c->lstride, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(tmp);
-  if (e != hipSuccess) return fail(CELL_E_DEVICE, hipGetErrorString(e));
-  return CELL_OK;
+  return slot_displacement(c, 0, load, u_out, on_device);
 }
 
 cell_status cell_energy_matrix(cell_t c, double* C_out) {
@@ -241,26 +270,7 @@ cell_status cell_energy_matrix(cell_t c, double* C_out) {
 
 cell_status cell_get_residual(cell_t c, int load, double* r_out, int on_device) {
   if (!c || !r_out) return fail(CELL_E_ARG, "null argument");
-  if (!c->solved) return fail(CELL_E_STATE, "no solution available");
-  if (load < 0 || load >= c->nload_solved) return fail(CELL_E_ARG, "load index out of range");
-  DevGuard dg(c->dev);
-  const long long off = (long long)load * c->lstride;
-  if (c->precision == CELL_MIXED) {
-    std::vector<float> h(c->lstride);
-    HIPCHK(hipMemcpyAsync(h.data(), c->f32.r + off, sizeof(float) * c->lstride, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (on_device) {
-      std::vector<double> d(h.begin(), h.end());
-      HIPCHK(hipMemcpy(r_out, d.data(), sizeof(double) * c->lstride, hipMemcpyHostToDevice));
-    } else {
-      for (long long i = 0; i < c->lstride; ++i) r_out[i] = (double)h[i];
-    }
-  } else {
-    HIPCHK(hipMemcpyAsync(r_out, c->f64.r + off, sizeof(double) * c->lstride,
-                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-  }
-  return CELL_OK;
+  return slot_residual(c, 0, load, r_out, on_device);
 }
 
 cell_status cell_reference_medium(cell_t c, double* lam0, double* mu0) {
@@ -470,6 +480,18 @@ cell_status cell_batch_effective_stiffness(cell_batch_t b, double* C_out, cell_i
     }
   }
   return st;
+}
+
+cell_status cell_batch_get_displacement(cell_batch_t b, int cell, int load, double* u_out, int on_device) {
+  if (!b || !u_out) return fail(CELL_E_ARG, "null argument");
+  if (cell < 0 || cell >= (int)b->cls_of.size()) return fail(CELL_E_ARG, "cell index out of range");
+  return slot_displacement(b->cls[b->cls_of[cell]], b->idx_of[cell], load, u_out, on_device);
+}
+
+cell_status cell_batch_get_residual(cell_batch_t b, int cell, int load, double* r_out, int on_device) {
+  if (!b || !r_out) return fail(CELL_E_ARG, "null argument");
+  if (cell < 0 || cell >= (int)b->cls_of.size()) return fail(CELL_E_ARG, "cell index out of range");
+  return slot_residual(b->cls[b->cls_of[cell]], b->idx_of[cell], load, r_out, on_device);
 }
 
 cell_status cell_batch_profile(cell_batch_t b, int enable) {

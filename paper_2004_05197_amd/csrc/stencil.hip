@@ -41,27 +41,34 @@ __host__ __device__ constexpr int sym_idx(int i, int j) {
   return i == j ? i : (i + j == 3 ? 3 : (i + j == 2 ? 4 : 5));
 }
 
-// One simplex of the Kuhn split (compile-time permutation) for one voxel.
-// u[c][k]: corner c = ox + 2 oy + 4 oz, component k.
-// UNI (equal edge lengths h): G holds raw differences and lw = lambda |s| / h^2,
-//   mw = mu |s| / h^2, sb = |s| D eps_bar / h, so the corner forces come out
-//   without any per-axis scaling.
-// !UNI: G = differences / h_a, fluxes * 1/h_a, lw = lambda |s|, sb = |s| D eps_bar.
-template <typename T, int A0, int A1, int A2, bool MACRO, bool UNI>
-__device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw2, T mw, const T* ih,
-                                         const T* sb, T (&f)[8][3], T* sacc) {
-  constexpr int c0 = 0, c1 = 1 << A0, c2 = c1 | (1 << A1), c3 = 7;
-  T G[3][3];
+// Edge formulation of one voxel.  The 12 edges of the six monotone paths
+// are: first edges along a from corner 0 (e0[a]), middle edges along b from
+// corner 1<<a (em[a][b], a != b), last edges along a into corner 7 (el[a]).
+// The first and last edges are shared by two simplices, the middle ones
+// belong to one.  Simplex s with axis order (p0, p1, p2) has the gradient
+// columns G[:, p0] = e0[p0], G[:, p1] = em[p0][p1], G[:, p2] = el[p2]
+// (differences, scaled by 1/h_a unless UNI) and sends the flux column
+// sigma_s[:, p_j] from the start to the end of its step j; the fluxes of a
+// shared edge are summed first, then each corner gets the signed sum of the
+// fluxes of its edges (12 edges instead of 18 simplex steps).
+// UNI (equal edge lengths h): differences unscaled, lw = lambda |s| / h^2,
+//   mw = mu |s| / h^2, sb = |s| D eps_bar / h: corner forces need no scaling.
+// !UNI: differences and fluxes times 1/h_a, lw = lambda |s|, sb = |s| D eps_bar.
+// One Kuhn simplex (compile-time axis order A0, A1, A2) given the edge
+// differences of its path: first edge along A0 from corner 0 (e0[A0]),
+// middle edge along A1 from corner 1<<A0 (em[A0][A1]), last edge along A2
+// into corner 7 (el[A2]).  Computes the stress and adds its three flux
+// columns to the edge fluxes (F0 / FL: first use assigns).
+template <typename T, int A0, int A1, int A2, bool F0, bool FL, bool MACRO>
+__device__ __forceinline__ void tet3(const T (&e0)[3][3], const T (&em)[3][3][3], const T (&el)[3][3], T lw,
+                                     T mw2, T mw, const T* sb, T (&p0)[3][3], T (&pm)[3][3][3], T (&pl)[3][3],
+                                     T* sacc) {
+  T G[3][3];  // G[k][a]: component k of the gradient along axis a
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    G[k][A0] = u[c1][k] - u[c0][k];
-    G[k][A1] = u[c2][k] - u[c1][k];
-    G[k][A2] = u[c3][k] - u[c2][k];
-    if (!UNI) {
-      G[k][A0] *= ih[A0];
-      G[k][A1] *= ih[A1];
-      G[k][A2] *= ih[A2];
-    }
+    G[k][A0] = e0[A0][k];
+    G[k][A1] = em[A0][A1][k];
+    G[k][A2] = el[A2][k];
   }
   const T lt = lw * (G[0][0] + G[1][1] + G[2][2]);
   T s[6];
@@ -80,16 +87,10 @@ __device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw2, T mw, 
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    T t1 = s[sym_idx(k, A0)], t2 = s[sym_idx(k, A1)], t3 = s[sym_idx(k, A2)];
-    if (!UNI) {
-      t1 *= ih[A0];
-      t2 *= ih[A1];
-      t3 *= ih[A2];
-    }
-    f[c0][k] -= t1;
-    f[c1][k] += t1 - t2;
-    f[c2][k] += t2 - t3;
-    f[c3][k] += t3;
+    const T t0 = s[sym_idx(k, A0)], t1 = s[sym_idx(k, A1)], t2 = s[sym_idx(k, A2)];
+    p0[A0][k] = F0 ? t0 : p0[A0][k] + t0;
+    pm[A0][A1][k] = t1;
+    pl[A2][k] = FL ? t2 : pl[A2][k] + t2;
   }
 }
 
@@ -98,17 +99,55 @@ __device__ __forceinline__ void simplex3(const T (&u)[8][3], T lw, T mw2, T mw, 
 template <typename T, bool MACRO, bool UNI>
 __device__ __forceinline__ void voxel3(const T (&u)[8][3], T lw, T mw, const T* ih, const T* sb,
                                        T (&f)[8][3], T* sacc) {
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) f[c][k] = T(0);
   const T mw2 = mw + mw;
-  simplex3<T, 0, 1, 2, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
-  simplex3<T, 0, 2, 1, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
-  simplex3<T, 1, 0, 2, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
-  simplex3<T, 1, 2, 0, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
-  simplex3<T, 2, 0, 1, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
-  simplex3<T, 2, 1, 0, MACRO, UNI>(u, lw, mw2, mw, ih, sb, f, sacc);
+  T e0[3][3], em[3][3][3], el[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      e0[a][k] = u[1 << a][k] - u[0][k];
+      el[a][k] = u[7][k] - u[7 ^ (1 << a)][k];
+      if (!UNI) {
+        e0[a][k] *= ih[a];
+        el[a][k] *= ih[a];
+      }
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        if (b != a) {
+          em[a][b][k] = u[(1 << a) | (1 << b)][k] - u[1 << a][k];
+          if (!UNI) em[a][b][k] *= ih[b];
+        }
+    }
+  T p0[3][3], pm[3][3][3], pl[3][3];
+  tet3<T, 0, 1, 2, true, true, MACRO>(e0, em, el, lw, mw2, mw, sb, p0, pm, pl, sacc);
+  tet3<T, 0, 2, 1, false, true, MACRO>(e0, em, el, lw, mw2, mw, sb, p0, pm, pl, sacc);
+  tet3<T, 1, 0, 2, true, false, MACRO>(e0, em, el, lw, mw2, mw, sb, p0, pm, pl, sacc);
+  tet3<T, 1, 2, 0, false, true, MACRO>(e0, em, el, lw, mw2, mw, sb, p0, pm, pl, sacc);
+  tet3<T, 2, 0, 1, true, false, MACRO>(e0, em, el, lw, mw2, mw, sb, p0, pm, pl, sacc);
+  tet3<T, 2, 1, 0, false, false, MACRO>(e0, em, el, lw, mw2, mw, sb, p0, pm, pl, sacc);
+  if (!UNI) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        p0[a][k] *= ih[a];
+        pl[a][k] *= ih[a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          if (b != a) pm[a][b][k] *= ih[b];
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f[0][k] = -(p0[0][k] + p0[1][k] + p0[2][k]);
+    f[7][k] = pl[0][k] + pl[1][k] + pl[2][k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      f[1 << a][k] = p0[a][k] - pm[a][b][k] - pm[a][c][k];            // first-edge end, middle-edge starts
+      f[7 ^ (1 << a)][k] = pm[b][c][k] + pm[c][b][k] - pl[a][k];      // middle-edge ends, last-edge start
+    }
+  }
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }

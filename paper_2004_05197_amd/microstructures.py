@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "circle2d", "rsa_spheres", "gaussian_random_field", "two_phase_grf",
-    "lognormal_field", "laminate", "random_cells", "WORKLOADS",
+    "lognormal_field", "laminate", "random_cells", "uneven_cell", "WORKLOADS",
 ]
 
 
@@ -49,7 +49,8 @@ def circle2d(n: int = 32, radius: float = 0.25, E_matrix: float = 1.0,
 
 
 def rsa_spheres(n: int, vf: float, seed: int, rmin: float = 4.0,
-                rmax: float = 8.0, max_reject: int = 1_000_000):
+                rmax: float = 8.0, max_reject: int = 1_000_000,
+                saturate: bool = False):
     """Random sequential addition of non-overlapping periodic spheres.
 
     Radii r ~ U[rmin, rmax] (voxel units), centres ~ U[0, n)^3.  A candidate
@@ -57,6 +58,8 @@ def rsa_spheres(n: int, vf: float, seed: int, rmin: float = 4.0,
     least the sum of the radii.  A voxel is inside a sphere iff the
     minimum-image distance from its centre to the sphere centre is < r.
     Spheres are added until the inclusion voxel fraction reaches ``vf``.
+    After ``max_reject`` rejected candidates the process is saturated: with
+    ``saturate`` the cell keeps the fraction reached, else it raises.
     Returns (mask[bool, (n, n, n)], achieved_vf, list_of_(centre, r)).
     """
     from scipy.spatial import cKDTree
@@ -135,6 +138,8 @@ def rsa_spheres(n: int, vf: float, seed: int, rmin: float = 4.0,
             mask.ravel()[flat] = True
         rejects += int(np.count_nonzero(clash[:kend]))
         if rejects > max_reject:
+            if saturate:
+                break
             raise RuntimeError("rsa_spheres: too many rejections")
         # larger blocks once acceptances become rare
         if accepted_here <= 1:
@@ -203,25 +208,40 @@ def laminate(shape_xyz, axis: int, layer_E, layer_nu, thickness):
     return E, nu
 
 
-def random_cells(count: int, base_seed: int = 1000, sizes=(32, 48, 64, 96),
-                 nu: float = 0.3):
-    """Uneven batch of sphere microstructures.
+def uneven_cell(seed: int, sizes=(32, 48, 64, 96), nu: float = 0.3):
+    """One cell of the uneven batch, all draws from ``seed``: size ~ U(sizes),
+    vf ~ U[0.1, 0.4], contrast ~ U[10, 100], then the sphere seed; spheres
+    with r ~ U[4, 8], E = contrast inside and 1 outside.  A target fraction
+    the small cells cannot reach keeps the saturated fraction.  Returns a
+    dict with keys n, vf, contrast, E, nu, achieved_vf."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.choice(np.asarray(sizes)))
+    vf = float(rng.uniform(0.1, 0.4))
+    contrast = float(rng.uniform(10.0, 100.0))
+    sub_seed = int(rng.integers(0, 2 ** 31 - 1))
+    mask, avf, _ = rsa_spheres(n, vf, sub_seed, saturate=True)
+    E = np.where(mask, contrast, 1.0).astype(np.float64)
+    return dict(n=n, vf=vf, contrast=contrast, E=E, nu=np.full_like(E, nu), achieved_vf=avf)
 
-    Cell k uses seed base_seed + k for all its draws: size ~ U(sizes),
-    vf ~ U[0.1, 0.4], contrast ~ U[10, 100], spheres with r ~ U[4, 8] and
-    E = contrast inside, E = 1 outside.  Yields dicts with keys
-    n, vf, contrast, E, nu, achieved_vf.
-    """
-    for k in range(count):
-        rng = np.random.default_rng(base_seed + k)
-        n = int(rng.choice(np.asarray(sizes)))
-        vf = float(rng.uniform(0.1, 0.4))
-        contrast = float(rng.uniform(10.0, 100.0))
-        sub_seed = int(rng.integers(0, 2 ** 31 - 1))
-        mask, avf, _ = rsa_spheres(n, vf, sub_seed)
-        E = np.where(mask, contrast, 1.0).astype(np.float64)
-        yield dict(n=n, vf=vf, contrast=contrast, E=E,
-                   nu=np.full_like(E, nu), achieved_vf=avf)
+
+def _uneven_cell_args(args):
+    return uneven_cell(*args)
+
+
+def random_cells(count: int, base_seed: int = 1000, sizes=(32, 48, 64, 96),
+                 nu: float = 0.3, workers: int = 1):
+    """Uneven batch of sphere microstructures: cell k is
+    ``uneven_cell(base_seed + k)``.  With workers > 1 the cells are built in
+    that many fresh (spawned) processes; the result does not depend on it."""
+    args = [(base_seed + k, sizes, nu) for k in range(count)]
+    if workers <= 1:
+        for a in args:
+            yield uneven_cell(*a)
+        return
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        yield from ex.map(_uneven_cell_args, args, chunksize=2)
 
 
 def spheres_cell(n: int, vf: float, seed: int, contrast: float,

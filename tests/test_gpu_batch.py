@@ -129,14 +129,14 @@ def test_batch_rejects_mismatched_configs(lib):
 
 
 def voigt_reuss(E, nu, d):
+    """Voigt (mean stiffness) and Reuss (inverse of the mean compliance)
+    bounds over the voxels; D is linear in (lambda, mu), and the compliance
+    mean runs over the distinct (lambda, mu) phases."""
     lam, mu = fem.lame(np.ravel(E), np.ravel(nu))
-    phases = {}
-    for l, m in zip(lam, mu):
-        phases[(l, m)] = phases.get((l, m), 0) + 1
-    tot = sum(phases.values())
-    V = sum(c * fem.D_voigt(l, m, d) for (l, m), c in phases.items()) / tot
-    R = np.linalg.inv(sum(c * np.linalg.inv(fem.D_voigt(l, m, d)) for (l, m), c in phases.items()) / tot)
-    return V, R
+    V = fem.D_voigt(lam.mean(), mu.mean(), d)
+    ph, cnt = np.unique(lam + 1j * mu, return_counts=True)
+    S = sum(k * np.linalg.inv(fem.D_voigt(p.real, p.imag, d)) for p, k in zip(ph, cnt)) / cnt.sum()
+    return V, np.linalg.inv(S)
 
 
 def test_uneven_workload_mixed(lib):
