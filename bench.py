@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
+    ap.add_argument("--schedule", default=None,
+                    help="six comma-separated ints: use this kernel schedule instead of tuning")
     ap.add_argument("--workload", default="grf3d", choices=["grf3d", "uneven"],
                     help="grf3d: the 256^3 headline workload; uneven: the batch of sphere cells")
     ap.add_argument("--cells", type=int, default=512, help="cells of the uneven batch")
@@ -224,8 +226,10 @@ def main():
     # ---------------------------------------------------------------- mixed
     cell = B.Cell((n1, n1, n1), precision=B.MIXED, tol=1e-6)
     cell.set_material(Ed, nud)
+    if args.schedule:
+        cell.schedule = tuple(int(v) for v in args.schedule.split(","))
     sched = cell.schedule
-    if not args.no_tune:
+    if not args.no_tune and not args.schedule:
         t_tune = time.perf_counter()
         sched = cell.autotune()
         progress(f"autotune: schedule {sched} in {time.perf_counter() - t_tune:.2f} s")

@@ -389,13 +389,12 @@ __device__ __forceinline__ T redot(const cpx<T>* r, const cpx<T>* z) {
 }
 
 // ===================================================== z pass (3D, last)
-template <typename T, int N, int V, int RP>
-__global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
-  constexpr int TX = z_tx<T, V>();
+template <typename T, int N, int TX, int RP, int NTH>
+__global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
   constexpr int NC = 3 * TX;  // columns: component-major, then slot
   __shared__ cpx<T> buf[N * NC];
   __shared__ cpx<T> tws[N];
-  __shared__ double sh[NTZ / WAVE];
+  __shared__ double sh[NTH / WAVE];
   // logical item = (y, slot tile, load), load fastest: the load cases of a
   // tile share its symbol-table lines and neighbouring tiles (which share
   // 128-byte spectrum lines) stay close, all on one XCD
@@ -411,21 +410,21 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
   const int y = pb / ntile;
   const int s0 = tile * TX;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NTZ) tws[i] = a.tw[i];
+  for (int i = tid; i < N; i += NTH) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
   const long long cstride = (long long)a.nz * a.ny * M;   // component
   const long long zstride = (long long)a.ny * M;          // z plane
-  for (int e = tid; e < N * NC; e += NTZ) {
+  for (int e = tid; e < N * NC; e += NTH) {
     const int z = e / NC, rem = e - z * NC;
     const int c = rem / TX, s = rem - c * TX;
     buf[e] = (s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
-  fft_lds<T, N, false, NC, NTZ, 1, ColTile<NC>, RP>(buf, tws);
+  fft_lds<T, N, false, NC, NTH, 1, ColTile<NC>, RP>(buf, tws);
   const bool pair_row = (s0 == 0) && (y == 0 || y == a.ny / 2);
   double acc = 0.0;
   // ordinary wavevectors (weight 2: each stands for itself and its conjugate)
-  for (int e = tid; e < N * TX; e += NTZ) {
+  for (int e = tid; e < N * TX; e += NTH) {
     const int kz = e / TX, s = e - kz * TX;
     const int slot = s0 + s;
     if (slot >= M || (slot == 0 && pair_row)) continue;
@@ -448,12 +447,12 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
     // column slot 0 of rows ky = 0, ny/2: w = A_hat + i B_hat with A, B real
     // along z; A: (kx, ky) = (0 | M, 0), B: (0 | M, ny/2).
     const int kxf = (y == 0) ? 0 : M;
-    constexpr int Q = (N + NTZ - 1) / NTZ;
+    constexpr int Q = (N + NTH - 1) / NTH;
     cpx<T> out[Q][3];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int kz = tid + q * NTZ;
+      const int kz = tid + q * NTH;
       if (kz < N) {
         const int km = (N - kz) % N;
         cpx<T> A[3], B[3], zA[3], zB[3];
@@ -486,7 +485,7 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int kz = tid + q * NTZ;
+      const int kz = tid + q * NTH;
       if (kz < N) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) buf[kz * NC + c * TX] = out[q][c];
@@ -494,13 +493,13 @@ __global__ __launch_bounds__(NTZ) void k_zpass(PArgs<T> a) {
     }
   }
   __syncthreads();
-  fft_lds<T, N, true, NC, NTZ, 1, ColTile<NC>, RP>(buf, tws);
-  for (int e = tid; e < N * NC; e += NTZ) {
+  fft_lds<T, N, true, NC, NTH, 1, ColTile<NC>, RP>(buf, tws);
+  for (int e = tid; e < N * NC; e += NTH) {
     const int z = e / NC, rem = e - z * NC;
     const int c = rem / TX, s = rem - c * TX;
     if (s0 + s < M) base[c * cstride + z * zstride + s] = buf[e];
   }
-  const double bs = block_sum<NTZ>(acc, sh);
+  const double bs = block_sum<NTH>(acc, sh);
   if (tid == 0) a.red.slot_parts(RED_RZ, l)[pb] = bs;
 }
 
@@ -658,7 +657,8 @@ hipError_t launch_finalize(const RedBuf& red, LoadState* st, double* res2, int s
 }
 
 int last_pass_blocks(int dim, int nx, int ny, bool fp64, const Sched& sc) {
-  const int TX = (fp64 ? 4 : 8) >> (sc.z_var ? 1 : 0);
+  const int B = fp64 ? 4 : 8;
+  const int TX = dim == 2 ? B >> (sc.z_var & 1) : (sc.z_var == 1 ? B / 2 : sc.z_var == 3 ? 2 * B : B);
   const int ntile = (nx / 2 + TX - 1) / TX;
   return dim == 3 ? ntile * ny : ntile;
 }
@@ -746,13 +746,12 @@ hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, const Sched&
   return sc.y_var ? launch_ypass_v<T, 1>(a, inverse, nload, s) : launch_ypass_v<T, 0>(a, inverse, nload, s);
 }
 
-template <typename T, int V, int RP>
+template <typename T, int TX, int RP, int NTH>
 static hipError_t launch_zpass_v(const PArgs<T>& a, int nload, hipStream_t s) {
-  constexpr int TX = z_tx<T, V>();
   const int ntile = (a.nx / 2 + TX - 1) / TX;
   dim3 grid(xcd_grid(ntile * a.ny * nload));
   switch (a.nz) {
-#define C_(n) case n: hipLaunchKernelGGL((k_zpass<T, n, V, RP>), grid, dim3(NTZ), 0, s, a); break;
+#define C_(n) case n: hipLaunchKernelGGL((k_zpass<T, n, TX, RP, NTH>), grid, dim3(NTH), 0, s, a); break;
     CELLFFT_NSIZES(C_)
 #undef C_
     default:
@@ -778,11 +777,23 @@ static hipError_t launch_ylast_v(const PArgs<T>& a, int nload, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_last(const PArgs<T>& a, int dim, int nload, const Sched& sc, hipStream_t s) {
+  // z_var (3D): columns x threads per block = B x 512, B/2 x 512, B x 768,
+  // 2B x 1024 with B = 8 (fp32) / 4 (fp64); wider column tiles read longer
+  // row segments of each z plane, more threads hide more latency
   if (dim == 3) {
-    if (sc.z_var) return sc.z_radix ? launch_zpass_v<T, 1, 1>(a, nload, s) : launch_zpass_v<T, 1, 0>(a, nload, s);
-    return sc.z_radix ? launch_zpass_v<T, 0, 1>(a, nload, s) : launch_zpass_v<T, 0, 0>(a, nload, s);
+    constexpr int B = sizeof(T) == 4 ? 8 : 4;
+    switch (sc.z_var * 2 + sc.z_radix) {
+      case 0: return launch_zpass_v<T, B, 0, NTZ>(a, nload, s);
+      case 1: return launch_zpass_v<T, B, 1, NTZ>(a, nload, s);
+      case 2: return launch_zpass_v<T, B / 2, 0, NTZ>(a, nload, s);
+      case 3: return launch_zpass_v<T, B / 2, 1, NTZ>(a, nload, s);
+      case 4: return launch_zpass_v<T, B, 0, 768>(a, nload, s);
+      case 5: return launch_zpass_v<T, B, 1, 768>(a, nload, s);
+      case 6: return launch_zpass_v<T, 2 * B, 0, 1024>(a, nload, s);
+      default: return launch_zpass_v<T, 2 * B, 1, 1024>(a, nload, s);
+    }
   }
-  return sc.z_var ? launch_ylast_v<T, 1>(a, nload, s) : launch_ylast_v<T, 0>(a, nload, s);
+  return (sc.z_var & 1) ? launch_ylast_v<T, 1>(a, nload, s) : launch_ylast_v<T, 0>(a, nload, s);
 }
 
 template <typename T>

@@ -38,7 +38,9 @@ struct Sched {
   int x_var = 0;    // x passes: rows per block = 2048 / (nx/2) (0) or 1024 / (nx/2) (1)
                     // complex values (fp64: 1024, 512)
   int y_var = 0;    // y pass columns per block: 16 (0) or 8 (1) (fp64: 8, 4)
-  int z_var = 0;    // last pass columns per block: 8 (0) or 4 (1) (fp64: 4, 2)
+  int z_var = 0;    // last pass columns x threads per block: 8 x 512 (0), 4 x 512 (1),
+                    // 3D also 8 x 768 (2), 16 x 1024 (3) (fp64 half the columns);
+                    // 2D: 2, 3 as 0, 1
   int z_radix = 0;  // last pass radix order: radix 8 first (0) or radix 4 first (1)
 };
 constexpr int SCHED_NFIELD = 6;

@@ -980,7 +980,7 @@ void sched_to_ints(const Sched& sc, int* v) {
 
 bool sched_from_ints(const int* v, Sched* sc) {
   const bool ok = v[0] >= 0 && v[0] < ST_NTILE && (v[1] == 8 || v[1] == 16 || v[1] == 32 || v[1] == 64) &&
-                  (v[2] == 0 || v[2] == 1) && (v[3] == 0 || v[3] == 1) && (v[4] == 0 || v[4] == 1) &&
+                  (v[2] == 0 || v[2] == 1) && (v[3] == 0 || v[3] == 1) && (v[4] >= 0 && v[4] <= 3) &&
                   (v[5] == 0 || v[5] == 1);
   if (!ok) return false;
   sc->st_tile = v[0];
@@ -1184,9 +1184,9 @@ cell_status tune_t(cell_s* c) {
       }
     }
   }
-  // last pass: columns per block x radix order
+  // last pass: columns and threads per block x radix order
   bms = 1e300;
-  for (int v = 0; v < 2; ++v)
+  for (int v = 0; v < (c->d == 3 ? 4 : 2); ++v)
     for (int rp = 0; rp < (c->d == 3 ? 2 : 1); ++rp) {
       Sched sc = best;
       sc.z_var = v;

@@ -961,9 +961,9 @@ int max_reduction_blocks(const Geom& g) {
   int mb = 0;
   const int nrows = g.dim * g.ny * g.nz;
   for (int fp64 = 0; fp64 < 2; ++fp64) {
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < 4; ++v) {
       Sched sc;
-      sc.x_var = v;
+      sc.x_var = v & 1;
       sc.z_var = v;
       mb = std::max(mb, xpass_blocks(g.nx, nrows, fp64, sc));
       mb = std::max(mb, last_pass_blocks(g.dim, g.nx, g.ny, fp64, sc));
