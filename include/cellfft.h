@@ -177,11 +177,12 @@ cell_status cell_profile_read(cell_t c, double* ms_out, long long* launches_out)
  * does not divide the grid falls back to the first one that does, or to the
  * runtime tile), stencil z
  * extent (8, 16, 32, 64), x-pass rows per block (0: 2048/(N_x/2) complex
- * values, 1: half; fp64 half of these), y-pass columns per block (0: 16,
- * 1: 8; fp64 8, 4), last pass columns x threads per block (0: 8 x 512,
+ * values, 1: half; fp64 half of these; 2, 3: the same with radix 16 first),
+ * y-pass columns per block (0: 16, 1: 8; fp64 8, 4; 2, 3: the same with
+ * radix 16 first), last pass columns x threads per block (0: 8 x 512,
  * 1: 4 x 512, 3D also 2: 8 x 768, 3: 16 x 1024; fp64 half the columns; 2D
  * takes 2, 3 as 0, 1), last-pass
- * radix order (0: radix 8 first, 1: radix 4 first).  Default
+ * radix order (0: radix 8 first, 1: radix 16 first).  Default
  * {0, 32, 0, 0, 0, 0}.
  *
  * cell_autotune times every variant on the handle's own buffers (material

@@ -153,11 +153,49 @@ template <typename T, bool INV> struct Dft<T, 8, INV> {
   }
 };
 
+// 16-point DFT as 4 x 4: four 4-point DFTs over n1 (n = 4 n1 + n2), the
+// twiddles W16^(n2 k1), four 4-point DFTs over n2; output k = k1 + 4 k2.
+// W16^m = exp(-+ 2 pi i m / 16) with the sign of the transform.
+template <typename T, bool INV> struct Dft<T, 16, INV> {
+  static __device__ __forceinline__ cpx<T> tw(cpx<T> a, T c, T s) {
+    // a * (c - i s) forward, a * (c + i s) inverse
+    return INV ? mk<T>(a.re * c - a.im * s, a.im * c + a.re * s) : mk<T>(a.re * c + a.im * s, a.im * c - a.re * s);
+  }
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);  // cos, sin of pi/8
+    const T r = T(0.70710678118654752440);
+    cpx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cpx<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Dft<T, 4, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = t[k1];
+    }
+    a[1][1] = tw(a[1][1], c1, s1);   // W^1
+    a[1][2] = tw(a[1][2], r, r);     // W^2
+    a[1][3] = tw(a[1][3], s1, c1);   // W^3
+    a[2][1] = tw(a[2][1], r, r);     // W^2
+    a[2][2] = mul_mi<T, INV>(a[2][2]);  // W^4
+    a[2][3] = tw(a[2][3], -r, r);    // W^6
+    a[3][1] = tw(a[3][1], s1, c1);   // W^3
+    a[3][2] = tw(a[3][2], -r, r);    // W^6
+    a[3][3] = tw(a[3][3], -c1, -s1);  // W^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cpx<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<T, 4, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
 // radix schedules: RP = 0: 8 first (except 16 = 4*4), then 4, 2, 3;
-// RP = 1: 4 first, then 2, 3 (more, cheaper stages)
+// RP = 1: 16 first, then as RP = 0 (fewer, larger stages)
 __host__ __device__ constexpr int pick_radix(int n, int rp = 0) {
-  return rp == 0 ? ((n % 8 == 0 && n != 16) ? 8 : (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : n)
-                 : ((n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : n);
+  return (rp == 1 && n % 16 == 0) ? 16
+                                  : ((n % 8 == 0 && n != 16) ? 8 : (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : n);
 }
 
 // Tile layouts.  ColMajorTile: element (n, c) at n*CS + c (columns fastest,
@@ -169,6 +207,14 @@ template <int CS> struct ColTile {
 };
 template <int RS> struct RowTile {
   static __device__ __forceinline__ int at(int n, int c) { return c * RS + n; }
+  static constexpr bool col_fast = false;
+};
+// RowTile with one padding element after every 8: the radix-8 Stockham
+// writes (stride 8 complex values) then fall on distinct LDS banks.
+// Rows need RS >= N + N/8.
+__host__ __device__ constexpr int pad8(int n) { return n + (n >> 3); }
+template <int RS> struct RowTileP {
+  static __device__ __forceinline__ int at(int n, int c) { return c * RS + pad8(n); }
   static constexpr bool col_fast = false;
 };
 

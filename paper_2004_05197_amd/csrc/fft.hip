@@ -49,10 +49,10 @@ constexpr int NTY = 512;
 constexpr int NTZ = 512;
 
 // ================================================================= x forward
-template <typename T, int M, int V>
+template <typename T, int M, int V, int RP>
 __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
   constexpr int RPB = x_rpb<T, M, V>();
-  constexpr int RS = M + 1;
+  constexpr int RS = pad8(M) + 1;  // padded rows (RowTileP)
   using T2 = typename V2<T>::type;
   __shared__ cpx<T> buf[RPB * RS];
   __shared__ cpx<T> tws[2 * M];
@@ -81,10 +81,10 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
       acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
       v = {rv.x, rv.y};
     }
-    buf[rr * RS + m] = v;
+    buf[rr * RS + pad8(m)] = v;
   }
   __syncthreads();
-  fft_lds<T, M, false, RPB, NT, 2, RowTile<RS>>(buf, tws);
+  fft_lds<T, M, false, RPB, NT, 2, RowTileP<RS>, RP>(buf, tws);
   // split the half-length transform into the packed real spectrum
   constexpr int KH = M / 2 + 1;
   for (int e = tid; e < RPB * KH; e += NT) {
@@ -94,13 +94,13 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
       const cpx<T> z0 = Z[0];
       Z[0] = {z0.re + z0.im, z0.re - z0.im};
     } else {
-      const cpx<T> zk = Z[k], zm = Z[M - k];
+      const cpx<T> zk = Z[pad8(k)], zm = Z[pad8(M - k)];
       const cpx<T> E = (zk + conj(zm)) * T(0.5);
       const cpx<T> D = (zk - conj(zm)) * T(0.5);
       const cpx<T> O = {D.im, -D.re};  // D / i
       const cpx<T> WO = cmul(tws[k], O);
-      Z[k] = E + WO;
-      if (M - k != k) Z[M - k] = conj(E - WO);
+      Z[pad8(k)] = E + WO;
+      if (M - k != k) Z[pad8(M - k)] = conj(E - WO);
     }
   }
   __syncthreads();
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
   for (int e = tid; e < RPB * M; e += NT) {
     const int rr = e / M, m = e - rr * M;
     const int row = row0 + rr;
-    if (row < a.nrows) S[(long long)row * M + m] = buf[rr * RS + m];
+    if (row < a.nrows) S[(long long)row * M + m] = buf[rr * RS + pad8(m)];
   }
   // ||r||^2 partial of this block (finalised by k_finalize)
   const double bs = block_sum<NT>(acc, sh);
@@ -116,10 +116,10 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
 }
 
 // ================================================================= x inverse
-template <typename T, int M, int V>
+template <typename T, int M, int V, int RP>
 __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
   constexpr int RPB = x_rpb<T, M, V>();
-  constexpr int RS = M + 1;
+  constexpr int RS = pad8(M) + 1;  // padded rows (RowTileP)
   using T2 = typename V2<T>::type;
   __shared__ cpx<T> buf[RPB * RS];
   __shared__ cpx<T> tws[2 * M];
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
   for (int e = tid; e < RPB * M; e += NT) {
     const int rr = e / M, m = e - rr * M;
     const int row = row0 + rr;
-    buf[rr * RS + m] = row < a.nrows ? S[(long long)row * M + m] : cpx<T>{T(0), T(0)};
+    buf[rr * RS + pad8(m)] = row < a.nrows ? S[(long long)row * M + m] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
   constexpr int KH = M / 2 + 1;
@@ -146,15 +146,15 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
       const cpx<T> x0 = X[0];
       X[0] = {x0.re + x0.im, x0.re - x0.im};
     } else {
-      const cpx<T> xk = X[k], xm = X[M - k];
+      const cpx<T> xk = X[pad8(k)], xm = X[pad8(M - k)];
       const cpx<T> E = xk + conj(xm);
       const cpx<T> O = cmul(xk - conj(xm), conj(tws[k]));
-      X[k] = {E.re - O.im, E.im + O.re};  // E + i O
-      if (M - k != k) X[M - k] = {E.re + O.im, -E.im + O.re};  // conj(E) + i conj(O)
+      X[pad8(k)] = {E.re - O.im, E.im + O.re};  // E + i O
+      if (M - k != k) X[pad8(M - k)] = {E.re + O.im, -E.im + O.re};  // conj(E) + i conj(O)
     }
   }
   __syncthreads();
-  fft_lds<T, M, true, RPB, NT, 2, RowTile<RS>>(buf, tws);
+  fft_lds<T, M, true, RPB, NT, 2, RowTileP<RS>, RP>(buf, tws);
   T2* x2 = reinterpret_cast<T2*>(a.x + l * a.lstride);
   T2* p2 = reinterpret_cast<T2*>(a.p + l * a.lstride);
   for (int e = tid; e < RPB * M; e += NT) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
     const int row = row0 + rr;
     if (row < a.nrows) {
       const long long off = (long long)row * M + m;
-      const cpx<T> z = buf[rr * RS + m];
+      const cpx<T> z = buf[rr * RS + pad8(m)];
       const T2 po = p2[off];
       T2 xv = x2[off];
       xv.x += alpha * po.x;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
 }
 
 // ================================================================= y pass 3D
-template <typename T, int N, bool INV, int V>
+template <typename T, int N, bool INV, int V, int RP>
 __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
   constexpr int TX = y_tx<T, V>();
   __shared__ cpx<T> buf[N * TX];
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
     }
     __syncthreads();
   }
-  fft_lds<T, N, INV, TX, NTY, 1, ColTile<TX>>(buf, tws);
+  fft_lds<T, N, INV, TX, NTY, 1, ColTile<TX>, RP>(buf, tws);
   if (!INV && s0 == 0) {
     // unmix column 0 into the X[0] field (rows < N/2) and X[nx/2] field
     cpx<T> v[(N + NTY - 1) / NTY];
@@ -389,40 +389,18 @@ __device__ __forceinline__ T redot(const cpx<T>* r, const cpx<T>* z) {
 }
 
 // ===================================================== z pass (3D, last)
+// One tile (slot columns s0..s0+TX-1 of row y, 3 components, all kz) held in
+// LDS: forward FFT along z, z_hat = K_ref^{-1} r_hat / n (table or closed
+// form), r.z partial (Parseval weights) into acc, inverse FFT.  Called by
+// every thread of the block; ends with a barrier.
 template <typename T, int N, int TX, int RP, int NTH>
-__global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
-  constexpr int NC = 3 * TX;  // columns: component-major, then slot
-  __shared__ cpx<T> buf[N * NC];
-  __shared__ cpx<T> tws[N];
-  __shared__ double sh[NTH / WAVE];
-  // logical item = (y, slot tile, load), load fastest: the load cases of a
-  // tile share its symbol-table lines and neighbouring tiles (which share
-  // 128-byte spectrum lines) stay close, all on one XCD
+__device__ __forceinline__ void zpass_tile(const PArgs<T>& a, int l, int y, int s0, cpx<T>* buf,
+                                           const cpx<T>* tws, double& acc) {
+  constexpr int NC = 3 * TX;
   const int M = a.nx / 2;
-  const int ntile = (M + TX - 1) / TX;
-  const int per_load = ntile * a.ny;
-  const int item = xcd_order(blockIdx.x, per_load * a.nload);
-  if (item < 0) return;
-  const int l = item % a.nload;
-  const int pb = item / a.nload;  // partial index within the load
-  if (!load_live(a.st + l, true)) return;
-  const int tile = pb % ntile;
-  const int y = pb / ntile;
-  const int s0 = tile * TX;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NTH) tws[i] = a.tw[i];
-  cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
-  const long long cstride = (long long)a.nz * a.ny * M;   // component
-  const long long zstride = (long long)a.ny * M;          // z plane
-  for (int e = tid; e < N * NC; e += NTH) {
-    const int z = e / NC, rem = e - z * NC;
-    const int c = rem / TX, s = rem - c * TX;
-    buf[e] = (s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
-  }
-  __syncthreads();
   fft_lds<T, N, false, NC, NTH, 1, ColTile<NC>, RP>(buf, tws);
   const bool pair_row = (s0 == 0) && (y == 0 || y == a.ny / 2);
-  double acc = 0.0;
   // ordinary wavevectors (weight 2: each stands for itself and its conjugate)
   for (int e = tid; e < N * TX; e += NTH) {
     const int kz = e / TX, s = e - kz * TX;
@@ -494,6 +472,41 @@ __global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
   }
   __syncthreads();
   fft_lds<T, N, true, NC, NTH, 1, ColTile<NC>, RP>(buf, tws);
+}
+
+// logical item = (y, slot tile, load), load fastest: the load cases of a
+// tile share its symbol-table lines and neighbouring tiles (which share
+// 128-byte spectrum lines) stay close, all on one XCD
+template <typename T, int N, int TX, int RP, int NTH>
+__global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
+  constexpr int NC = 3 * TX;  // columns: component-major, then slot
+  __shared__ cpx<T> buf[N * NC];
+  __shared__ cpx<T> tws[N];
+  __shared__ double sh[NTH / WAVE];
+  const int M = a.nx / 2;
+  const int ntile = (M + TX - 1) / TX;
+  const int per_load = ntile * a.ny;
+  const int item = xcd_order(blockIdx.x, per_load * a.nload);
+  if (item < 0) return;
+  const int l = item % a.nload;
+  const int pb = item / a.nload;  // partial index within the load
+  if (!load_live(a.st + l, true)) return;
+  const int tile = pb % ntile;
+  const int y = pb / ntile;
+  const int s0 = tile * TX;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NTH) tws[i] = a.tw[i];
+  cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
+  const long long cstride = (long long)a.nz * a.ny * M;   // component
+  const long long zstride = (long long)a.ny * M;          // z plane
+  for (int e = tid; e < N * NC; e += NTH) {
+    const int z = e / NC, rem = e - z * NC;
+    const int c = rem / TX, s = rem - c * TX;
+    buf[e] = (s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
+  }
+  __syncthreads();
+  double acc = 0.0;
+  zpass_tile<T, N, TX, RP, NTH>(a, l, y, s0, buf, tws, acc);
   for (int e = tid; e < N * NC; e += NTH) {
     const int z = e / NC, rem = e - z * NC;
     const int c = rem / TX, s = rem - c * TX;
@@ -680,15 +693,15 @@ bool fft_size_ok(int n) {
 
 int xpass_blocks(int nx, int nrows, bool fp64, const Sched& sc) {
   const int M = nx / 2;
-  const int tgt = (fp64 ? 1024 : 2048) >> (sc.x_var ? 1 : 0);
+  const int tgt = (fp64 ? 1024 : 2048) >> (sc.x_var & 1);
   const int rpb = (tgt / M) < 1 ? 1 : tgt / M;
   return (nrows + rpb - 1) / rpb;
 }
 
-template <typename T, int V>
+template <typename T, int V, int RP>
 static hipError_t launch_xfwd_v(const XArgs<T>& a, int nx, dim3 grid, hipStream_t s) {
   switch (nx / 2) {
-#define C_(m) case m: hipLaunchKernelGGL((k_xfwd<T, m, V>), grid, dim3(NT), 0, s, a); break;
+#define C_(m) case m: hipLaunchKernelGGL((k_xfwd<T, m, V, RP>), grid, dim3(NT), 0, s, a); break;
     CELLFFT_MSIZES(C_)
 #undef C_
     default:
@@ -697,10 +710,10 @@ static hipError_t launch_xfwd_v(const XArgs<T>& a, int nx, dim3 grid, hipStream_
   return hipGetLastError();
 }
 
-template <typename T, int V>
+template <typename T, int V, int RP>
 static hipError_t launch_xinv_v(const XArgs<T>& a, int nx, dim3 grid, hipStream_t s) {
   switch (nx / 2) {
-#define C_(m) case m: hipLaunchKernelGGL((k_xinv<T, m, V>), grid, dim3(NT), 0, s, a); break;
+#define C_(m) case m: hipLaunchKernelGGL((k_xinv<T, m, V, RP>), grid, dim3(NT), 0, s, a); break;
     CELLFFT_MSIZES(C_)
 #undef C_
     default:
@@ -712,16 +725,26 @@ static hipError_t launch_xinv_v(const XArgs<T>& a, int nx, dim3 grid, hipStream_
 template <typename T>
 hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, const Sched& sc, hipStream_t s) {
   const dim3 grid(xpass_blocks(nx, a.nrows, sizeof(T) == 8, sc), nload);
-  return sc.x_var ? launch_xfwd_v<T, 1>(a, nx, grid, s) : launch_xfwd_v<T, 0>(a, nx, grid, s);
+  switch (sc.x_var) {
+    case 0: return launch_xfwd_v<T, 0, 0>(a, nx, grid, s);
+    case 1: return launch_xfwd_v<T, 1, 0>(a, nx, grid, s);
+    case 2: return launch_xfwd_v<T, 0, 1>(a, nx, grid, s);
+    default: return launch_xfwd_v<T, 1, 1>(a, nx, grid, s);
+  }
 }
 
 template <typename T>
 hipError_t launch_xinv(const XArgs<T>& a, int nx, int nload, const Sched& sc, hipStream_t s) {
   const dim3 grid(xpass_blocks(nx, a.nrows, sizeof(T) == 8, sc), nload);
-  return sc.x_var ? launch_xinv_v<T, 1>(a, nx, grid, s) : launch_xinv_v<T, 0>(a, nx, grid, s);
+  switch (sc.x_var) {
+    case 0: return launch_xinv_v<T, 0, 0>(a, nx, grid, s);
+    case 1: return launch_xinv_v<T, 1, 0>(a, nx, grid, s);
+    case 2: return launch_xinv_v<T, 0, 1>(a, nx, grid, s);
+    default: return launch_xinv_v<T, 1, 1>(a, nx, grid, s);
+  }
 }
 
-template <typename T, int V>
+template <typename T, int V, int RP>
 static hipError_t launch_ypass_v(const YArgs<T>& a, bool inverse, int nload, hipStream_t s) {
   constexpr int TX = y_tx<T, V>();
   const int M = a.nx / 2;
@@ -730,8 +753,8 @@ static hipError_t launch_ypass_v(const YArgs<T>& a, bool inverse, int nload, hip
   switch (a.ny) {
 #define C_(n)                                                                     \
   case n:                                                                         \
-    if (inverse) hipLaunchKernelGGL((k_ypass<T, n, true, V>), grid, dim3(NTY), 0, s, a); \
-    else hipLaunchKernelGGL((k_ypass<T, n, false, V>), grid, dim3(NTY), 0, s, a);       \
+    if (inverse) hipLaunchKernelGGL((k_ypass<T, n, true, V, RP>), grid, dim3(NTY), 0, s, a); \
+    else hipLaunchKernelGGL((k_ypass<T, n, false, V, RP>), grid, dim3(NTY), 0, s, a);       \
     break;
     CELLFFT_NSIZES(C_)
 #undef C_
@@ -743,7 +766,12 @@ static hipError_t launch_ypass_v(const YArgs<T>& a, bool inverse, int nload, hip
 
 template <typename T>
 hipError_t launch_ypass(const YArgs<T>& a, bool inverse, int nload, const Sched& sc, hipStream_t s) {
-  return sc.y_var ? launch_ypass_v<T, 1>(a, inverse, nload, s) : launch_ypass_v<T, 0>(a, inverse, nload, s);
+  switch (sc.y_var) {
+    case 0: return launch_ypass_v<T, 0, 0>(a, inverse, nload, s);
+    case 1: return launch_ypass_v<T, 1, 0>(a, inverse, nload, s);
+    case 2: return launch_ypass_v<T, 0, 1>(a, inverse, nload, s);
+    default: return launch_ypass_v<T, 1, 1>(a, inverse, nload, s);
+  }
 }
 
 template <typename T, int TX, int RP, int NTH>

@@ -35,13 +35,15 @@ struct Sched {
                     // that does not divide the grid falls back to the first that
                     // does, else to the runtime-tile kernel
   int st_tz = 32;   // z extent of a stencil tile (8, 16, 32 or 64)
-  int x_var = 0;    // x passes: rows per block = 2048 / (nx/2) (0) or 1024 / (nx/2) (1)
-                    // complex values (fp64: 1024, 512)
-  int y_var = 0;    // y pass columns per block: 16 (0) or 8 (1) (fp64: 8, 4)
+  int x_var = 0;    // x passes: rows per block = 2048 / (nx/2) (0, 2) or 1024 / (nx/2)
+                    // (1, 3) complex values (fp64: 1024, 512); radix 8 first (0, 1)
+                    // or radix 16 first (2, 3)
+  int y_var = 0;    // y pass columns per block: 16 (0, 2) or 8 (1, 3) (fp64: 8, 4);
+                    // radix 8 first (0, 1) or radix 16 first (2, 3)
   int z_var = 0;    // last pass columns x threads per block: 8 x 512 (0), 4 x 512 (1),
-                    // 3D also 8 x 768 (2), 16 x 1024 (3) (fp64 half the columns);
-                    // 2D: 2, 3 as 0, 1
-  int z_radix = 0;  // last pass radix order: radix 8 first (0) or radix 4 first (1)
+                    // 3D also 8 x 768 (2), 16 x 1024 (3)
+                    // (fp64 half the columns); 2D: 2, 3 as 0, 1
+  int z_radix = 0;  // last pass radix order: radix 8 first (0) or radix 16 first (1)
 };
 constexpr int SCHED_NFIELD = 6;
 constexpr int ST_NTILE = 5;

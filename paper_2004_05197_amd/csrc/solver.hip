@@ -980,7 +980,7 @@ void sched_to_ints(const Sched& sc, int* v) {
 
 bool sched_from_ints(const int* v, Sched* sc) {
   const bool ok = v[0] >= 0 && v[0] < ST_NTILE && (v[1] == 8 || v[1] == 16 || v[1] == 32 || v[1] == 64) &&
-                  (v[2] == 0 || v[2] == 1) && (v[3] == 0 || v[3] == 1) && (v[4] >= 0 && v[4] <= 3) &&
+                  (v[2] >= 0 && v[2] <= 3) && (v[3] >= 0 && v[3] <= 3) && (v[4] >= 0 && v[4] <= 3) &&
                   (v[5] == 0 || v[5] == 1);
   if (!ok) return false;
   sc->st_tile = v[0];
@@ -1154,7 +1154,7 @@ cell_status tune_t(cell_s* c) {
   }
   // x passes (forward and inverse together)
   bms = 1e300;
-  for (int v = 0; v < 2; ++v) {
+  for (int v = 0; v < 4; ++v) {
     Sched sc = best;
     sc.x_var = v;
     STCHK(tm.time([&]() -> cell_status {
@@ -1170,7 +1170,7 @@ cell_status tune_t(cell_s* c) {
   // y pass (3D; forward and inverse)
   if (c->d == 3) {
     bms = 1e300;
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < 4; ++v) {
       Sched sc = best;
       sc.y_var = v;
       STCHK(tm.time([&]() -> cell_status {

@@ -50,7 +50,7 @@ def test_operator_every_stencil_variant(lib, shape, tile, tz, prec, tol):
     assert relerr(q, ref) < tol
 
 
-FFT_VARIANTS = [(x, y, z, rp) for x in (0, 1) for y in (0, 1) for z in (0, 1, 2, 3) for rp in (0, 1)]
+FFT_VARIANTS = [(x, y, z, rp) for x in (0, 1, 2, 3) for y in (0, 1, 2, 3) for z in (0, 1, 2, 3) for rp in (0, 1)]
 
 
 @pytest.mark.parametrize("shape", [(64, 32, 24), (48, 96, 16), (32, 48), (96, 8)])
@@ -88,8 +88,8 @@ def test_solve_under_other_schedules(lib):
 
 def test_schedule_validation(lib):
     with lib.Cell((16, 16, 16)) as c:
-        for bad in [(5, 32, 0, 0, 0, 0), (0, 12, 0, 0, 0, 0), (0, 32, 2, 0, 0, 0), (0, 32, 0, 0, 4, 0),
-                    (0, 32, 0, 0, 0, -1)]:
+        for bad in [(5, 32, 0, 0, 0, 0), (0, 12, 0, 0, 0, 0), (0, 32, 4, 0, 0, 0), (0, 32, 0, 4, 0, 0),
+                    (0, 32, 0, 0, 4, 0), (0, 32, 0, 0, 0, -1), (0, 32, 0, 0, 0, 2)]:
             with pytest.raises(lib.CellError) as e:
                 c.schedule = bad
             assert e.value.status == lib.CELL_E_ARG
