@@ -63,7 +63,10 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
   const T alpha = (T)st->alpha;
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * M; i += NT) tws[i] = a.tw[i];
-  const int row0 = blockIdx.x * RPB;
+  // XCD order: consecutive row groups (contiguous memory) on one XCD
+  const int rb = xcd_order(blockIdx.x, (a.nrows + RPB - 1) / RPB);
+  if (rb < 0) return;
+  const int row0 = rb * RPB;
   T2* r2 = reinterpret_cast<T2*>(a.r + l * a.lstride);
   const T2* q2 = reinterpret_cast<const T2*>(a.q + l * a.lstride);
   double acc = 0.0;
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
   }
   // ||r||^2 partial of this block (finalised by k_finalize)
   const double bs = block_sum<NT>(acc, sh);
-  if (tid == 0) a.red.slot_parts(RED_RR, l)[blockIdx.x] = bs;
+  if (tid == 0) a.red.slot_parts(RED_RR, l)[rb] = bs;
 }
 
 // ================================================================= x inverse
@@ -130,7 +133,10 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
   const T beta = (T)st->beta;
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * M; i += NT) tws[i] = a.tw[i];
-  const int row0 = blockIdx.x * RPB;
+  // XCD order: consecutive row groups (contiguous memory) on one XCD
+  const int rb = xcd_order(blockIdx.x, (a.nrows + RPB - 1) / RPB);
+  if (rb < 0) return;
+  const int row0 = rb * RPB;
   const cpx<T>* S = a.S + l * (a.lstride / 2);
   for (int e = tid; e < RPB * M; e += NT) {
     const int rr = e / M, m = e - rr * M;
@@ -186,7 +192,10 @@ __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
   if (!load_live(a.st + l, true)) return;
   const int M = a.nx / 2;
   const int ntile = (M + TX - 1) / TX;
-  int b = blockIdx.x;
+  // XCD order: the slot tiles of one (component, z) plane, which share
+  // DRAM pages, run back to back on one XCD
+  int b = xcd_order(blockIdx.x, ntile * a.nz * a.ncomp);
+  if (b < 0) return;
   const int tile = b % ntile;
   b /= ntile;
   const int z = b % a.nz;
@@ -606,9 +615,10 @@ __global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
 // ================================================================ finalize
 // One block per load: fixed-order sum of the per-block partials written by
 // the producing kernel, then the scalar update of that reduction.
-__global__ __launch_bounds__(NT) void k_finalize(RedBuf red, LoadState* st, double* res2, int slot,
+template <int NTF>
+__global__ __launch_bounds__(NTF) void k_finalize(RedBuf red, LoadState* st, double* res2, int slot,
                                                  int nparts, int only_load, const int* mask) {
-  __shared__ double sh[NT / WAVE];
+  __shared__ double sh[NTF / WAVE];
   const int l = blockIdx.x;
   LoadState* S = st + l;
   bool live;
@@ -627,8 +637,8 @@ __global__ __launch_bounds__(NT) void k_finalize(RedBuf red, LoadState* st, doub
   }
   const double* parts = red.slot_parts(slot, l);
   double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += NT) v += parts[i];
-  const double s = block_sum<NT>(v, sh);
+  for (int i = threadIdx.x; i < nparts; i += NTF) v += parts[i];
+  const double s = block_sum<NTF>(v, sh);
   if (threadIdx.x != 0) return;
   switch (slot) {
     case RED_PQ:
@@ -665,7 +675,12 @@ __global__ __launch_bounds__(NT) void k_finalize(RedBuf red, LoadState* st, doub
 
 hipError_t launch_finalize(const RedBuf& red, LoadState* st, double* res2, int slot, int nparts, int nload,
                            int only_load, const int* mask, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(nload), dim3(NT), 0, s, red, st, res2, slot, nparts, only_load, mask);
+  // one block per load: 1024 threads for the long partial lists (x passes),
+  // 256 for short ones
+  if (nparts > 4096)
+    hipLaunchKernelGGL(k_finalize<1024>, dim3(nload), dim3(1024), 0, s, red, st, res2, slot, nparts, only_load, mask);
+  else
+    hipLaunchKernelGGL(k_finalize<NT>, dim3(nload), dim3(NT), 0, s, red, st, res2, slot, nparts, only_load, mask);
   return hipGetLastError();
 }
 
@@ -724,7 +739,7 @@ static hipError_t launch_xinv_v(const XArgs<T>& a, int nx, dim3 grid, hipStream_
 
 template <typename T>
 hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, const Sched& sc, hipStream_t s) {
-  const dim3 grid(xpass_blocks(nx, a.nrows, sizeof(T) == 8, sc), nload);
+  const dim3 grid(xcd_grid(xpass_blocks(nx, a.nrows, sizeof(T) == 8, sc)), nload);
   switch (sc.x_var) {
     case 0: return launch_xfwd_v<T, 0, 0>(a, nx, grid, s);
     case 1: return launch_xfwd_v<T, 1, 0>(a, nx, grid, s);
@@ -735,7 +750,7 @@ hipError_t launch_xfwd(const XArgs<T>& a, int nx, int nload, const Sched& sc, hi
 
 template <typename T>
 hipError_t launch_xinv(const XArgs<T>& a, int nx, int nload, const Sched& sc, hipStream_t s) {
-  const dim3 grid(xpass_blocks(nx, a.nrows, sizeof(T) == 8, sc), nload);
+  const dim3 grid(xcd_grid(xpass_blocks(nx, a.nrows, sizeof(T) == 8, sc)), nload);
   switch (sc.x_var) {
     case 0: return launch_xinv_v<T, 0, 0>(a, nx, grid, s);
     case 1: return launch_xinv_v<T, 1, 0>(a, nx, grid, s);
@@ -749,7 +764,7 @@ static hipError_t launch_ypass_v(const YArgs<T>& a, bool inverse, int nload, hip
   constexpr int TX = y_tx<T, V>();
   const int M = a.nx / 2;
   const int ntile = (M + TX - 1) / TX;
-  dim3 grid(ntile * a.nz * a.ncomp, nload);
+  dim3 grid(xcd_grid(ntile * a.nz * a.ncomp), nload);
   switch (a.ny) {
 #define C_(n)                                                                     \
   case n:                                                                         \
