@@ -46,8 +46,8 @@ def byte_model(kind, n, prec_bytes):
     f = 3 * n * prec_bytes
     return {
         "k_apply": 2 * f,      # read p, write q (+ material once per launch)
-        "x_fwd": 4 * f,        # read r, q; write r, spectrum
-        "y_fwd": 2 * f,        # read/write spectrum
+        "x_fwd": 3 * f,        # read q and the x-transformed residual R; write R
+        "y_fwd": 2 * f,        # read R, write the spectrum
         "last": 2 * f,         # read/write spectrum
         "y_inv": 2 * f,
         "x_inv": 5 * f,        # read spectrum, p, x; write x, p

@@ -49,40 +49,48 @@ constexpr int NTY = 512;
 constexpr int NTZ = 512;
 
 // ================================================================= x forward
-template <typename T, int M, int V, int RP>
+// MODE 0 (iteration): R -= alpha FFT_x(q) with the ||r||^2 partials from R
+// by Parseval along x (packed slot 0 holds the two real values X[0] and
+// X[nx/2], weight 1; slots k >= 1 stand for k and nx - k, weight 2).
+// MODE 1 (after a residual recomputation): R = FFT_x(r).
+template <typename T, int M, int V, int RP, int MODE>
 __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
   constexpr int RPB = x_rpb<T, M, V>();
   constexpr int RS = pad8(M) + 1;  // padded rows (RowTileP)
+  constexpr int QX = (RPB * M + NT - 1) / NT;
   using T2 = typename V2<T>::type;
   __shared__ cpx<T> buf[RPB * RS];
   __shared__ cpx<T> tws[2 * M];
   __shared__ double sh[NT / WAVE];
   const int l = blockIdx.y;
   LoadState* st = a.st + l;
-  if (!load_live(st, false)) return;
-  const T alpha = (T)st->alpha;
+  if (MODE == 0) {
+    if (!load_live(st, false)) return;
+  } else {
+    if (a.mask ? a.mask[l] == 0 : !load_live(st, true)) return;
+  }
+  const T alpha = MODE == 0 ? (T)st->alpha : T(0);
   const int tid = threadIdx.x;
   for (int i = tid; i < 2 * M; i += NT) tws[i] = a.tw[i];
   // XCD order: consecutive row groups (contiguous memory) on one XCD
   const int rb = xcd_order(blockIdx.x, (a.nrows + RPB - 1) / RPB);
   if (rb < 0) return;
   const int row0 = rb * RPB;
-  T2* r2 = reinterpret_cast<T2*>(a.r + l * a.lstride);
-  const T2* q2 = reinterpret_cast<const T2*>(a.q + l * a.lstride);
-  double acc = 0.0;
-  for (int e = tid; e < RPB * M; e += NT) {
+  const T2* in2 = reinterpret_cast<const T2*>((MODE == 0 ? a.q : a.r) + l * a.lstride);
+  cpx<T>* R = a.R + l * (a.lstride / 2);
+  cpx<T> rv[QX];  // mode 0: this thread's R values, loaded with q
+#pragma unroll
+  for (int q = 0; q < QX; ++q) {
+    const int e = tid + q * NT;
+    if (e >= RPB * M) break;
     const int rr = e / M, m = e - rr * M;
     const int row = row0 + rr;
     cpx<T> v = {T(0), T(0)};
     if (row < a.nrows) {
       const long long off = (long long)row * M + m;
-      T2 rv = r2[off];
-      const T2 qv = q2[off];
-      rv.x -= alpha * qv.x;
-      rv.y -= alpha * qv.y;
-      r2[off] = rv;
-      acc += (double)rv.x * rv.x + (double)rv.y * rv.y;
-      v = {rv.x, rv.y};
+      const T2 w = in2[off];
+      v = {w.x, w.y};
+      if (MODE == 0) rv[q] = R[off];
     }
     buf[rr * RS + pad8(m)] = v;
   }
@@ -107,15 +115,32 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
     }
   }
   __syncthreads();
-  cpx<T>* S = a.S + l * (a.lstride / 2);
-  for (int e = tid; e < RPB * M; e += NT) {
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < QX; ++q) {
+    const int e = tid + q * NT;
+    if (e >= RPB * M) break;
     const int rr = e / M, m = e - rr * M;
     const int row = row0 + rr;
-    if (row < a.nrows) S[(long long)row * M + m] = buf[rr * RS + pad8(m)];
+    if (row < a.nrows) {
+      const long long off = (long long)row * M + m;
+      const cpx<T> h = buf[rr * RS + pad8(m)];
+      if (MODE == 0) {
+        cpx<T> v = rv[q];
+        v.re -= alpha * h.re;
+        v.im -= alpha * h.im;
+        R[off] = v;
+        acc += (m == 0 ? 1.0 : 2.0) * ((double)v.re * v.re + (double)v.im * v.im);
+      } else {
+        R[off] = h;
+      }
+    }
   }
-  // ||r||^2 partial of this block (finalised by k_finalize)
-  const double bs = block_sum<NT>(acc, sh);
-  if (tid == 0) a.red.slot_parts(RED_RR, l)[rb] = bs;
+  if (MODE == 0) {
+    // ||r||^2 partial of this block (finalised by k_finalize)
+    const double bs = block_sum<NT>(acc * (1.0 / (2.0 * M)), sh);
+    if (tid == 0) a.red.slot_parts(RED_RR, l)[rb] = bs;
+  }
 }
 
 // ================================================================= x inverse
@@ -203,10 +228,12 @@ __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
   const int s0 = tile * TX;
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NTY) tws[i] = a.tw[i];
-  cpx<T>* base = a.S + l * a.lstrideC + ((long long)(c * a.nz + z) * a.ny) * M + s0;
+  const long long plane = l * a.lstrideC + ((long long)(c * a.nz + z) * a.ny) * M + s0;
+  cpx<T>* base = a.S + plane;
+  const cpx<T>* src = ((!INV && a.Sin) ? a.Sin : a.S) + plane;
   for (int e = tid; e < N * TX; e += NTY) {
     const int y = e / TX, s = e - y * TX;
-    buf[e] = (s0 + s < M) ? base[(long long)y * M + s] : cpx<T>{T(0), T(0)};
+    buf[e] = (s0 + s < M) ? src[(long long)y * M + s] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
   if (INV && s0 == 0) {
@@ -543,11 +570,12 @@ __global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NTZ) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + s0;
+  const cpx<T>* src = (a.Sin ? a.Sin : a.S) + l * a.lstrideC + s0;
   const long long cstride = (long long)a.ny * M;
   for (int e = tid; e < N * NC; e += NTZ) {
     const int y = e / NC, rem = e - y * NC;
     const int c = rem / TX, s = rem - c * TX;
-    buf[e] = (s0 + s < M) ? base[c * cstride + (long long)y * M + s] : cpx<T>{T(0), T(0)};
+    buf[e] = (s0 + s < M) ? src[c * cstride + (long long)y * M + s] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
   fft_lds<T, N, false, NC, NTZ, 1, ColTile<NC>>(buf, tws);
@@ -716,7 +744,11 @@ int xpass_blocks(int nx, int nrows, bool fp64, const Sched& sc) {
 template <typename T, int V, int RP>
 static hipError_t launch_xfwd_v(const XArgs<T>& a, int nx, dim3 grid, hipStream_t s) {
   switch (nx / 2) {
-#define C_(m) case m: hipLaunchKernelGGL((k_xfwd<T, m, V, RP>), grid, dim3(NT), 0, s, a); break;
+#define C_(m)                                                                               \
+  case m:                                                                                   \
+    if (a.mode == 0) hipLaunchKernelGGL((k_xfwd<T, m, V, RP, 0>), grid, dim3(NT), 0, s, a); \
+    else hipLaunchKernelGGL((k_xfwd<T, m, V, RP, 1>), grid, dim3(NT), 0, s, a);             \
+    break;
     CELLFFT_MSIZES(C_)
 #undef C_
     default:

@@ -58,14 +58,19 @@ struct Geom {
 
 // ---------------------------------------------------------------- x passes
 template <typename T> struct XArgs {
-  T* r;            // residual (xfwd: updated in place)
-  const T* q;      // K p (xfwd)
+  const T* r;      // residual in real space (xfwd mode 1)
+  const T* q;      // K p (xfwd mode 0)
+  cpx<T>* R;       // residual transformed along x (packed half spectrum of every
+                   // x row), the form in which the iteration keeps r
   cpx<T>* S;       // packed half spectrum, same element count as a real field
   T* x;            // iterate (xinv: x += alpha p_old)
   T* p;            // direction (xinv: p = z + beta p_old)
-  long long lstride;  // reals per load in r/q/x/p (= d n); S stride = lstride/2
+  long long lstride;  // reals per load in r/q/x/p (= d n); S, R stride = lstride/2
   int nrows;       // rows of length nx per load = d * ny * nz
   const cpx<T>* tw;   // nx twiddles exp(-2 pi i m / nx)
+  int mode;        // xfwd: 0: R -= alpha FFT_x(q), ||r||^2 partials (Parseval);
+                   //       1: R = FFT_x(r) for the slots in mask (or the active ones)
+  const int* mask;
   LoadState* st;
   RedBuf red;
 };
@@ -73,6 +78,8 @@ template <typename T> struct XArgs {
 // ---------------------------------------------------------------- y pass (3D)
 template <typename T> struct YArgs {
   cpx<T>* S;
+  const cpx<T>* Sin;    // forward pass: read from here (the x-transformed residual),
+                        // write S; nullptr: in place
   long long lstrideC;   // complex elements per load
   int nx, ny, nz, ncomp;
   const cpx<T>* tw;     // ny twiddles
@@ -82,6 +89,7 @@ template <typename T> struct YArgs {
 // --------------------------------------------- last pass with preconditioner
 template <typename T> struct PArgs {
   cpx<T>* S;
+  const cpx<T>* Sin;    // 2D: read from here, write S (nullptr: in place)
   long long lstrideC;
   int nx, ny, nz;
   const cpx<T>* tw;     // twiddles of the last axis (nz in 3D, ny in 2D)

@@ -21,6 +21,7 @@ template <typename T> struct Fields {
   T* p = nullptr;
   T* q = nullptr;
   cpx<T>* S = nullptr;
+  cpx<T>* R = nullptr;  // residual transformed along x, [nslot][d n / 2]
   cpx<T>* tw[3] = {nullptr, nullptr, nullptr};
   T* trig[3] = {nullptr, nullptr, nullptr};
   T* symtab = nullptr;   // 3D: [ncell][ny][nz][nx/2][6]

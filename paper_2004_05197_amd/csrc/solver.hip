@@ -129,7 +129,8 @@ cell_status ensure_fields(cell_s* c) {
     if (hipMalloc((void**)b, bytes) != hipSuccess) return fail(CELL_E_NOMEM, "device allocation of a field failed");
     HIPCHK(hipMemset(*b, 0, bytes));
   }
-  if (hipMalloc((void**)&F.S, bytes) != hipSuccess) return fail(CELL_E_NOMEM, "device allocation of the spectrum failed");
+  if (hipMalloc((void**)&F.S, bytes) != hipSuccess || hipMalloc((void**)&F.R, bytes) != hipSuccess)
+    return fail(CELL_E_NOMEM, "device allocation of the spectrum failed");
   const int N[3] = {c->g.nx, c->g.ny, c->g.nz};
   for (int a = 0; a < c->d; ++a) {
     std::vector<cpx<T>> tw(N[a]);
@@ -179,6 +180,7 @@ template <typename T> void free_fields(Fields<T>& F) {
   fr(F.p);
   fr(F.q);
   fr(F.S);
+  fr(F.R);
   fr(F.symtab);
   fr(F.symtabB);
   fr(F.med);
@@ -253,6 +255,7 @@ PArgs<T> make_pargs(cell_s* c, int cell) {
   pa.tab_stride = 0;
   pa.tabB_stride = 0;
   pa.med = nullptr;
+  pa.Sin = nullptr;
   pa.st = c->st;
   pa.red = red_of(c);
   return pa;
@@ -306,6 +309,26 @@ cell_status ensure_symtab(cell_s* c, PArgs<T>& pa) {
   return CELL_OK;
 }
 
+template <typename T>
+XArgs<T> xargs(cell_s* c) {
+  Fields<T>& F = fields<T>(c);
+  XArgs<T> xa{};
+  xa.r = F.r;
+  xa.q = F.q;
+  xa.R = F.R;
+  xa.S = F.S;
+  xa.x = F.x;
+  xa.p = F.p;
+  xa.lstride = c->lstride;
+  xa.nrows = (int)(c->lstride / c->g.nx);
+  xa.tw = F.tw[0];
+  xa.mode = 0;
+  xa.mask = nullptr;
+  xa.st = c->st;
+  xa.red = red_of(c);
+  return xa;
+}
+
 // one PCG iteration over all slots (or the initial preconditioning if !kapply)
 template <typename T>
 cell_status iteration(cell_s* c, bool kapply) {
@@ -317,25 +340,24 @@ cell_status iteration(cell_s* c, bool kapply) {
     ProfScope ps(c, CELL_K_APPLY);
     HIPCHK(launch_stencil<T>(ka, c->sched, s));
   }
-  XArgs<T> xa{};
-  xa.r = F.r;
-  xa.q = F.q;
-  xa.S = F.S;
-  xa.x = F.x;
-  xa.p = F.p;
-  xa.lstride = c->lstride;
-  xa.nrows = (int)(c->lstride / c->g.nx);
-  xa.tw = F.tw[0];
-  xa.st = c->st;
-  xa.red = red_of(c);
-  {
+  XArgs<T> xa = xargs<T>(c);
+  if (kapply) {
+    // R -= alpha FFT_x(q), ||r||^2
+    {
+      ProfScope ps(c, CELL_K_XFWD);
+      HIPCHK(launch_xfwd<T>(xa, c->g.nx, ns, c->sched, s));
+    }
+    HIPCHK(launch_finalize(xa.red, c->st, c->res2, RED_RR,
+                           xpass_blocks(c->g.nx, xa.nrows, sizeof(T) == 8, c->sched), ns, -1, nullptr, s));
+  } else {
+    // first preconditioning: R = FFT_x(r) of the active slots
+    xa.mode = 1;
     ProfScope ps(c, CELL_K_XFWD);
     HIPCHK(launch_xfwd<T>(xa, c->g.nx, ns, c->sched, s));
   }
-  HIPCHK(launch_finalize(xa.red, c->st, c->res2, RED_RR, xpass_blocks(c->g.nx, xa.nrows, sizeof(T) == 8, c->sched),
-                         ns, -1, nullptr, s));
   YArgs<T> ya{};
   ya.S = F.S;
+  ya.Sin = F.R;
   ya.lstrideC = c->lstride / 2;
   ya.nx = c->g.nx;
   ya.ny = c->g.ny;
@@ -345,6 +367,7 @@ cell_status iteration(cell_s* c, bool kapply) {
   ya.st = c->st;
   PArgs<T> pa = make_pargs<T>(c, 0);
   STCHK(ensure_symtab<T>(c, pa));
+  if (c->d == 2) pa.Sin = F.R;  // 2D: the last pass follows the x pass
   if (c->d == 3) {
     ProfScope ps(c, CELL_K_YFWD);
     HIPCHK(launch_ypass<T>(ya, false, ns, c->sched, s));
@@ -360,6 +383,7 @@ cell_status iteration(cell_s* c, bool kapply) {
     HIPCHK(launch_ypass<T>(ya, true, ns, c->sched, s));
   }
   {
+    xa.mode = 0;
     ProfScope ps(c, CELL_K_XINV);
     HIPCHK(launch_xinv<T>(xa, c->g.nx, ns, c->sched, s));
   }
@@ -516,6 +540,14 @@ cell_status poll_t(SolveRun& R) {
       u64 = c->x64;
     }
     STCHK(residual<T>(c, u64, c->mask));
+    {
+      // the iteration keeps r transformed along x: refresh it
+      XArgs<T> xa = xargs<T>(c);
+      xa.mode = 1;
+      xa.mask = c->mask;
+      ProfScope ps(c, CELL_K_XFWD);
+      HIPCHK(launch_xfwd<T>(xa, c->g.nx, ns, c->sched, s));
+    }
     for (int l = 0; l < ns; ++l) {
       if (!c->mask_h[l]) continue;
       LoadState& S = c->st_h[l];
@@ -1087,21 +1119,14 @@ cell_status tune_t(cell_s* c) {
   HIPCHK(hipMemsetAsync(F.p, 0, fb, s));
   HIPCHK(hipMemsetAsync(F.q, 0, fb, s));
   HIPCHK(hipMemsetAsync(F.S, 0, fb, s));
+  HIPCHK(hipMemsetAsync(F.R, 0, fb, s));
   PArgs<T> pa = make_pargs<T>(c, 0);
+  if (c->d == 2) pa.Sin = F.R;
   STCHK(ensure_symtab<T>(c, pa));
-  XArgs<T> xa{};
-  xa.r = F.r;
-  xa.q = F.q;
-  xa.S = F.S;
-  xa.x = F.x;
-  xa.p = F.p;
-  xa.lstride = c->lstride;
-  xa.nrows = (int)(c->lstride / c->g.nx);
-  xa.tw = F.tw[0];
-  xa.st = c->st;
-  xa.red = red_of(c);
+  XArgs<T> xa = xargs<T>(c);
   YArgs<T> ya{};
   ya.S = F.S;
+  ya.Sin = F.R;
   ya.lstrideC = c->lstride / 2;
   ya.nx = c->g.nx;
   ya.ny = c->g.ny;
