@@ -162,11 +162,23 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
   const int rb = xcd_order(blockIdx.x, (a.nrows + RPB - 1) / RPB);
   if (rb < 0) return;
   const int row0 = rb * RPB;
-  const cpx<T>* S = a.S + l * (a.lstride / 2);
+  const cpx<T>* S = a.S + l * a.lsS;
+  // S rows live in padded (component, z) planes of zsS complex values
+  const int zr0 = row0 / a.ny, yb = row0 - zr0 * a.ny;
   for (int e = tid; e < RPB * M; e += NT) {
     const int rr = e / M, m = e - rr * M;
     const int row = row0 + rr;
-    buf[rr * RS + pad8(m)] = row < a.nrows ? S[(long long)row * M + m] : cpx<T>{T(0), T(0)};
+    int y = yb + rr, zr = zr0;
+    if (RPB <= a.ny) {
+      if (y >= a.ny) {
+        y -= a.ny;
+        ++zr;
+      }
+    } else {
+      zr += y / a.ny;
+      y -= (y / a.ny) * a.ny;
+    }
+    buf[rr * RS + pad8(m)] = row < a.nrows ? S[(long long)zr * a.zsS + (long long)y * M + m] : cpx<T>{T(0), T(0)};
   }
   __syncthreads();
   constexpr int KH = M / 2 + 1;
@@ -228,9 +240,8 @@ __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
   const int s0 = tile * TX;
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NTY) tws[i] = a.tw[i];
-  const long long plane = l * a.lstrideC + ((long long)(c * a.nz + z) * a.ny) * M + s0;
-  cpx<T>* base = a.S + plane;
-  const cpx<T>* src = ((!INV && a.Sin) ? a.Sin : a.S) + plane;
+  cpx<T>* base = a.S + l * a.lsS + (long long)(c * a.nz + z) * a.zsS + s0;
+  const cpx<T>* src = (!INV && a.Sin) ? a.Sin + l * a.lstrideC + ((long long)(c * a.nz + z) * a.ny) * M + s0 : base;
   for (int e = tid; e < N * TX; e += NTY) {
     const int y = e / TX, s = e - y * TX;
     buf[e] = (s0 + s < M) ? src[(long long)y * M + s] : cpx<T>{T(0), T(0)};
@@ -533,8 +544,8 @@ __global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NTH) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
-  const long long cstride = (long long)a.nz * a.ny * M;   // component
-  const long long zstride = (long long)a.ny * M;          // z plane
+  const long long cstride = (long long)a.nz * a.zsS;      // component
+  const long long zstride = a.zsS;                        // z plane (padded)
   for (int e = tid; e < N * NC; e += NTH) {
     const int z = e / NC, rem = e - z * NC;
     const int c = rem / TX, s = rem - c * TX;

@@ -65,8 +65,11 @@ template <typename T> struct XArgs {
   cpx<T>* S;       // packed half spectrum, same element count as a real field
   T* x;            // iterate (xinv: x += alpha p_old)
   T* p;            // direction (xinv: p = z + beta p_old)
-  long long lstride;  // reals per load in r/q/x/p (= d n); S, R stride = lstride/2
+  long long lstride;  // reals per load in r/q/x/p (= d n); R stride = lstride/2
   int nrows;       // rows of length nx per load = d * ny * nz
+  int ny;          // rows per (component, z) plane
+  long long zsS;   // S: complex values per (component, z) plane (ny nx/2 + padding)
+  long long lsS;   // S: complex values per load
   const cpx<T>* tw;   // nx twiddles exp(-2 pi i m / nx)
   int mode;        // xfwd: 0: R -= alpha FFT_x(q), ||r||^2 partials (Parseval);
                    //       1: R = FFT_x(r) for the slots in mask (or the active ones)
@@ -78,9 +81,10 @@ template <typename T> struct XArgs {
 // ---------------------------------------------------------------- y pass (3D)
 template <typename T> struct YArgs {
   cpx<T>* S;
-  const cpx<T>* Sin;    // forward pass: read from here (the x-transformed residual),
-                        // write S; nullptr: in place
-  long long lstrideC;   // complex elements per load
+  const cpx<T>* Sin;    // forward pass: read from here (the x-transformed residual,
+                        // unpadded planes), write S; nullptr: in place
+  long long lstrideC;   // complex elements per load of Sin (unpadded)
+  long long zsS, lsS;   // S: complex values per (component, z) plane and per load
   int nx, ny, nz, ncomp;
   const cpx<T>* tw;     // ny twiddles
   LoadState* st;
@@ -90,7 +94,9 @@ template <typename T> struct YArgs {
 template <typename T> struct PArgs {
   cpx<T>* S;
   const cpx<T>* Sin;    // 2D: read from here, write S (nullptr: in place)
-  long long lstrideC;
+  long long lstrideC;   // S: complex values per load (3D: 3 nz zsS)
+  long long zsS;        // S: complex values per (component, z) plane (3D; padded so
+                        // that the z pass's plane-strided reads spread over channels)
   int nx, ny, nz;
   const cpx<T>* tw;     // twiddles of the last axis (nz in 3D, ny in 2D)
   const T* trig[3];     // per axis: (sin(pi k / N_a), cos(pi k / N_a)), k < N_a

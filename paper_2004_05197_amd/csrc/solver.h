@@ -41,6 +41,7 @@ struct cell_s {
   cellfft::Geom g{};
   int d = 3, nv = 6;
   long long n = 0, lstride = 0;
+  long long s_zs = 0, s_ls = 0;  // spectrum S: complex values per (component, z) plane, per slot
   int precision = CELL_FP64;
   double tol = 1e-10;
   int max_iter = 10000;

@@ -129,8 +129,10 @@ cell_status ensure_fields(cell_s* c) {
     if (hipMalloc((void**)b, bytes) != hipSuccess) return fail(CELL_E_NOMEM, "device allocation of a field failed");
     HIPCHK(hipMemset(*b, 0, bytes));
   }
-  if (hipMalloc((void**)&F.S, bytes) != hipSuccess || hipMalloc((void**)&F.R, bytes) != hipSuccess)
+  const size_t sbytes = sizeof(cpx<T>) * (size_t)c->s_ls * c->nslot;
+  if (hipMalloc((void**)&F.S, sbytes) != hipSuccess || hipMalloc((void**)&F.R, bytes) != hipSuccess)
     return fail(CELL_E_NOMEM, "device allocation of the spectrum failed");
+  HIPCHK(hipMemset(F.S, 0, sbytes));
   const int N[3] = {c->g.nx, c->g.ny, c->g.nz};
   for (int a = 0; a < c->d; ++a) {
     std::vector<cpx<T>> tw(N[a]);
@@ -237,7 +239,8 @@ PArgs<T> make_pargs(cell_s* c, int cell) {
   Fields<T>& F = fields<T>(c);
   PArgs<T> pa{};
   pa.S = F.S;
-  pa.lstrideC = c->lstride / 2;
+  pa.lstrideC = c->s_ls;
+  pa.zsS = c->s_zs;
   pa.nx = c->g.nx;
   pa.ny = c->g.ny;
   pa.nz = c->g.nz;
@@ -321,6 +324,9 @@ XArgs<T> xargs(cell_s* c) {
   xa.p = F.p;
   xa.lstride = c->lstride;
   xa.nrows = (int)(c->lstride / c->g.nx);
+  xa.ny = c->g.ny;
+  xa.zsS = c->s_zs;
+  xa.lsS = c->s_ls;
   xa.tw = F.tw[0];
   xa.mode = 0;
   xa.mask = nullptr;
@@ -359,6 +365,8 @@ cell_status iteration(cell_s* c, bool kapply) {
   ya.S = F.S;
   ya.Sin = F.R;
   ya.lstrideC = c->lstride / 2;
+  ya.zsS = c->s_zs;
+  ya.lsS = c->s_ls;
   ya.nx = c->g.nx;
   ya.ny = c->g.ny;
   ya.nz = c->g.nz;
@@ -698,6 +706,9 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
   int dev = cfg->device;
   if (dev < 0) HIPCHK(hipGetDevice(&dev));
   if (dev >= ndev) return fail(CELL_E_ARG, "device ordinal out of range");
+  const char* zp = std::getenv("CELLFFT_ZPAD");
+  const long long zpad = zp ? std::atoll(zp) : 64;  // complex values
+  if (zpad < 0 || zpad > (1 << 20)) return fail(CELL_E_ARG, "CELLFFT_ZPAD out of range");
   DevGuard dg(dev);
   cell_s* c = new cell_s();
   c->dev = dev;
@@ -715,6 +726,16 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
     c->g.h[a] = L / N;
   }
   c->lstride = (long long)c->d * c->n;
+  if (c->d == 3) {
+    // pad each (component, z) plane of the spectrum: the z pass reads one
+    // row segment per plane, and unpadded planes of a power-of-two size
+    // would put all of them on the same memory channels
+    c->s_zs = (long long)c->g.ny * (c->g.nx / 2) + zpad;
+    c->s_ls = 3LL * c->g.nz * c->s_zs;
+  } else {
+    c->s_zs = (long long)c->g.ny * (c->g.nx / 2);
+    c->s_ls = c->lstride / 2;
+  }
   c->precision = cfg->precision;
   c->tol = cfg->tol > 0.0 ? cfg->tol : (cfg->precision == CELL_MIXED ? 1e-6 : 1e-10);
   c->max_iter = cfg->max_iter > 0 ? cfg->max_iter : 10000;
@@ -1118,7 +1139,7 @@ cell_status tune_t(cell_s* c) {
   HIPCHK(hipMemsetAsync(F.r, 0, fb, s));
   HIPCHK(hipMemsetAsync(F.p, 0, fb, s));
   HIPCHK(hipMemsetAsync(F.q, 0, fb, s));
-  HIPCHK(hipMemsetAsync(F.S, 0, fb, s));
+  HIPCHK(hipMemsetAsync(F.S, 0, sizeof(cpx<T>) * (size_t)c->s_ls * ns, s));
   HIPCHK(hipMemsetAsync(F.R, 0, fb, s));
   PArgs<T> pa = make_pargs<T>(c, 0);
   if (c->d == 2) pa.Sin = F.R;
@@ -1128,6 +1149,8 @@ cell_status tune_t(cell_s* c) {
   ya.S = F.S;
   ya.Sin = F.R;
   ya.lstrideC = c->lstride / 2;
+  ya.zsS = c->s_zs;
+  ya.lsS = c->s_ls;
   ya.nx = c->g.nx;
   ya.ny = c->g.ny;
   ya.nz = c->g.nz;
