@@ -174,6 +174,24 @@ def bench_uneven(args, B, ms, progress):
     }
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Device-to-device copy rate (GB/s of read + write traffic) of a plain
+    torch copy of `mib` MiB, best of `reps`: the practically reachable HBM
+    rate that the roofline fraction can be compared with."""
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps + 1):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2 * mib * (1 << 20) / (best * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +286,7 @@ def main():
         alg_bytes += launches * 8 * n
     achieved = alg_bytes / (ms_tot * 1e-3) / 1e9
     gpu_ms = sum(prof[k][0] for k in prof)
+    copy_gbs = copy_bandwidth(torch)
     roofline = {
         "bound": "hbm",
         "kernel": dom,
@@ -279,6 +298,8 @@ def main():
         "avg_launch_ms": round(ms_tot / launches, 4),
         "launches": launches,
         "bytes_per_launch": round(alg_bytes / launches),
+        "copy_gbs": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
     }
     # whole-iteration byte model: all six kernels
     all_bytes = sum((iters_total + (0 if k == "k_apply" else 6 * args.steps)) * byte_model(k, n, 4)
@@ -342,6 +363,7 @@ def main():
         },
         "roofline": roofline,
         "iteration_byte_model_frac": round(all_bytes / (loop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "iteration_byte_model_frac_of_copy": round(all_bytes / (loop_ms * 1e-3) / 1e9 / copy_gbs, 4),
         "kernel_ms": kernel_ms,
         "gpu_busy_frac": round(gpu_ms * 1e-3 / dt, 4),
         "fp64": fp64,
