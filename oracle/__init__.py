@@ -21,7 +21,12 @@ What it computes (plain definitions, written out slowly):
                  its impulse response (Sec. 3.2: constant stencil functions
                  make the reference matrix circulant), and a textbook
                  preconditioned conjugate-gradient solve.
+  * ``hyper``    the compressible neo-Hookean cell problem (Sec. 2.2, eq.
+                 NeoHookeanEnergy) on the same mesh: energy, first Piola
+                 stress, its derivative, explicit tangent assembly and
+                 Newton's method (Sec. 4, nonlinear problems) with direct
+                 sparse solves and an Armijo line search.
 
 Every function states the passage or the standard mathematics it follows.
 """
-from . import fem, matfree  # noqa: F401
+from . import fem, hyper, matfree  # noqa: F401
