@@ -24,7 +24,11 @@ for the barycentric gradient g_j of vertex j), the tangent
 K_T = sum |s| G^T A G.  Newton's method (Sec. 4, subsection on nonlinear
 problems: the Jacobian is reassembled in each iteration) solves K_T du = f
 with node 0 pinned and takes the largest step t in {1, 1/2, 1/4, ...} that
-keeps every J > 0 and decreases Pi by at least 1e-4 t f.du (Armijo).
+keeps every J > 0 and decreases Pi by at least 1e-4 t f.du (Armijo).  The
+paper does not fix the step control; near the solution the decrease falls
+below the rounding level of Pi (about 1e-13 |Y| max(|lambda| + 2 mu)
+d (1 + |F_bar|^2)), and there a step is also taken when Pi does not grow by
+more than that level and ||f|| falls by the factor 1 - 1e-4 t.
 """
 from __future__ import annotations
 
@@ -172,6 +176,8 @@ def newton(grid, E, nu, Fbar, tol=1e-12, maxit=30, u0=None):
     keep = np.setdiff1d(np.arange(d * n), pinned)
     lam, mu = lame(np.ravel(E), np.ravel(nu))
     scale = grid.volume * float(np.max(mu)) * max(np.abs(Fbar).max(), 1.0)
+    fmax = max(np.abs(Fbar).max(), 1.0)
+    dE = 1e-13 * grid.volume * float(np.max(np.abs(lam) + 2 * mu)) * d * (1.0 + fmax ** 2)
     f = residual(grid, E, nu, u, Fbar)
     Pi = total_energy(grid, E, nu, u, Fbar)
     norms = [float(np.linalg.norm(f))]
@@ -189,6 +195,10 @@ def newton(grid, E, nu, Fbar, tol=1e-12, maxit=30, u0=None):
             Pt = total_energy(grid, E, nu, ut, Fbar)
             if np.isfinite(Pt) and Pt <= Pi - 1e-4 * t * slope:
                 break
+            if np.isfinite(Pt) and Pt - Pi <= dE:
+                ft = np.linalg.norm(residual(grid, E, nu, ut, Fbar))
+                if ft <= (1.0 - 1e-4 * t) * norms[-1]:
+                    break
             t *= 0.5
             if t < 1e-10:
                 raise RuntimeError("line search failed")
