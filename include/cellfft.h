@@ -168,6 +168,48 @@ cell_status cell_profile(cell_t c, int enable);
  * (CELL_NKERNEL entries each, host). */
 cell_status cell_profile_read(cell_t c, double* ms_out, long long* launches_out);
 
+/* ---- neo-Hookean cell problem (Newton's method) ----------------------------
+ *
+ * Compressible neo-Hookean energy density (Sec. 2.2, eq. NeoHookeanEnergy),
+ * J = det F:  W(F) = lambda/2 (ln J)^2 - mu ln J + mu/2 (tr(F^T F) - tr I),
+ * with F = F_bar + grad u on every simplex (2D: plane strain, F the in-plane
+ * block).  For each macroscopic deformation gradient F_bar the periodic
+ * fluctuation u minimising sum |s| W is found by Newton's method (Sec. 4,
+ * nonlinear problems: the tangent is re-evaluated at every iterate).  Each
+ * Newton step solves K_T(u) du = f(u) = -grad Pi by the same preconditioned
+ * CG (Fourier reference medium, mixed or FP64 as configured, tolerance
+ * cfg.tol on the step), then takes the largest step 1, 1/2, 1/4, ... that
+ * keeps every J > 0 and decreases Pi by at least 1e-4 t f.du.  Residuals,
+ * energies and stresses are evaluated in FP64. */
+typedef struct {
+  int nload;
+  int newton_iters[6];   /* Newton steps per load */
+  int cg_iters[6];       /* PCG iterations summed over the steps */
+  double resnorm[6];     /* final ||f|| / max(||f_0||, |Y| max(|lambda| + 2 mu) max(|F_bar|, 1)) */
+  double energy[6];      /* Pi / |Y| */
+  double seconds;
+} cell_hyper_info;
+
+/* nload (<= max_loads) macroscopic deformation gradients F_bar[nload][d][d]
+ * (host, row-major; det > 0).  tol: stop when ||f|| <= tol times the scale
+ * above (0 -> 1e-10); max_newton: 0 -> 50.  P_out (host, may be NULL):
+ * [nload][d][d] mean first Piola-Kirchhoff stress.  Afterwards
+ * cell_get_displacement returns the fluctuation of each load; the linear
+ * results (cell_energy_matrix, cell_get_residual, cell_adjoint) are
+ * CELL_E_STATE until the next linear solve.  CELL_E_BREAKDOWN if the line
+ * search finds no admissible step. */
+cell_status cell_solve_hyper(cell_t c, int nload, const double* F_bar, double tol, int max_newton, double* P_out,
+                             cell_hyper_info* info);
+
+/* Single steps of the Newton path (parity checks), on host arrays [d][n]:
+ * q = K_T(u) p, the tangent at F = F_bar + grad u, in the given precision
+ * (CELL_MIXED needs a mixed-precision handle); and f = -grad Pi(u) in FP64
+ * with sums_out[10] (may be NULL) = sum |s| W, then sum |s| P (3 x 3
+ * row-major; 2D uses the leading 2 x 2).  Invalidate the last solve. */
+cell_status cell_apply_hyper_tangent(cell_t c, int precision, const double* F_bar, const double* u, const double* p,
+                                     double* q_out);
+cell_status cell_hyper_residual(cell_t c, const double* F_bar, const double* u, double* f_out, double* sums_out);
+
 /* ---- autotuner ------------------------------------------------------------
  *
  * A schedule picks the compiled variant of each iteration kernel; all

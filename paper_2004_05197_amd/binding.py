@@ -59,6 +59,16 @@ class CellInfo(ct.Structure):
                     sym_gap=self.sym_gap, seconds=self.seconds)
 
 
+class CellHyperInfo(ct.Structure):
+    _fields_ = [("nload", ct.c_int), ("newton_iters", ct.c_int * 6), ("cg_iters", ct.c_int * 6),
+                ("resnorm", ct.c_double * 6), ("energy", ct.c_double * 6), ("seconds", ct.c_double)]
+
+    def as_dict(self):
+        k = self.nload
+        return dict(nload=k, newton_iters=list(self.newton_iters[:k]), cg_iters=list(self.cg_iters[:k]),
+                    resnorm=list(self.resnorm[:k]), energy=list(self.energy[:k]), seconds=self.seconds)
+
+
 _P = ct.c_void_p
 _D = ct.POINTER(ct.c_double)
 _SIGS = {
@@ -89,6 +99,9 @@ _SIGS = {
     "cell_batch_get_displacement": (ct.c_int, [_P, ct.c_int, ct.c_int, _P, ct.c_int]),
     "cell_batch_get_residual": (ct.c_int, [_P, ct.c_int, ct.c_int, _P, ct.c_int]),
     "cell_autotune": (ct.c_int, [_P, ct.c_int]),
+    "cell_solve_hyper": (ct.c_int, [_P, ct.c_int, _P, ct.c_double, ct.c_int, _P, ct.POINTER(CellHyperInfo)]),
+    "cell_apply_hyper_tangent": (ct.c_int, [_P, ct.c_int, _P, _P, _P, _P]),
+    "cell_hyper_residual": (ct.c_int, [_P, _P, _P, _P, _P]),
     "cell_get_schedule": (ct.c_int, [_P, _P]),
     "cell_set_schedule": (ct.c_int, [_P, _P]),
 }
@@ -221,6 +234,37 @@ class Cell:
         g = np.zeros(self.n)
         _check(_lib.cell_adjoint(self._h, a.ctypes.data_as(ct.c_void_p), g.ctypes.data_as(ct.c_void_p), 0))
         return g
+
+    def solve_hyper(self, F_bar, tol=0.0, max_newton=0):
+        """Neo-Hookean cell problem for macroscopic deformation gradients
+        F_bar (nload, d, d); returns (mean first Piola stress (nload, d, d), info)."""
+        Fb = np.ascontiguousarray(np.asarray(F_bar, dtype=np.float64).reshape(-1, self.dim, self.dim))
+        nl = Fb.shape[0]
+        P = np.zeros((nl, self.dim, self.dim))
+        info = CellHyperInfo()
+        st = _check(_lib.cell_solve_hyper(self._h, nl, Fb.ctypes.data_as(ct.c_void_p), float(tol), int(max_newton),
+                                          P.ctypes.data_as(ct.c_void_p), ct.byref(info)))
+        self.solves += 1
+        return P, dict(info.as_dict(), status=STATUS_NAMES[st])
+
+    def hyper_tangent(self, F_bar, u, p, precision=None):
+        Fb = np.ascontiguousarray(np.asarray(F_bar, dtype=np.float64).reshape(self.dim, self.dim))
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float64)).ravel()
+        q = np.zeros_like(u)
+        pr = self.precision if precision is None else precision
+        _check(_lib.cell_apply_hyper_tangent(self._h, int(pr), Fb.ctypes.data_as(ct.c_void_p), u.ctypes.data_as(ct.c_void_p),
+                                             p.ctypes.data_as(ct.c_void_p), q.ctypes.data_as(ct.c_void_p)))
+        return q
+
+    def hyper_residual(self, F_bar, u):
+        Fb = np.ascontiguousarray(np.asarray(F_bar, dtype=np.float64).reshape(self.dim, self.dim))
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()
+        f = np.zeros_like(u)
+        sums = np.zeros(10)
+        _check(_lib.cell_hyper_residual(self._h, Fb.ctypes.data_as(ct.c_void_p), u.ctypes.data_as(ct.c_void_p),
+                                        f.ctypes.data_as(ct.c_void_p), sums.ctypes.data_as(ct.c_void_p)))
+        return f, sums
 
     def displacement(self, load=0):
         u = np.zeros((self.dim, self.n))

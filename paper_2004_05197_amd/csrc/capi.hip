@@ -145,7 +145,7 @@ cell_status slot_displacement(cell_s* c, int cell, int load, double* u_out, int 
 
 // final residual of load `load` of cell `cell` (FP32 rounding in mixed mode)
 cell_status slot_residual(cell_s* c, int cell, int load, double* r_out, int on_device) {
-  if (!c->solved) return fail(CELL_E_STATE, "no solution available");
+  if (!c->solved || !c->linear_results) return fail(CELL_E_STATE, "no linear solution available");
   if (load < 0 || load >= c->nload_solved) return fail(CELL_E_ARG, "load index out of range");
   DevGuard dg(c->dev);
   const long long off = ((long long)cell * c->lpc + load) * c->lstride;
@@ -262,7 +262,7 @@ cell_status cell_get_displacement(cell_t c, int load, double* u_out, int on_devi
 
 cell_status cell_energy_matrix(cell_t c, double* C_out) {
   if (!c || !C_out) return fail(CELL_E_ARG, "null argument");
-  if (!c->solved) return fail(CELL_E_STATE, "no solution available");
+  if (!c->solved || !c->linear_results) return fail(CELL_E_STATE, "no linear solution available");
   const double* h = homog_of(c, 0);
   for (int i = 0; i < c->nload_solved * c->nload_solved; ++i) C_out[i] = h[i];
   return CELL_OK;
@@ -303,6 +303,45 @@ cell_status cell_profile(cell_t c, int enable) {
 cell_status cell_profile_read(cell_t c, double* ms_out, long long* launches_out) {
   if (!c || !ms_out || !launches_out) return fail(CELL_E_ARG, "null argument");
   return instance_profile_read(c, ms_out, launches_out);
+}
+
+cell_status cell_solve_hyper(cell_t c, int nload, const double* F_bar, double tol, int max_newton, double* P_out,
+                             cell_hyper_info* info) {
+  const double t0 = now_s();
+  if (!c || !F_bar) return fail(CELL_E_ARG, "null argument");
+  if (nload < 1 || nload > c->lpc) return fail(CELL_E_ARG, "nload must be in [1, max_loads]");
+  if (!c->have_mat[0]) return fail(CELL_E_STATE, "cell_set_material has not been called");
+  if (tol < 0.0 || !std::isfinite(tol) || max_newton < 0) return fail(CELL_E_ARG, "invalid tol or max_newton");
+  const int d = c->d;
+  for (int j = 0; j < nload; ++j) {
+    const double* F = F_bar + j * d * d;
+    for (int i = 0; i < d * d; ++i)
+      if (!std::isfinite(F[i])) return fail(CELL_E_ARG, "non-finite F_bar");
+    const double det = d == 3 ? F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+                                    F[2] * (F[3] * F[7] - F[4] * F[6])
+                              : F[0] * F[3] - F[1] * F[2];
+    if (!(det > 0.0)) return fail(CELL_E_ARG, "F_bar must have a positive determinant");
+  }
+  DevGuard dg(c->dev);
+  const cell_status st =
+      instance_hyper_solve(c, nload, F_bar, tol > 0.0 ? tol : 1e-10, max_newton > 0 ? max_newton : 50, P_out, info);
+  if (info) info->seconds = now_s() - t0;
+  return st;
+}
+
+cell_status cell_apply_hyper_tangent(cell_t c, int precision, const double* F_bar, const double* u, const double* p,
+                                     double* q_out) {
+  if (!c || !F_bar || !u || !p || !q_out) return fail(CELL_E_ARG, "null argument");
+  if (!c->have_mat[0]) return fail(CELL_E_STATE, "cell_set_material has not been called");
+  DevGuard dg(c->dev);
+  return instance_hyper_step(c, precision, F_bar, u, p, q_out, nullptr);
+}
+
+cell_status cell_hyper_residual(cell_t c, const double* F_bar, const double* u, double* f_out, double* sums_out) {
+  if (!c || !F_bar || !u || !f_out) return fail(CELL_E_ARG, "null argument");
+  if (!c->have_mat[0]) return fail(CELL_E_STATE, "cell_set_material has not been called");
+  DevGuard dg(c->dev);
+  return instance_hyper_step(c, CELL_FP64, F_bar, u, nullptr, f_out, sums_out);
 }
 
 cell_status cell_autotune(cell_t c, int force) {

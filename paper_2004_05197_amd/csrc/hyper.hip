@@ -1,0 +1,368 @@
+// Compressible neo-Hookean cell problem (gfx950): the nonlinear residual,
+// the tangent operator and the small vector kernels of Newton's method.
+//
+// Energy density (Sec. 2.2, eq. NeoHookeanEnergy), J = det F:
+//   W(F) = lambda/2 (ln J)^2 - mu ln J + mu/2 (|F|^2 - d),
+//   P(F) = mu (F - F^-T) + lambda ln J F^-T,
+//   dP   = mu dF + (mu - lambda ln J) F^-T dF^T F^-T + lambda tr(F^-1 dF) F^-T,
+// with F = F_bar + grad u on every simplex of the Kuhn subdivision (2D: the
+// in-plane block, plane strain).  On simplex s with axis order
+// (p_0, .., p_{d-1}) and path vertices v_0 = 0, v_{k+1} = v_k + e_{p_k},
+// grad u has the columns (u(v_{k+1}) - u(v_k)) / h_{p_k} and the
+// barycentric gradient of v_k is e_{p_{k-1}}/h_{p_{k-1}} - e_{p_k}/h_{p_k}.
+//
+// The kernels are node-centric gathers: every thread owns one node and sums
+// the contributions of the simplices of its 2^d voxels that contain it, so
+// each output is written once, without atomics (deterministic).
+//   MODE 0: q = K_T(u) p, p.q partials                     (T = float/double)
+//   MODE 1: r = rhs - K_T(u) du, ||r||^2 partials          (FP64, r as TO)
+//   MODE 2: f = -sum |s| B^T P(F), ||f||^2 partials, and per own voxel the
+//           sums of |s| W and |s| P (energy, mean stress)  (FP64)
+#include "kernels.h"
+
+namespace cellfft {
+
+namespace {
+
+__device__ __forceinline__ int hwrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <int D> struct KuhnPerm;
+template <> struct KuhnPerm<3> {
+  static constexpr int n = 6;
+  static constexpr int p[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+};
+template <> struct KuhnPerm<2> {
+  static constexpr int n = 2;
+  static constexpr int p[2][2] = {{0, 1}, {1, 0}};
+};
+
+// inverse (cofactor / det), det
+template <typename T>
+__device__ __forceinline__ T inv3(const T (&F)[3][3], T (&Fi)[3][3]) {
+  const T c00 = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  const T c01 = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  const T c02 = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  const T det = F[0][0] * c00 + F[0][1] * c01 + F[0][2] * c02;
+  const T id = T(1) / det;
+  Fi[0][0] = c00 * id;
+  Fi[1][0] = c01 * id;
+  Fi[2][0] = c02 * id;
+  Fi[0][1] = (F[0][2] * F[2][1] - F[0][1] * F[2][2]) * id;
+  Fi[1][1] = (F[0][0] * F[2][2] - F[0][2] * F[2][0]) * id;
+  Fi[2][1] = (F[0][1] * F[2][0] - F[0][0] * F[2][1]) * id;
+  Fi[0][2] = (F[0][1] * F[1][2] - F[0][2] * F[1][1]) * id;
+  Fi[1][2] = (F[0][2] * F[1][0] - F[0][0] * F[1][2]) * id;
+  Fi[2][2] = (F[0][0] * F[1][1] - F[0][1] * F[1][0]) * id;
+  return det;
+}
+
+template <typename T>
+__device__ __forceinline__ T inv2(const T (&F)[2][2], T (&Fi)[2][2]) {
+  const T det = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  const T id = T(1) / det;
+  Fi[0][0] = F[1][1] * id;
+  Fi[1][1] = F[0][0] * id;
+  Fi[0][1] = -F[0][1] * id;
+  Fi[1][0] = -F[1][0] * id;
+  return det;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T invD(const T (&F)[D][D], T (&Fi)[D][D]) {
+  if constexpr (D == 3) return inv3(F, Fi);
+  else return inv2(F, Fi);
+}
+
+}  // namespace
+
+template <typename T, typename TO, int MODE, int D>
+__global__ __launch_bounds__(NT) void k_hyper(HyArgs<T> a) {
+  __shared__ double sh[NT / WAVE];
+  constexpr int NCORN = 1 << D;
+  const int l = blockIdx.y;
+  bool live;
+  if (MODE == 0) live = a.st[l].state == ST_ACTIVE;
+  else live = a.mask ? a.mask[l] != 0 : true;
+  if (!live) return;
+  const Geom& g = a.g;
+  const int nx = g.nx, ny = g.ny, nz = D == 3 ? g.nz : 1;
+  const long long n = g.n;
+  T ih[3] = {T(1.0 / g.h[0]), T(1.0 / g.h[1]), T(1.0 / g.h[2])};
+  const T vol = T(D == 3 ? g.h[0] * g.h[1] * g.h[2] / 6.0 : g.h[0] * g.h[1] / 2.0);
+  const T* u = a.u + l * a.lstride;
+  const T* p = a.p ? a.p + l * a.lstride : nullptr;
+  const T* matl = a.mat + (long long)(l / a.lpc) * a.mat_stride;
+  T Fb[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) Fb[i][j] = (T)a.Fbar[l * 9 + i * 3 + j];
+  double acc = 0.0;
+  double own[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // MODE 2: |s| W, |s| P (row-major 3 x 3)
+  for (long long node = (long long)blockIdx.x * NT + threadIdx.x; node < n; node += (long long)gridDim.x * NT) {
+    const int i = (int)(node % nx);
+    const int j = (int)((node / nx) % ny);
+    const int k = D == 3 ? (int)(node / ((long long)nx * ny)) : 0;
+    T force[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) force[c] = T(0);
+    // the node is corner `cn` of the voxel at node - offset(cn) (cn is
+    // uniform across the block; the simplex loop is unrolled, the corner
+    // loop is not, to keep the register footprint of one voxel)
+#pragma unroll 1
+    for (int cn = 0; cn < NCORN; ++cn) {
+      const int vi = hwrap(i - (cn & 1), nx), vj = hwrap(j - ((cn >> 1) & 1), ny);
+      const int vk = D == 3 ? hwrap(k - ((cn >> 2) & 1), nz) : 0;
+      const long long vid = ((long long)vk * ny + vj) * nx + vi;
+      const T lam = matl[2 * vid], mu = matl[2 * vid + 1];
+      T uu[NCORN][D], pp[NCORN][D];
+#pragma unroll
+      for (int q = 0; q < NCORN; ++q) {
+        const long long nd = ((long long)(D == 3 ? hwrap(vk + ((q >> 2) & 1), nz) : 0) * ny +
+                              hwrap(vj + ((q >> 1) & 1), ny)) * nx + hwrap(vi + (q & 1), nx);
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          uu[q][c] = u[c * n + nd];
+          pp[q][c] = (MODE != 2 && p) ? p[c * n + nd] : T(0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < KuhnPerm<D>::n; ++t) {
+        int path[D + 1];
+        path[0] = 0;
+#pragma unroll
+        for (int m = 0; m < D; ++m) path[m + 1] = path[m] | (1 << KuhnPerm<D>::p[t][m]);
+        bool on_path = false;
+#pragma unroll
+        for (int m = 0; m <= D; ++m) on_path = on_path || path[m] == cn;
+        const bool own_voxel = MODE == 2 && cn == 0;
+        if (!on_path && !own_voxel) continue;
+        // F = F_bar + grad u, dG = grad p
+        T F[D][D], dG[D][D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+          const int ax = KuhnPerm<D>::p[t][m];
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            F[c][ax] = Fb[c][ax] + (uu[path[m + 1]][c] - uu[path[m]][c]) * ih[ax];
+            dG[c][ax] = (pp[path[m + 1]][c] - pp[path[m]][c]) * ih[ax];
+          }
+        }
+        T Fi[D][D];
+        const T J = invD<T, D>(F, Fi);
+        const T lnJ = J > T(0) ? log(J) : T(NAN);
+        T P[D][D];
+        if (MODE == 2) {
+          T ff = T(0);
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+              P[r][c] = mu * (F[r][c] - Fi[c][r]) + lam * lnJ * Fi[c][r];
+              ff += F[r][c] * F[r][c];
+            }
+          if (own_voxel) {
+            own[0] += (double)(vol * (T(0.5) * lam * lnJ * lnJ - mu * lnJ + T(0.5) * mu * (ff - T(D))));
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+#pragma unroll
+              for (int c = 0; c < D; ++c) own[1 + r * 3 + c] += (double)(vol * P[r][c]);
+          }
+        } else {
+          // dP = mu dG + (mu - lam lnJ) (Fi dG Fi)^T + lam tr(Fi dG) Fi^T
+          T M[D][D], tr = T(0);
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+              T s1 = T(0);
+#pragma unroll
+              for (int x = 0; x < D; ++x) s1 += Fi[r][x] * dG[x][c];
+              M[r][c] = s1;  // (Fi dG)_rc
+            }
+#pragma unroll
+          for (int r = 0; r < D; ++r) tr += M[r][r];
+          T N[D][D];
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+              T s1 = T(0);
+#pragma unroll
+              for (int x = 0; x < D; ++x) s1 += M[r][x] * Fi[x][c];
+              N[r][c] = s1;  // (Fi dG Fi)_rc
+            }
+          const T cm = mu - lam * lnJ, cl = lam * tr;
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = 0; c < D; ++c) P[r][c] = mu * dG[r][c] + cm * N[c][r] + cl * Fi[c][r];
+        }
+        // node force: |s| P g_m for the path vertex v_m = this corner,
+        // g_m = e_{p_{m-1}}/h_{p_{m-1}} - e_{p_m}/h_{p_m}
+#pragma unroll
+        for (int m = 0; m <= D; ++m) {
+          if (path[m] != cn) continue;
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            T v = T(0);
+            if (m > 0) v += P[c][KuhnPerm<D>::p[t][m > 0 ? m - 1 : 0]] * ih[KuhnPerm<D>::p[t][m > 0 ? m - 1 : 0]];
+            if (m < D) v -= P[c][KuhnPerm<D>::p[t][m < D ? m : 0]] * ih[KuhnPerm<D>::p[t][m < D ? m : 0]];
+            force[c] += vol * v;
+          }
+        }
+      }
+    }
+    // outputs
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const long long o = l * a.lstride + c * n + node;
+      if (MODE == 0) {
+        reinterpret_cast<TO*>(a.out)[o] = (TO)force[c];
+        acc += (double)(p ? p[c * n + node] : T(0)) * (double)force[c];
+      } else if (MODE == 1) {
+        const double rv = a.rhs[o] - (double)force[c];
+        reinterpret_cast<TO*>(a.out)[o] = (TO)rv;
+        acc += rv * rv;
+      } else {
+        const double fv = -(double)force[c];
+        reinterpret_cast<double*>(a.out)[o] = fv;
+        acc += fv * fv;
+      }
+    }
+  }
+  const double bs = block_sum<NT>(acc, sh);
+  if (threadIdx.x == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blockIdx.x] = bs;
+  if (MODE == 2) {
+    for (int v = 0; v < 10; ++v) {
+      const double s = block_sum<NT>(own[v], sh);
+      if (threadIdx.x == 0) a.vparts[((long long)l * 10 + v) * a.red.maxblk + blockIdx.x] = s;
+    }
+  }
+}
+
+// per slot: fixed-order sums of nval partial rows -> vals[slot][nval]
+__global__ __launch_bounds__(NT) void k_sum_vals(const double* parts, int maxblk, int nparts, int nval,
+                                                 const int* mask, double* vals) {
+  __shared__ double sh[NT / WAVE];
+  const int v = blockIdx.x, l = blockIdx.y;
+  if (mask && mask[l] == 0) return;
+  const double* row = parts + ((long long)l * nval + v) * maxblk;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NT) s += row[i];
+  s = block_sum<NT>(s, sh);
+  if (threadIdx.x == 0) vals[(long long)l * nval + v] = s;
+}
+
+// y[slot] = x[slot] + t[slot] * d[slot] for the masked slots
+__global__ void k_axpy_slots(const double* x, const double* t, const double* d, double* y, long long len,
+                             const int* mask) {
+  const int l = blockIdx.y;
+  if (mask && mask[l] == 0) return;
+  const double tl = t[l];
+  const long long o = (long long)l * len;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long long)gridDim.x * blockDim.x)
+    y[o + i] = x[o + i] + tl * d[o + i];
+}
+
+// y[slot] = (TO) x[slot] for the masked slots (mask == nullptr: all)
+template <typename TI, typename TO>
+__global__ void k_copy_slots(const TI* x, TO* y, long long len, const int* mask) {
+  const int l = blockIdx.y;
+  if (mask && mask[l] == 0) return;
+  const long long o = (long long)l * len;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long long)gridDim.x * blockDim.x)
+    y[o + i] = (TO)x[o + i];
+}
+
+// x[slot] = 0 for the masked slots
+__global__ void k_zero_slots(double* x, long long len, const int* mask) {
+  const int l = blockIdx.y;
+  if (mask && mask[l] == 0) return;
+  const long long o = (long long)l * len;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (long long)gridDim.x * blockDim.x)
+    x[o + i] = 0.0;
+}
+
+// partials of a[slot] . b[slot] (FP64) into the RES slot of the reduction buffer
+__global__ __launch_bounds__(NT) void k_dot_slots(const double* x, const double* y, long long len, const int* mask,
+                                                  RedBuf red) {
+  __shared__ double sh[NT / WAVE];
+  const int l = blockIdx.y;
+  if (mask && mask[l] == 0) return;
+  const long long o = (long long)l * len;
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < len; i += (long long)gridDim.x * NT)
+    s += x[o + i] * y[o + i];
+  s = block_sum<NT>(s, sh);
+  if (threadIdx.x == 0) red.slot_parts(RED_RES, l)[blockIdx.x] = s;
+}
+
+int hyper_blocks(const Geom& g, int maxblk) {
+  const long long nb = (g.n + NT - 1) / NT;
+  return (int)(nb < maxblk ? nb : maxblk);
+}
+
+template <typename T, typename TO, int MODE>
+static hipError_t launch_hyper_impl(const HyArgs<T>& a, hipStream_t s) {
+  const int nb = hyper_blocks(a.g, a.red.maxblk);
+  dim3 grid(nb, a.nload);
+  if (a.g.dim == 3) hipLaunchKernelGGL((k_hyper<T, TO, MODE, 3>), grid, dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL((k_hyper<T, TO, MODE, 2>), grid, dim3(NT), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_finalize(a.red, a.st, a.res2, MODE == 0 ? RED_PQ : RED_RES, nb, a.nload, -1, MODE == 0 ? nullptr : a.mask, s);
+  if (e != hipSuccess || MODE != 2) return e;
+  hipLaunchKernelGGL(k_sum_vals, dim3(10, a.nload), dim3(NT), 0, s, (const double*)a.vparts, a.red.maxblk, nb, 10,
+                     a.mask, a.vals);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hyper_tangent(const HyArgs<T>& a, hipStream_t s) {
+  return launch_hyper_impl<T, T, 0>(a, s);
+}
+
+hipError_t launch_hyper_tangent_residual(const HyArgs<double>& a, bool out32, hipStream_t s) {
+  return out32 ? launch_hyper_impl<double, float, 1>(a, s) : launch_hyper_impl<double, double, 1>(a, s);
+}
+
+hipError_t launch_hyper_residual(const HyArgs<double>& a, hipStream_t s) {
+  return launch_hyper_impl<double, double, 2>(a, s);
+}
+
+hipError_t launch_axpy_slots(const double* x, const double* t, const double* d, double* y, long long len, int nslot,
+                             const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_slots, dim3(512, nslot), dim3(256), 0, s, x, t, d, y, len, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_slots(const double* x, double* y, long long len, int nslot, const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy_slots<double, double>), dim3(512, nslot), dim3(256), 0, s, x, y, len, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_slots(const double* x, float* y, long long len, int nslot, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy_slots<double, float>), dim3(512, nslot), dim3(256), 0, s, x, y, len,
+                     (const int*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_slots(double* x, long long len, int nslot, const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_slots, dim3(512, nslot), dim3(256), 0, s, x, len, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_slots(const double* x, const double* y, long long len, int nslot, const int* mask,
+                            const RedBuf& red, LoadState* st, double* res2, hipStream_t s) {
+  const int nb = red.maxblk < 1024 ? red.maxblk : 1024;
+  hipLaunchKernelGGL(k_dot_slots, dim3(nb, nslot), dim3(NT), 0, s, x, y, len, mask, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(red, st, res2, RED_RES, nb, nslot, -1, mask, s);
+}
+
+template hipError_t launch_hyper_tangent<float>(const HyArgs<float>&, hipStream_t);
+template hipError_t launch_hyper_tangent<double>(const HyArgs<double>&, hipStream_t);
+
+}  // namespace cellfft

@@ -141,6 +141,43 @@ template <typename T> struct KArgs {
   RedBuf red;
 };
 
+// ------------------------------------------------- neo-Hookean (Newton) path
+template <typename T> struct HyArgs {
+  const T* u;           // Newton state: F = F_bar + grad u, [slot][d][n]
+  const T* p;           // mode 0: direction; mode 1: correction du (nullptr = 0)
+  void* out;            // mode 0: q (T); mode 1: r (float or double); mode 2: f (double)
+  const double* rhs;    // mode 1: Newton right-hand side [slot][d][n]
+  const T* mat;         // (lambda, mu) per voxel, [cell][n][2]
+  long long mat_stride;
+  long long lstride;    // reals per slot
+  Geom g;
+  const double* Fbar;   // [slot][3][3] macroscopic deformation gradients (row-major)
+  int nload;            // slots in the launch
+  int lpc;              // slots per cell
+  LoadState* st;        // mode 0: per-slot state (active slots only)
+  const int* mask;      // modes 1, 2: slots to compute (nullptr = all)
+  double* res2;         // per-slot ||out||^2 (modes 1, 2)
+  double* vparts;       // mode 2: per-block sums [slot][10][maxblk]: |s| W, |s| P (3 x 3)
+  double* vals;         // mode 2: [slot][10] finalised sums
+  RedBuf red;
+};
+
+// q = K_T(u) p (T arithmetic) with the PCG scalar update of the p.q partials
+template <typename T> hipError_t launch_hyper_tangent(const HyArgs<T>& a, hipStream_t s);
+// r = rhs - K_T(u) du in FP64 (written as float if out32), ||r||^2
+hipError_t launch_hyper_tangent_residual(const HyArgs<double>& a, bool out32, hipStream_t s);
+// f = -sum |s| B^T P(F) in FP64, ||f||^2, energy and mean-stress sums
+hipError_t launch_hyper_residual(const HyArgs<double>& a, hipStream_t s);
+int hyper_blocks(const Geom& g, int maxblk);
+hipError_t launch_axpy_slots(const double* x, const double* t, const double* d, double* y, long long len, int nslot,
+                             const int* mask, hipStream_t s);
+hipError_t launch_copy_slots(const double* x, double* y, long long len, int nslot, const int* mask, hipStream_t s);
+hipError_t launch_round_slots(const double* x, float* y, long long len, int nslot, hipStream_t s);
+hipError_t launch_zero_slots(double* x, long long len, int nslot, const int* mask, hipStream_t s);
+// per-slot x . y (FP64) into res2 for the masked slots
+hipError_t launch_dot_slots(const double* x, const double* y, long long len, int nslot, const int* mask,
+                            const RedBuf& red, LoadState* st, double* res2, hipStream_t s);
+
 // effective stiffness / adjoint
 struct HArgs {
   const double* u;      // solved fluctuations [nload][d][n]

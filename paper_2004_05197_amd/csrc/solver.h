@@ -77,6 +77,18 @@ struct cell_s {
   double* grad = nullptr;
   double* scratch = nullptr;
   int hblk = 0;
+  // neo-Hookean Newton path
+  int op = 0;                   // PCG operator: 0 linear elasticity, 1 neo-Hookean tangent
+  double* hy_u = nullptr;       // Newton state [nslot][d n]
+  float* hy_u32 = nullptr;      // its FP32 rounding (mixed-precision tangent)
+  double* hy_ut = nullptr;      // line-search trial state
+  double* hy_rhs = nullptr;     // f(u) = -grad Pi [nslot][d n]
+  double* hy_F = nullptr;       // [nslot][9] macroscopic deformation gradients
+  double* hy_t = nullptr;       // [nslot] line-search steps
+  double* hy_vparts = nullptr;  // [nslot][10][maxblk] energy / stress partials
+  double* hy_vals = nullptr;    // [nslot][10]
+  double* hy_vals_h = nullptr;  // pinned host copy
+  bool linear_results = false;  // homog / residual hold the last linear solve
   // last solve
   int nload_solved = 0;
   double eps_v[6][6] = {};
@@ -116,10 +128,19 @@ cell_status instance_solve(cell_s* c, int nload, const double* eps, cell_info* i
 // single steps on slot 0 of cell 0 (host vectors [d][n]); invalidate the last solve
 cell_status instance_apply_operator(cell_s* c, int precision, const double* u, double* q);
 cell_status instance_apply_precond(cell_s* c, int precision, const double* r, double* z);
+// neo-Hookean single steps on slot 0: p != nullptr: out = K_T(u) p (precision);
+// p == nullptr: out = f(u) = -grad Pi in FP64, vals[10] = sum |s| W, sum |s| P
+cell_status instance_hyper_step(cell_s* c, int precision, const double* Fbar, const double* u, const double* p,
+                                double* out, double* vals);
 cell_status instance_profile(cell_s* c, int enable);
 cell_status instance_profile_read(cell_s* c, double* ms_out, long long* launches_out);
 // autotuner: schedule from the cache (unless force) or by timing the variants
 cell_status instance_autotune(cell_s* c, int force);
+// neo-Hookean cell problem for nload macroscopic deformation gradients
+// (host [nload][d][d]); results per cell: P_out [ncell][nload][d][d] (mean
+// first Piola stress), infos [ncell] (may be nullptr)
+cell_status instance_hyper_solve(cell_s* c, int nload, const double* Fbar, double tol, int max_newton,
+                                 double* P_out, cell_hyper_info* infos);
 void instance_get_schedule(cell_s* c, int* out);            // SCHED_NFIELD ints
 cell_status instance_set_schedule(cell_s* c, const int* in);
 

@@ -335,6 +335,31 @@ XArgs<T> xargs(cell_s* c) {
   return xa;
 }
 
+// neo-Hookean operator arguments (state u in the arithmetic type)
+template <typename T> const T* hy_state(cell_s* c);
+template <> const float* hy_state<float>(cell_s* c) { return c->hy_u32; }
+template <> const double* hy_state<double>(cell_s* c) { return c->hy_u; }
+
+template <typename T>
+HyArgs<T> hyargs(cell_s* c) {
+  HyArgs<T> h{};
+  h.u = hy_state<T>(c);
+  h.mat = mat_of<T>(c);
+  h.mat_stride = 2 * c->n;
+  h.lstride = c->lstride;
+  h.g = c->g;
+  h.Fbar = c->hy_F;
+  h.nload = c->nslot;
+  h.lpc = c->lpc;
+  h.st = c->st;
+  h.mask = nullptr;
+  h.res2 = c->res2;
+  h.vparts = c->hy_vparts;
+  h.vals = c->hy_vals;
+  h.red = red_of(c);
+  return h;
+}
+
 // one PCG iteration over all slots (or the initial preconditioning if !kapply)
 template <typename T>
 cell_status iteration(cell_s* c, bool kapply) {
@@ -342,9 +367,16 @@ cell_status iteration(cell_s* c, bool kapply) {
   hipStream_t s = c->stream;
   const int ns = c->nslot;
   if (kapply) {
-    KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c));
     ProfScope ps(c, CELL_K_APPLY);
-    HIPCHK(launch_stencil<T>(ka, c->sched, s));
+    if (c->op == 1) {
+      HyArgs<T> ha = hyargs<T>(c);
+      ha.p = F.p;
+      ha.out = F.q;
+      HIPCHK(launch_hyper_tangent<T>(ha, s));
+    } else {
+      KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c));
+      HIPCHK(launch_stencil<T>(ka, c->sched, s));
+    }
   }
   XArgs<T> xa = xargs<T>(c);
   if (kapply) {
@@ -403,6 +435,21 @@ cell_status iteration(cell_s* c, bool kapply) {
 template <typename T>
 cell_status residual(cell_s* c, const double* u, const int* mask) {
   Fields<T>& F = fields<T>(c);
+  if (c->op == 1) {
+    // Newton step: r = f(u) - K_T(u) du
+    HyArgs<double> ha = hyargs<double>(c);
+    ha.p = u;
+    ha.rhs = c->hy_rhs;
+    ha.out = F.r;
+    ha.mask = mask;
+    {
+      ProfScope ps(c, CELL_K_RESIDUAL);
+      HIPCHK(launch_hyper_tangent_residual(ha, sizeof(T) == 4, c->stream));
+    }
+    HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * c->nslot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CELL_OK;
+  }
   KArgs<double> ka = kargs<double>(c, 1, u, nullptr, c->mat64);
   ka.mask = mask;
   ka.sparts = c->sparts;
@@ -676,6 +723,15 @@ void instance_destroy(cell_s* c) {
   fr(c->hres);
   fr(c->grad);
   fr(c->scratch);
+  fr(c->hy_u);
+  fr(c->hy_u32);
+  fr(c->hy_ut);
+  fr(c->hy_rhs);
+  fr(c->hy_F);
+  fr(c->hy_t);
+  fr(c->hy_vparts);
+  fr(c->hy_vals);
+  if (c->hy_vals_h) (void)hipHostFree(c->hy_vals_h);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->st_h) (void)hipHostFree(c->st_h);
   if (c->res2_h) (void)hipHostFree(c->res2_h);
@@ -876,7 +932,10 @@ cell_status solve_end(SolveRun& R) {
   cell_s* c = R.c;
   const cell_status st = end_t(R);
   if (st < 0) return st;
-  STCHK(homogenize(c, R.nload));
+  if (c->op == 0) {
+    STCHK(homogenize(c, R.nload));
+    c->linear_results = true;
+  }
   c->solved = true;
   c->nload_solved = R.nload;
   return st;
@@ -891,6 +950,214 @@ cell_status instance_solve(cell_s* c, int nload, const double* eps, cell_info* i
     STCHK(solve_poll(R));
   }
   return solve_end(R);
+}
+
+// =================================================== neo-Hookean (Newton)
+namespace {
+
+cell_status ensure_hyper(cell_s* c) {
+  if (c->hy_u) return CELL_OK;
+  const size_t fb = sizeof(double) * (size_t)c->lstride * c->nslot;
+  auto dm = [&](void** p, size_t b) { return hipMalloc(p, b) == hipSuccess; };
+  if (!dm((void**)&c->hy_u, fb) || !dm((void**)&c->hy_ut, fb) || !dm((void**)&c->hy_rhs, fb) ||
+      !dm((void**)&c->hy_F, sizeof(double) * 9 * c->nslot) || !dm((void**)&c->hy_t, sizeof(double) * c->nslot) ||
+      !dm((void**)&c->hy_vparts, sizeof(double) * 10 * (size_t)c->nslot * c->maxblk) ||
+      !dm((void**)&c->hy_vals, sizeof(double) * 10 * c->nslot) ||
+      (c->precision == CELL_MIXED && !dm((void**)&c->hy_u32, sizeof(float) * (size_t)c->lstride * c->nslot)))
+    return fail(CELL_E_NOMEM, "device allocation of the Newton state failed");
+  if (hipHostMalloc((void**)&c->hy_vals_h, sizeof(double) * 10 * c->nslot) != hipSuccess)
+    return fail(CELL_E_NOMEM, "pinned host allocation failed");
+  return CELL_OK;
+}
+
+// f(u), ||f||^2, sum |s| W and sum |s| P of the masked slots at state u
+// (FP64); results in res2_h and hy_vals_h
+cell_status hyper_eval(cell_s* c, const double* u, const int* mask) {
+  HyArgs<double> ha = hyargs<double>(c);
+  ha.u = u;
+  ha.out = c->hy_rhs;
+  ha.mask = mask;
+  {
+    ProfScope ps(c, CELL_K_RESIDUAL);
+    HIPCHK(launch_hyper_residual(ha, c->stream));
+  }
+  HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * c->nslot, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(c->hy_vals_h, c->hy_vals, sizeof(double) * 10 * c->nslot, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CELL_OK;
+}
+
+// the pinned mask is read by the copy when the stream reaches it: drain the
+// stream before rewriting it (an earlier queued copy would see the new mask)
+cell_status upload_mask(cell_s* c, const std::vector<int>& m) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int l = 0; l < c->nslot; ++l) c->mask_h[l] = m[l];
+  HIPCHK(hipMemcpyAsync(c->mask, c->mask_h, sizeof(int) * c->nslot, hipMemcpyHostToDevice, c->stream));
+  return CELL_OK;
+}
+
+cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int max_newton, double* P_out,
+                      cell_hyper_info* infos) {
+  const int ns = c->nslot, d = c->d, lpc = c->lpc;
+  const long long len = c->lstride;
+  hipStream_t s = c->stream;
+  STCHK(c->precision == CELL_MIXED ? ensure_fields<float>(c) : ensure_fields<double>(c));
+  STCHK(ensure_hyper(c));
+  c->solved = false;
+  c->solved_unit = false;
+  c->linear_results = false;
+  std::vector<double> Fh(9 * (size_t)ns, 0.0);
+  std::vector<int> act(ns, 0), done(ns, 1), searching(ns, 0);
+  std::vector<double> scale(ns, 0.0), E(ns, 0.0), fn(ns, 0.0), slope(ns, 0.0), t(ns, 1.0), dE(ns, 0.0);
+  const double vol = d == 3 ? c->g.h[0] * c->g.h[1] * c->g.h[2] * c->n : c->g.h[0] * c->g.h[1] * c->n;
+  for (int l = 0; l < ns; ++l) {
+    const int j = l % lpc;
+    for (int a = 0; a < 3; ++a) Fh[9 * l + 4 * a] = 1.0;
+    if (j >= nload) continue;
+    act[l] = 1;
+    done[l] = 0;
+    double fmax = 1.0;
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        Fh[9 * l + 3 * a + b] = Fb[(j * d + a) * d + b];
+        fmax = std::max(fmax, std::fabs(Fb[(j * d + a) * d + b]));
+      }
+    scale[l] = vol * c->maxmod[l / lpc] * fmax;
+    // rounding level of the energy sum (terms of size modulus (|F|^2 + d))
+    dE[l] = 1e-13 * vol * c->maxmod[l / lpc] * d * (1.0 + fmax * fmax);
+  }
+  HIPCHK(hipMemcpyAsync(c->hy_F, Fh.data(), sizeof(double) * 9 * ns, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_zero_slots(c->hy_u, len, ns, nullptr, s));
+  STCHK(upload_mask(c, act));
+  STCHK(hyper_eval(c, c->hy_u, c->mask));
+  std::vector<double> ref(ns, 0.0);
+  for (int l = 0; l < ns; ++l) {
+    if (!act[l]) continue;
+    fn[l] = std::sqrt(c->res2_h[l]);
+    E[l] = c->hy_vals_h[10 * l];
+    if (!std::isfinite(E[l])) return fail(CELL_E_ARG, "the macroscopic gradient has det <= 0 in slot " + std::to_string(l));
+    ref[l] = std::max(fn[l], scale[l]);
+  }
+  std::vector<int> nit(ns, 0), ncg(ns, 0);
+  std::vector<double> zeros(36, 0.0);
+  std::vector<cell_info> cgi(c->ncell);
+  const double* du = c->precision == CELL_MIXED ? c->x64 : c->f64.x;
+  for (int it = 0;; ++it) {
+    bool all = true;
+    for (int l = 0; l < ns; ++l) {
+      if (!act[l]) continue;
+      done[l] = fn[l] <= tol * ref[l];
+      if (!done[l]) all = false;
+    }
+    if (all || it >= max_newton) break;
+    // tangent state; the converged slots get a zero right-hand side (their
+    // PCG stops at once)
+    if (c->precision == CELL_MIXED) HIPCHK(launch_round_slots(c->hy_u, c->hy_u32, len, ns, s));
+    STCHK(upload_mask(c, done));
+    HIPCHK(launch_zero_slots(c->hy_rhs, len, ns, c->mask, s));
+    c->op = 1;
+    {
+      SolveRun R;
+      cell_status st = solve_begin(R, c, nload, zeros.data(), cgi.data());
+      while (st >= 0 && !R.done) {
+        st = solve_launch(R);
+        if (st >= 0) {
+          const hipError_t e = hipStreamSynchronize(s);
+          if (e != hipSuccess) st = fail(CELL_E_DEVICE, hipGetErrorString(e));
+        }
+        if (st >= 0) st = solve_poll(R);
+      }
+      if (st >= 0) st = solve_end(R);
+      c->op = 0;
+      if (st < 0) return st;
+    }
+    for (int l = 0; l < ns; ++l)
+      if (act[l] && !done[l]) ncg[l] += cgi[l / lpc].iters[l % lpc];
+    // slope f . du, then the line search on the energy
+    for (int l = 0; l < ns; ++l) searching[l] = act[l] && !done[l];
+    STCHK(upload_mask(c, searching));
+    HIPCHK(launch_dot_slots(c->hy_rhs, du, len, ns, c->mask, red_of(c), c->st, c->res2, s));
+    HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int l = 0; l < ns; ++l) {
+      slope[l] = c->res2_h[l];
+      t[l] = 1.0;
+    }
+    for (int ls = 0;; ++ls) {
+      bool any = false;
+      for (int l = 0; l < ns; ++l) any = any || searching[l];
+      if (!any) break;
+      if (ls == 40) return fail(CELL_E_BREAKDOWN, "Newton line search found no admissible step");
+      STCHK(upload_mask(c, searching));
+      HIPCHK(hipMemcpyAsync(c->hy_t, t.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+      HIPCHK(launch_axpy_slots(c->hy_u, c->hy_t, du, c->hy_ut, len, ns, c->mask, s));
+      STCHK(hyper_eval(c, c->hy_ut, c->mask));
+      std::vector<int> acc(ns, 0);
+      for (int l = 0; l < ns; ++l) {
+        if (!searching[l]) continue;
+        const double Et = c->hy_vals_h[10 * l], fnt = std::sqrt(c->res2_h[l]);
+        // Armijo on the energy; where the change is below the energy's
+        // rounding level, a decrease of the residual norm instead
+        const bool armijo = Et <= E[l] - 1e-4 * t[l] * slope[l];
+        const bool flat = Et - E[l] <= dE[l] && fnt <= (1.0 - 1e-4 * t[l]) * fn[l];
+        if (std::isfinite(Et) && (armijo || flat)) {
+          acc[l] = 1;
+          searching[l] = 0;
+          E[l] = Et;
+          fn[l] = fnt;
+          nit[l] += 1;
+        } else {
+          t[l] *= 0.5;
+        }
+      }
+      STCHK(upload_mask(c, acc));
+      HIPCHK(launch_copy_slots(c->hy_ut, c->hy_u, len, ns, c->mask, s));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  // results of the last accepted evaluation of every slot
+  if (P_out)
+    for (int l = 0; l < ns; ++l) {
+      if (!act[l]) continue;
+      const int cell = l / lpc, j = l % lpc;
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b)
+          P_out[(((size_t)cell * nload + j) * d + a) * d + b] = c->hy_vals_h[10 * l + 1 + 3 * a + b] / vol;
+    }
+  if (infos)
+    for (int l = 0; l < ns; ++l) {
+      if (!act[l]) continue;
+      cell_hyper_info& I = infos[l / lpc];
+      const int j = l % lpc;
+      I.nload = nload;
+      I.newton_iters[j] = nit[l];
+      I.cg_iters[j] = ncg[l];
+      I.resnorm[j] = ref[l] > 0 ? fn[l] / ref[l] : 0.0;
+      I.energy[j] = E[l] / vol;
+    }
+  // the fluctuations are the displacement results (mean removed on output)
+  double* sol = c->precision == CELL_MIXED ? c->x64 : c->f64.x;
+  HIPCHK(launch_copy_slots(c->hy_u, sol, len, ns, nullptr, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->solved = true;
+  c->nload_solved = nload;
+  bool conv = true;
+  for (int l = 0; l < ns; ++l)
+    if (act[l] && !(fn[l] <= tol * ref[l])) conv = false;
+  return conv ? CELL_OK : CELL_NOT_CONVERGED;
+}
+
+}  // namespace
+
+cell_status instance_hyper_solve(cell_s* c, int nload, const double* Fbar, double tol, int max_newton,
+                                 double* P_out, cell_hyper_info* infos) {
+  for (int cell = 0; cell < c->ncell; ++cell)
+    if (!c->have_mat[cell]) return fail(CELL_E_STATE, "material not set for cell " + std::to_string(cell));
+  if (infos) std::memset(infos, 0, sizeof(cell_hyper_info) * c->ncell);
+  const cell_status st = hyper_run(c, nload, Fbar, tol, max_newton, P_out, infos);
+  c->op = 0;
+  return st;
 }
 
 // ============================================ single-step entry points (tests)
@@ -956,6 +1223,54 @@ cell_status apply_precond_t(cell_s* c, const double* r, double* z) {
 }
 
 }  // namespace
+
+// neo-Hookean single steps on slot 0: q = K_T(u) p in the given precision,
+// or (p == nullptr) f = -grad Pi(u) in FP64 with the 10 sums |s| W, |s| P
+template <typename T>
+cell_status hyper_step_t(cell_s* c, const double* Fbar, const double* u, const double* p, double* out,
+                         double* vals) {
+  STCHK(ensure_fields<T>(c));
+  STCHK(ensure_hyper(c));
+  Fields<T>& F = fields<T>(c);
+  HIPCHK(hipStreamSynchronize(c->stream));  // the pinned states are rewritten below
+  c->solved = c->solved_unit = c->linear_results = false;
+  std::vector<double> Fh(9 * (size_t)c->nslot, 0.0);
+  for (int l = 0; l < c->nslot; ++l)
+    for (int a = 0; a < 3; ++a) Fh[9 * l + 4 * a] = 1.0;
+  for (int a = 0; a < c->d; ++a)
+    for (int b = 0; b < c->d; ++b) Fh[3 * a + b] = Fbar[a * c->d + b];
+  HIPCHK(hipMemcpyAsync(c->hy_F, Fh.data(), sizeof(double) * 9 * c->nslot, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->hy_u, u, sizeof(double) * c->lstride, hipMemcpyHostToDevice, c->stream));
+  if (c->hy_u32) HIPCHK(launch_round_slots(c->hy_u, c->hy_u32, c->lstride, 1, c->stream));
+  diag_state(c);
+  HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * c->nslot, hipMemcpyHostToDevice, c->stream));
+  std::vector<int> m(c->nslot, 0);
+  m[0] = 1;
+  STCHK(upload_mask(c, m));
+  if (p) {
+    STCHK(upload_field<T>(c, F.p, p));
+    HyArgs<T> ha = hyargs<T>(c);
+    if (sizeof(T) == 4 && !c->hy_u32) return fail(CELL_E_ARG, "FP32 tangent needs a mixed-precision handle");
+    ha.p = F.p;
+    ha.out = F.q;
+    HIPCHK(launch_hyper_tangent<T>(ha, c->stream));
+    return download_field<T>(c, out, F.q);
+  }
+  STCHK(hyper_eval(c, c->hy_u, c->mask));
+  std::vector<double> h(c->lstride);
+  HIPCHK(hipMemcpyAsync(out, c->hy_rhs, sizeof(double) * c->lstride, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (vals)
+    for (int v = 0; v < 10; ++v) vals[v] = c->hy_vals_h[v];
+  return CELL_OK;
+}
+
+cell_status instance_hyper_step(cell_s* c, int precision, const double* Fbar, const double* u, const double* p,
+                                double* out, double* vals) {
+  if (precision == CELL_FP64 || !p) return hyper_step_t<double>(c, Fbar, u, p, out, vals);
+  if (precision == CELL_MIXED) return hyper_step_t<float>(c, Fbar, u, p, out, vals);
+  return fail(CELL_E_ARG, "invalid precision");
+}
 
 cell_status instance_apply_operator(cell_s* c, int precision, const double* u, double* q) {
   if (precision == CELL_FP64) return apply_operator_t<double>(c, u, q);

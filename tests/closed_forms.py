@@ -30,3 +30,37 @@ def backus(lam, mu, w, d, normal):
         C[t1, t2] = C[t2, t1] = avg(2 * mu * lam / M) + lM ** 2 * inv1M
         C[idx[(t1, t2)], idx[(t1, t2)]] = avg(mu)
     return C
+
+
+def laminate_neohooke(phases, frac, Fbar):
+    """Neo-Hookean laminate with layers normal to x, phases (lambda, mu) with
+    volume fractions frac: the exact solution has F_k = F_bar + a_k (x) e_x
+    with sum frac_k a_k = 0 (compatibility) and equal tractions P(F_k) e_x
+    (equilibrium), a small nonlinear system solved here independently of any
+    finite-element code.  Returns (mean first Piola stress, energy density)."""
+    from scipy.optimize import fsolve
+    from oracle import hyper
+    d = Fbar.shape[0]
+    K = len(phases)
+
+    def Fk(a):
+        out = []
+        for k in range(K):
+            F = Fbar.copy()
+            F[:, 0] += a[k * d:(k + 1) * d]
+            out.append(F)
+        return out
+
+    def eqs(a):
+        Fs = Fk(a)
+        t = [hyper.piola(F[None], np.array([l]), np.array([m]))[0][:, 0] for F, (l, m) in zip(Fs, phases)]
+        res = [t[k] - t[-1] for k in range(K - 1)]
+        res.append(sum(frac[k] * a[k * d:(k + 1) * d] for k in range(K)))
+        return np.concatenate(res)
+
+    a = fsolve(eqs, np.zeros(K * d), xtol=1e-14)
+    assert np.abs(eqs(a)).max() < 1e-12
+    Fs = Fk(a)
+    P = sum(f * hyper.piola(F[None], np.array([l]), np.array([m]))[0] for f, F, (l, m) in zip(frac, Fs, phases))
+    W = sum(f * hyper.energy_density(F[None], np.array([l]), np.array([m]))[0] for f, F, (l, m) in zip(frac, Fs, phases))
+    return P, W

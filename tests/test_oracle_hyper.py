@@ -4,9 +4,9 @@ the exact laminate solution (an independent nonlinear system per layer),
 and frame indifference."""
 import numpy as np
 import pytest
-from scipy.optimize import fsolve
 
 from oracle import fem, hyper
+from closed_forms import laminate_neohooke
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
@@ -112,35 +112,6 @@ def test_small_strain_limit_is_linear_cstar(shape):
     assert err < 50 * eps, err
 
 
-def laminate_exact(phases, frac, Fbar):
-    """Layers normal to x: F_k = F_bar + a_k (x) e_x, sum frac_k a_k = 0 and
-    equal tractions P(F_k) e_x.  Returns (P_mean, energy density)."""
-    d = Fbar.shape[0]
-    K = len(phases)
-
-    def Fk(a):
-        out = []
-        for k in range(K):
-            F = Fbar.copy()
-            F[:, 0] += a[k * d:(k + 1) * d]
-            out.append(F)
-        return out
-
-    def eqs(a):
-        Fs = Fk(a)
-        t = [hyper.piola(F[None], np.array([l]), np.array([m]))[0][:, 0] for F, (l, m) in zip(Fs, phases)]
-        res = [t[k] - t[-1] for k in range(K - 1)]
-        res.append(sum(frac[k] * a[k * d:(k + 1) * d] for k in range(K)))
-        return np.concatenate(res)
-
-    a = fsolve(eqs, np.zeros(K * d), xtol=1e-14)
-    assert np.abs(eqs(a)).max() < 1e-12
-    Fs = Fk(a)
-    P = sum(f * hyper.piola(F[None], np.array([l]), np.array([m]))[0] for f, F, (l, m) in zip(frac, Fs, phases))
-    W = sum(f * hyper.energy_density(F[None], np.array([l]), np.array([m]))[0] for f, F, (l, m) in zip(frac, Fs, phases))
-    return P, W
-
-
 @pytest.mark.parametrize("shape", [(6, 2, 2), (8, 3)])
 def test_laminate_exact_solution(shape):
     d = len(shape)
@@ -159,7 +130,7 @@ def test_laminate_exact_solution(shape):
     Fbar[0, 1] = -0.1
     out = hyper.newton(grid, E, nu, Fbar, tol=1e-14)
     phases = [tuple(float(x) for x in fem.lame(e, v)) for e, v in zip(Eph, nuph)]
-    P, W = laminate_exact(phases, [t / nx for t in thick], Fbar)
+    P, W = laminate_neohooke(phases, [t / nx for t in thick], Fbar)
     assert np.abs(out["P_mean"] - P).max() < 1e-10 * np.abs(P).max()
     assert abs(out["energy"] - W) < 1e-10 * abs(W)
     assert out["iterations"] >= 2
