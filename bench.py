@@ -174,6 +174,127 @@ def bench_uneven(args, B, ms, progress):
     }
 
 
+# Algorithmic floating-point operations of one tangent product K_T(u) p per
+# voxel (3D): the six Kuhn simplices, each evaluated once (the per-simplex
+# count of the design notes: F and grad p 45, inverse and det 42, ln J 1,
+# (F^-1 dG) and (F^-1 dG F^-1) 92, coefficients 3, dP 45, nodal forces 48)
+HYPER_FLOPS_PER_SIMPLEX = 276
+HYPER_FLOPS_PER_VOXEL = 6 * HYPER_FLOPS_PER_SIMPLEX
+# vector FP32 FMA rate without packed FP32: 256 CUs x 64 lanes x 2 flops
+# x 2.4 GHz (the published 157.3 TFLOP/s counts packed FP32 issue)
+ALU_F32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def hyper_loads(d=3, amp=0.05):
+    """Six macroscopic gradients: uniaxial stretches 1 + amp along x, y, z
+    and simple shears amp in the yz, xz and xy planes."""
+    F = np.tile(np.eye(d), (6, 1, 1))
+    for a in range(3):
+        F[a, a, a] += amp
+    for J, (a, b) in enumerate([(1, 2), (0, 2), (0, 1)]):
+        F[3 + J, a, b] = amp
+    return F
+
+
+def cpu_baseline_hyper(E, nu, Fb, sub=16):
+    from oracle import fem, hyper
+    Es = np.ascontiguousarray(E[:sub, :sub, :sub])
+    nus = np.ascontiguousarray(nu[:sub, :sub, :sub])
+    g = fem.Grid((sub, sub, sub))
+    t0 = time.perf_counter()
+    out = hyper.newton(g, Es, nus, Fb, tol=1e-30, maxit=1)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": 3 * g.n * out["iterations"] / dt,
+        "unit": "DOF-Newton-iterations/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"1 Newton iteration (explicit sparse tangent assembly, sparse direct solve, energy line "
+                  f"search; numpy/scipy FP64) for the stretch load on a {sub}^3 periodic sub-block of the "
+                  f"{E.shape[0]}^3 field, {dt:.1f} s",
+    }
+
+
+def bench_hyper(args, B, ms, progress):
+    """Neo-Hookean Newton-PCG: the grf3d geometry (E 1:1000), six 5 %
+    stretch/shear loads batched, mixed precision inner solves (tol 1e-6),
+    Newton tolerance 1e-8 of the load scale."""
+    import torch
+    n1 = args.n
+    n = n1 ** 3
+    E, nu = ms.two_phase_grf(n1, seed=3)
+    Fb = hyper_loads()
+    cell = B.Cell((n1, n1, n1), precision=B.MIXED, tol=1e-6)
+    cell.set_material(torch.from_numpy(E.ravel()).cuda(), torch.from_numpy(nu.ravel()).cuda())
+    sched = cell.schedule
+    if not args.no_tune:
+        sched = cell.autotune()
+        progress(f"autotune: schedule {sched}")
+    for i in range(args.warmup):
+        P, info = cell.solve_hyper(Fb, tol=1e-8)
+        progress(f"warmup {i}: newton {info['newton_iters']} cg {info['cg_iters']} {info['seconds']:.2f} s")
+    cell.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cg_total, newton_total = 0, 0
+    for i in range(args.steps):
+        P, info = cell.solve_hyper(Fb, tol=1e-8)
+        cg_total += sum(info["cg_iters"])
+        newton_total += sum(info["newton_iters"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = cell.profile_read()
+    cell.profile(False)
+    cell.close()
+    progress(f"timed {args.steps} steps in {dt:.3f} s: newton {info['newton_iters']} cg {info['cg_iters']} "
+             f"status {info['status']}")
+    kinds = ["k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv", "residual"]
+    dom = max(kinds, key=lambda k: prof[k][0])
+    ms_k, launches_k = prof["k_apply"]
+    flops = cg_total * n * HYPER_FLOPS_PER_VOXEL
+    achieved = flops / (ms_k * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        progress("cpu oracle baseline ...")
+        cpu = cpu_baseline_hyper(E, nu, Fb[0])
+    return {
+        "metric": "DOF-CG-iterations/sec of the neo-Hookean Newton-PCG at 256^3 (mixed inner solves)",
+        "value": 3 * n * cg_total / dt,
+        "unit": "DOF-CG-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"hyper_grf3d_{n1}: {n1}^3 voxels, the thresholded Gaussian random field of the "
+                        "linear workload (E 1:1000, nu 0.25/0.35), compressible neo-Hookean, six loads "
+                        "(stretches 1.05 along x, y, z; shears 0.05 in yz, xz, xy) in one batched Newton "
+                        "solve, inner PCG mixed precision tol 1e-6, Newton tol 1e-8",
+            "voxels": n,
+            "loads": 6,
+            "newton_iters": info["newton_iters"],
+            "cg_iters": info["cg_iters"],
+            "schedule": list(sched),
+        },
+        "dof_newton_iter_per_s": 3 * n * newton_total / dt,
+        "roofline": {
+            "bound": "alu", "kernel": "k_apply (neo-Hookean tangent)", "achieved": round(achieved, 2),
+            "peak": round(ALU_F32_PEAK_TFLOPS, 1), "unit": "TFLOP/s", "frac": round(achieved / ALU_F32_PEAK_TFLOPS, 4),
+            "traffic": None, "avg_launch_ms": round(ms_k / launches_k, 4), "launches": launches_k,
+            "flops_per_voxel": HYPER_FLOPS_PER_VOXEL, "dominant_kernel": dom,
+        },
+        "kernel_ms": {k: round(v[0], 2) for k, v in prof.items()},
+        "gpu_busy_frac": round(sum(v[0] for v in prof.values()) * 1e-3 / dt, 4),
+        "cpu_baseline": cpu,
+    }
+
+
 def copy_bandwidth(torch, mib=1024, reps=5):
     """Device-to-device copy rate (GB/s of read + write traffic) of a plain
     torch copy of `mib` MiB, best of `reps`: the practically reachable HBM
@@ -203,8 +324,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
     ap.add_argument("--schedule", default=None,
                     help="six comma-separated ints: use this kernel schedule instead of tuning")
-    ap.add_argument("--workload", default="grf3d", choices=["grf3d", "uneven"],
-                    help="grf3d: the 256^3 headline workload; uneven: the batch of sphere cells")
+    ap.add_argument("--workload", default="grf3d", choices=["grf3d", "uneven", "hyper"],
+                    help="grf3d: the 256^3 headline workload; uneven: the batch of sphere cells; "
+                         "hyper: the neo-Hookean Newton-PCG on the grf3d geometry")
     ap.add_argument("--cells", type=int, default=512, help="cells of the uneven batch")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -226,6 +348,9 @@ def main():
 
     if args.workload == "uneven":
         print(json.dumps(bench_uneven(args, B, ms, progress)), flush=True)
+        return
+    if args.workload == "hyper":
+        print(json.dumps(bench_hyper(args, B, ms, progress)), flush=True)
         return
     n1 = args.n
     n = n1 ** 3

@@ -187,6 +187,7 @@ typedef struct {
   int cg_iters[6];       /* PCG iterations summed over the steps */
   double resnorm[6];     /* final ||f|| / max(||f_0||, |Y| max(|lambda| + 2 mu) max(|F_bar|, 1)) */
   double energy[6];      /* Pi / |Y| */
+  int negcurv_steps[6];  /* Newton steps whose inner PCG stopped on p.K_T p <= 0 */
   double seconds;
 } cell_hyper_info;
 
@@ -196,8 +197,11 @@ typedef struct {
  * [nload][d][d] mean first Piola-Kirchhoff stress.  Afterwards
  * cell_get_displacement returns the fluctuation of each load; the linear
  * results (cell_energy_matrix, cell_get_residual, cell_adjoint) are
- * CELL_E_STATE until the next linear solve.  CELL_E_BREAKDOWN if the line
- * search finds no admissible step. */
+ * CELL_E_STATE until the next linear solve.  Where K_T is not positive
+ * definite, the inner PCG stops at the first direction with p.K_T p <= 0
+ * and the step is the iterate reached so far, or the preconditioned
+ * residual if that is the first direction (a descent direction either
+ * way).  CELL_E_BREAKDOWN if the line search finds no admissible step. */
 cell_status cell_solve_hyper(cell_t c, int nload, const double* F_bar, double tol, int max_newton, double* P_out,
                              cell_hyper_info* info);
 

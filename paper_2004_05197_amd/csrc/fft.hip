@@ -683,7 +683,8 @@ __global__ __launch_bounds__(NTF) void k_finalize(RedBuf red, LoadState* st, dou
     case RED_PQ:
       S->pq = s;
       S->iters += 1;
-      if (!(s > 0.0) || !(s < 1e300)) S->state = ST_BREAKDOWN;
+      if (!(s == s) || !(s < 1e300)) S->state = ST_BREAKDOWN;
+      else if (!(s > 0.0)) S->state = S->negok ? ST_NEGCURV : ST_BREAKDOWN;
       else S->alpha = S->rz / s;
       break;
     case RED_RR:

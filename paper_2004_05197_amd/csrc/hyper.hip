@@ -298,6 +298,49 @@ __global__ __launch_bounds__(NT) void k_dot_slots(const double* x, const double*
   if (threadIdx.x == 0) red.slot_parts(RED_RES, l)[blockIdx.x] = s;
 }
 
+// per (slot, component): partial sums of the n nodal values
+__global__ __launch_bounds__(NT) void k_comp_parts(const double* x, long long lstride, long long n, int nb,
+                                                   const int* mask, double* parts) {
+  __shared__ double sh[NT / WAVE];
+  const int c = blockIdx.y, l = blockIdx.z;
+  if (mask && mask[l] == 0) return;
+  const double* v = x + (long long)l * lstride + (long long)c * n;
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)nb * NT) s += v[i];
+  s = block_sum<NT>(s, sh);
+  if (threadIdx.x == 0) parts[((long long)l * 3 + c) * nb + blockIdx.x] = s;
+}
+
+// x -= mean over the nodes, per (slot, component); every block adds the
+// partials in the same order, so all blocks subtract the same mean
+__global__ __launch_bounds__(NT) void k_sub_mean(double* x, long long lstride, long long n, int nb,
+                                                 const int* mask, const double* parts) {
+  __shared__ double sh[NT / WAVE];
+  const int c = blockIdx.y, l = blockIdx.z;
+  if (mask && mask[l] == 0) return;
+  const double* row = parts + ((long long)l * 3 + c) * nb;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) s += row[i];
+  const double mean = block_sum<NT>(s, sh) / (double)n;
+  double* v = x + (long long)l * lstride + (long long)c * n;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) v[i] -= mean;
+}
+
+hipError_t launch_remove_mean(double* x, long long lstride, long long n, int d, int nslot, const int* mask,
+                              double* parts, int maxparts, hipStream_t s) {
+  long long nb = (n + 4LL * NT - 1) / (4LL * NT);
+  if (nb > 1024) nb = 1024;
+  if (nb > maxparts) nb = maxparts;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_comp_parts, dim3((unsigned)nb, d, nslot), dim3(NT), 0, s, (const double*)x, lstride, n, (int)nb,
+                     mask, parts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sub_mean, dim3(256, d, nslot), dim3(NT), 0, s, x, lstride, n, (int)nb, mask,
+                     (const double*)parts);
+  return hipGetLastError();
+}
+
 int hyper_blocks(const Geom& g, int maxblk) {
   const long long nb = (g.n + NT - 1) / NT;
   return (int)(nb < maxblk ? nb : maxblk);
@@ -345,6 +388,11 @@ hipError_t launch_copy_slots(const double* x, double* y, long long len, int nslo
 hipError_t launch_round_slots(const double* x, float* y, long long len, int nslot, hipStream_t s) {
   hipLaunchKernelGGL((k_copy_slots<double, float>), dim3(512, nslot), dim3(256), 0, s, x, y, len,
                      (const int*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen_slots(const float* x, double* y, long long len, int nslot, const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy_slots<float, double>), dim3(512, nslot), dim3(256), 0, s, x, y, len, mask);
   return hipGetLastError();
 }
 

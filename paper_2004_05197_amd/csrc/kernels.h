@@ -173,6 +173,11 @@ hipError_t launch_axpy_slots(const double* x, const double* t, const double* d, 
                              const int* mask, hipStream_t s);
 hipError_t launch_copy_slots(const double* x, double* y, long long len, int nslot, const int* mask, hipStream_t s);
 hipError_t launch_round_slots(const double* x, float* y, long long len, int nslot, hipStream_t s);
+// x[slot][c] -= its mean over the n nodes, per component, for the masked
+// slots; parts: scratch of at least 3 * nslot * maxparts doubles
+hipError_t launch_remove_mean(double* x, long long lstride, long long n, int d, int nslot, const int* mask,
+                              double* parts, int maxparts, hipStream_t s);
+hipError_t launch_widen_slots(const float* x, double* y, long long len, int nslot, const int* mask, hipStream_t s);
 hipError_t launch_zero_slots(double* x, long long len, int nslot, const int* mask, hipStream_t s);
 // per-slot x . y (FP64) into res2 for the masked slots
 hipError_t launch_dot_slots(const double* x, const double* y, long long len, int nslot, const int* mask,

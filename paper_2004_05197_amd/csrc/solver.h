@@ -89,6 +89,7 @@ struct cell_s {
   double* hy_vals = nullptr;    // [nslot][10]
   double* hy_vals_h = nullptr;  // pinned host copy
   bool linear_results = false;  // homog / residual hold the last linear solve
+  std::vector<int> negcurv;     // per slot: iterations at a negative-curvature stop (0: none)
   // last solve
   int nload_solved = 0;
   double eps_v[6][6] = {};

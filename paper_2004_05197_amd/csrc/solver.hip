@@ -499,6 +499,8 @@ cell_status begin_t(SolveRun& R) {
     S.state = ST_IDLE;
     S.maxit = c->max_iter;
     S.first = 1;
+    S.negok = c->op == 1;
+    c->negcurv[l] = 0;
     const int cell = l / c->lpc, j = l % c->lpc;
     if (j >= R.nload) continue;
     R.active[l] = 1;
@@ -577,8 +579,9 @@ cell_status poll_t(SolveRun& R) {
       continue;
     }
     // CONVERGED: the converging iteration has completed (its operator
-    // finalisation, which marks DONE, has not run yet)
-    const bool finished = S.state == ST_DONE || S.state == ST_CONVERGED;
+    // finalisation, which marks DONE, has not run yet); NEGCURV: stopped on
+    // p.Kp <= 0 with the previous iterate
+    const bool finished = S.state == ST_DONE || S.state == ST_CONVERGED || S.state == ST_NEGCURV;
     if (finished || (mixed && S.state == ST_ACTIVE && S.rr < DELTA * DELTA * R.rr_ru[l])) {
       c->mask_h[l] = 1;
       any = true;
@@ -607,6 +610,14 @@ cell_status poll_t(SolveRun& R) {
       if (!c->mask_h[l]) continue;
       LoadState& S = c->st_h[l];
       const bool finished = S.state == ST_DONE || S.state == ST_CONVERGED;
+      if (S.state == ST_NEGCURV) {
+        c->negcurv[l] = S.iters;  // operator applications, the last one with p.Kp <= 0
+        R.fin[l] = 1;
+        S.state = ST_DONE;
+        S.rr = c->res2_h[l];
+        R.rr_ru[l] = S.rr;
+        continue;
+      }
       const double rt = c->res2_h[l];
       R.rr_ru[l] = rt;
       R.nref[l] += 1;
@@ -843,6 +854,7 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
       hipHostMalloc((void**)&c->res2_h, sizeof(double) * ns) != hipSuccess ||
       hipHostMalloc((void**)&c->mask_h, sizeof(int) * ns) != hipSuccess)
     return bail(fail(CELL_E_NOMEM, "pinned host allocation failed"));
+  c->negcurv.assign(ns, 0);
   if (hipMemset(c->cnt, 0, sizeof(unsigned) * RED_NSLOT * ns) != hipSuccess ||
       hipMemset(c->st, 0, sizeof(LoadState) * ns) != hipSuccess ||
       hipMemset(c->mask, 0, sizeof(int) * ns) != hipSuccess)
@@ -1039,7 +1051,7 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
     if (!std::isfinite(E[l])) return fail(CELL_E_ARG, "the macroscopic gradient has det <= 0 in slot " + std::to_string(l));
     ref[l] = std::max(fn[l], scale[l]);
   }
-  std::vector<int> nit(ns, 0), ncg(ns, 0);
+  std::vector<int> nit(ns, 0), ncg(ns, 0), nneg(ns, 0);
   std::vector<double> zeros(36, 0.0);
   std::vector<cell_info> cgi(c->ncell);
   const double* du = c->precision == CELL_MIXED ? c->x64 : c->f64.x;
@@ -1056,6 +1068,15 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
     if (c->precision == CELL_MIXED) HIPCHK(launch_round_slots(c->hy_u, c->hy_u32, len, ns, s));
     STCHK(upload_mask(c, done));
     HIPCHK(launch_zero_slots(c->hy_rhs, len, ns, c->mask, s));
+    // f has zero nodal mean per component exactly; its rounding part lies in
+    // the operator's null space, which the PCG cannot reduce (it would set a
+    // floor ~1e-16 |P| / ||f|| under the relative tolerance near the solution)
+    {
+      std::vector<int> live(ns, 0);
+      for (int l = 0; l < ns; ++l) live[l] = act[l] && !done[l];
+      STCHK(upload_mask(c, live));
+      HIPCHK(launch_remove_mean(c->hy_rhs, len, c->n, d, ns, c->mask, c->hy_vparts, 10 * c->maxblk / 3, s));
+    }
     c->op = 1;
     {
       SolveRun R;
@@ -1072,8 +1093,24 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
       c->op = 0;
       if (st < 0) return st;
     }
-    for (int l = 0; l < ns; ++l)
+    // negative curvature in the first inner iteration leaves du = 0: take
+    // the first direction, the preconditioned residual (a descent direction)
+    std::vector<int> first_dir(ns, 0);
+    bool any_first = false;
+    for (int l = 0; l < ns; ++l) {
       if (act[l] && !done[l]) ncg[l] += cgi[l / lpc].iters[l % lpc];
+      if (act[l] && !done[l] && c->negcurv[l] > 0) {
+        nneg[l] += 1;
+        if (c->negcurv[l] == 1) first_dir[l] = any_first = true;
+      }
+    }
+    if (any_first) {
+      STCHK(upload_mask(c, first_dir));
+      if (c->precision == CELL_MIXED)
+        HIPCHK(launch_widen_slots(reinterpret_cast<const float*>(c->f32.p), c->x64, len, ns, c->mask, s));
+      else
+        HIPCHK(launch_copy_slots(c->f64.p, c->f64.x, len, ns, c->mask, s));
+    }
     // slope f . du, then the line search on the energy
     for (int l = 0; l < ns; ++l) searching[l] = act[l] && !done[l];
     STCHK(upload_mask(c, searching));
@@ -1133,6 +1170,7 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
       I.nload = nload;
       I.newton_iters[j] = nit[l];
       I.cg_iters[j] = ncg[l];
+      I.negcurv_steps[j] = nneg[l];
       I.resnorm[j] = ref[l] > 0 ? fn[l] / ref[l] : 0.0;
       I.energy[j] = E[l] / vol;
     }
@@ -1155,8 +1193,11 @@ cell_status instance_hyper_solve(cell_s* c, int nload, const double* Fbar, doubl
   for (int cell = 0; cell < c->ncell; ++cell)
     if (!c->have_mat[cell]) return fail(CELL_E_STATE, "material not set for cell " + std::to_string(cell));
   if (infos) std::memset(infos, 0, sizeof(cell_hyper_info) * c->ncell);
+  const double t0 = now_s();
   const cell_status st = hyper_run(c, nload, Fbar, tol, max_newton, P_out, infos);
   c->op = 0;
+  if (infos && st >= 0)
+    for (int cell = 0; cell < c->ncell; ++cell) infos[cell].seconds = now_s() - t0;
   return st;
 }
 

@@ -12,7 +12,9 @@ enum : int {
   ST_CONVERGED = 2,  // residual test passed in this iteration; the iteration
                      // still completes (preconditioning + direction update)
   ST_DONE = 3,       // iteration finished after convergence / max_iter
-  ST_BREAKDOWN = -1  // p.Kp <= 0 or r.z <= 0 or non-finite scalar
+  ST_BREAKDOWN = -1,  // p.Kp <= 0 or r.z <= 0 or non-finite scalar
+  ST_NEGCURV = -2     // p.Kp <= 0 in a solve that allows it (Newton steps):
+                      // the iterate of the previous iteration is kept
 };
 
 // Device-resident per-load scalars.  All reductions are FP64.
@@ -28,7 +30,7 @@ struct LoadState {
   int maxit;
   int first;      // 1 until the first preconditioning has set rz
   int maxit_hit;  // 1 if the iteration stopped on max_iter
-  int pad;
+  int negok;      // 1: p.Kp <= 0 ends the iteration (ST_NEGCURV), else breakdown
 };
 
 // Reduction slots (one counter and one partials row per slot and load)

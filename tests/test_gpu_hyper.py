@@ -76,6 +76,30 @@ def test_newton_matches_oracle(lib, shape, prec):
         assert info["resnorm"][J] <= 1e-11
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_indefinite_tangent(lib, prec):
+    """F_bar with det 0.52: K_T(0) has negative eigenvalues (the oracle's
+    assembled tangent, checked here), so the first inner PCG meets
+    p.K_T p <= 0 and stops; Newton still reaches the oracle's minimiser
+    (K_T positive definite there)."""
+    shape = (8, 6)
+    E, nu, Fb = rand_case(shape, 1, amp=0.15)
+    grid = fem.Grid(shape, lengths=[1.0, 1.1])
+    K0 = hyper.assemble_tangent(grid, E, nu, np.zeros((2, grid.n)), Fb[0]).toarray()
+    assert np.linalg.eigvalsh(K0)[0] < -0.1
+    ref = hyper.newton(grid, E, nu, Fb[0], tol=1e-13)
+    Kf = hyper.assemble_tangent(grid, E, nu, ref["u"], Fb[0]).toarray()
+    assert np.linalg.eigvalsh(Kf)[2] > 0.1
+    with lib.Cell(shape, precision=prec, tol=1e-10 if prec == 0 else 1e-6, lengths=grid.L) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        P, info = c.solve_hyper(Fb[:1], tol=1e-11)
+        u = c.displacement(0)
+    assert info["status"] == "CELL_OK"
+    assert info["negcurv_steps"][0] >= 1
+    assert relerr(P[0], ref["P_mean"]) < 1e-9
+    assert relerr(u, ref["u"]) < 1e-7
+
+
 @pytest.mark.parametrize("shape", [(24, 4, 4), (24, 6)])
 def test_laminate_exact(lib, shape):
     d = len(shape)
