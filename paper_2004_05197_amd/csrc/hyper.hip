@@ -241,6 +241,231 @@ __global__ __launch_bounds__(NT) void k_hyper(HyArgs<T> a) {
   }
 }
 
+// =========================================== tiled tangent product (3D)
+// Voxel-centric form of K_T(u) p: every simplex is evaluated once per tile
+// (plus the one-voxel halo on the low x and y sides) instead of once per
+// vertex.  Block: BX x BY node tile marching tz node planes along z; the u
+// and p values of node planes k and k+1 sit in LDS.  Per voxel layer k every
+// thread evaluates voxel (tx-1, ty-1) (whose corner (1,1,*) is its own node)
+// and keeps the (1,1,*) corner forces; the BX+BY+1 halo voxels go to the
+// first threads.  Corner forces (0,0,*), (1,0,*), (0,1,*) are exchanged
+// through LDS; the (.,.,1) corners are carried to the next plane.
+
+// nodal forces of one voxel: f[corner][c] += K_T-product contributions of
+// the six Kuhn simplices (corners as bit masks x | y << 1 | z << 2); u and p
+// of corner (ox, oy, oz) at lds[oz][field * 3 + c][base + oy * PW + ox]
+template <typename T, int PW, int PP>
+__device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int base, const T (&Fb)[3][3], T lam,
+                                             T mu, const T (&ih)[3], T vol, T (&f)[8][3]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) f[q][c] = T(0);
+  auto ld = [&](int q, int fld, int c) -> T {
+    const T* pl = (q & 4) ? pl1 : pl0;
+    return pl[(fld * 3 + c) * PP + base + ((q >> 1) & 1) * PW + (q & 1)];
+  };
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    constexpr int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int path[4];
+    path[0] = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) path[m + 1] = path[m] | (1 << perm[t][m]);
+    T F[3][3], dG[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int ax = perm[t][m];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        F[c][ax] = Fb[c][ax] + (ld(path[m + 1], 0, c) - ld(path[m], 0, c)) * ih[ax];
+        dG[c][ax] = (ld(path[m + 1], 1, c) - ld(path[m], 1, c)) * ih[ax];
+      }
+    }
+    T Fi[3][3];
+    const T J = inv3(F, Fi);
+    const T lnJ = J > T(0) ? log(J) : T(NAN);
+    T M[3][3], tr = T(0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) M[r][c] = Fi[r][0] * dG[0][c] + Fi[r][1] * dG[1][c] + Fi[r][2] * dG[2][c];
+    tr = M[0][0] + M[1][1] + M[2][2];
+    const T cm = mu - lam * lnJ, cl = lam * tr;
+    // Q[c][m] = |s| dP[c][p_m] / h_{p_m}; dP[r][c] = mu dG + cm (M Fi)^T + cl Fi^T
+    T Q[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int ax = perm[t][m];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T N = M[ax][0] * Fi[0][c] + M[ax][1] * Fi[1][c] + M[ax][2] * Fi[2][c];  // (M Fi)[ax][c]
+        Q[c][m] = (mu * dG[c][ax] + cm * N + cl * Fi[ax][c]) * (vol * ih[ax]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      f[path[0]][c] -= Q[c][0];
+      f[path[1]][c] += Q[c][0] - Q[c][1];
+      f[path[2]][c] += Q[c][1] - Q[c][2];
+      f[path[3]][c] += Q[c][2];
+    }
+  }
+}
+
+template <typename T, int BX, int BY>
+__global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt, int nyt, int nzt) {
+  constexpr int NTH = BX * BY;
+  constexpr int PW = BX + 2, PP = PW * (BY + 2);
+  constexpr int VW = BX + 1, VV = VW * (BY + 1);
+  constexpr int NPL = 6 * PP;  // u and p, three components each, per node plane
+  constexpr int PF = (NPL + NTH - 1) / NTH;
+  constexpr int NEXTRA = BX + BY + 1;
+  __shared__ T pl[2 * NPL];
+  __shared__ T cb[18 * VV];
+  __shared__ double sh[NTH / WAVE];
+  const int tid = threadIdx.x;
+  const int tx = tid % BX, ty = tid / BX;
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int n = (int)a.g.n;
+  const int nxy = nx * ny;
+  const int ntiles = nxt * nyt * nzt;
+  const int item = xcd_order(blockIdx.x, ntiles * a.nload);
+  if (item < 0) return;
+  const int l = item % a.nload;
+  const int blk = item / a.nload;
+  if (a.st[l].state != ST_ACTIVE) return;
+  const int bxi = blk % nxt, byi = (blk / nxt) % nyt, bzi = blk / (nxt * nyt);
+  const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * tz;
+  const T ih[3] = {T(1.0 / a.g.h[0]), T(1.0 / a.g.h[1]), T(1.0 / a.g.h[2])};
+  const T vol = T(a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0);
+  T Fb[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Fb[i][j] = (T)a.Fbar[l * 9 + i * 3 + j];
+  const bool has_extra = tid < NEXTRA;
+  const int ex = tid < BY ? BX - 1 : tid - BY - 1;
+  const int ey = tid < BY ? tid - 1 : BY - 1;
+  // per prefetch slot: in-plane offset of this thread's element (field f,
+  // component c, wrapped x and y) and which field it reads, -1 if unused
+  int poff[PF];
+#pragma unroll
+  for (int q = 0; q < PF; ++q) {
+    const int e = tid + q * NTH;
+    poff[q] = -1;
+    if (e < NPL) {
+      const int fc = e / PP, rem = e - fc * PP;
+      const int py = rem / PW, px = rem - py * PW;
+      poff[q] = (fc % 3) * n + hwrap(y0 - 1 + py, ny) * nx + hwrap(x0 - 1 + px, nx);
+    }
+  }
+  const int vown = hwrap(y0 + ty - 1, ny) * nx + hwrap(x0 + tx - 1, nx);
+  const int vext = hwrap(y0 + ey, ny) * nx + hwrap(x0 + ex, nx);
+  const int bown = ty * PW + tx;
+  const int bext = (ey + 1) * PW + (ex + 1);
+  const int cown = ty * VW + tx;
+  const int cext = (ey + 1) * VW + (ex + 1);
+  const T* u = a.u + l * a.lstride;
+  const T* p = a.p + l * a.lstride;
+  T* out = reinterpret_cast<T*>(a.out) + l * a.lstride;
+  const T* matl = a.mat + (long long)(l / a.lpc) * a.mat_stride;
+  T pf[PF];
+  auto fetch_plane = [&](int zp) {
+    const int zoff = hwrap(zp, nz) * nxy;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid + q * NTH;
+      if (poff[q] >= 0) pf[q] = (e < 3 * PP ? u : p)[poff[q] + zoff];
+    }
+  };
+  auto store_plane = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q)
+      if (poff[q] >= 0) pl[slot * NPL + tid + q * NTH] = pf[q];
+  };
+  double acc = 0.0;
+  T carry[3] = {T(0), T(0), T(0)};
+  fetch_plane(z0 - 1);
+  store_plane(0);
+  fetch_plane(z0);
+  store_plane(1);
+  int zm = hwrap(z0 - 1, nz) * nxy;
+  T lam0 = matl[2 * (zm + vown)], mu0 = matl[2 * (zm + vown) + 1];
+  T lame = T(0), mue = T(0);
+  if (has_extra) {
+    lame = matl[2 * (zm + vext)];
+    mue = matl[2 * (zm + vext) + 1];
+  }
+  __syncthreads();
+  for (int L = 0; L <= tz; ++L) {
+    const int k = z0 - 1 + L;
+    const int s0 = L & 1, s1 = (L + 1) & 1;
+    if (L < tz) fetch_plane(k + 2);
+    T lam1 = T(0), mu1 = T(0), lame1 = T(0), mue1 = T(0);
+    if (L < tz) {
+      const int zn = hwrap(k + 1, nz) * nxy;
+      lam1 = matl[2 * (zn + vown)];
+      mu1 = matl[2 * (zn + vown) + 1];
+      if (has_extra) {
+        lame1 = matl[2 * (zn + vext)];
+        mue1 = matl[2 * (zn + vext) + 1];
+      }
+    }
+    T pk[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pk[c] = pl[s0 * NPL + (3 + c) * PP + (ty + 1) * PW + (tx + 1)];
+    T own[2][3];
+#pragma nounroll
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1 && !has_extra) break;
+      T f[8][3];
+      hyper_voxel3<T, PW, PP>(pl + s0 * NPL, pl + s1 * NPL, pass == 0 ? bown : bext, Fb, pass == 0 ? lam0 : lame,
+                              pass == 0 ? mu0 : mue, ih, vol, f);
+      const int ci = pass == 0 ? cown : cext;
+#pragma unroll
+      for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cb[((0 * 2 + oz) * 3 + c) * VV + ci] = f[0 + 4 * oz][c];
+          cb[((1 * 2 + oz) * 3 + c) * VV + ci] = f[1 + 4 * oz][c];
+          cb[((2 * 2 + oz) * 3 + c) * VV + ci] = f[2 + 4 * oz][c];
+          if (pass == 0) own[oz][c] = f[3 + 4 * oz][c];
+        }
+    }
+    __syncthreads();
+    {
+      const int i00 = (ty + 1) * VW + (tx + 1);
+      const int i10 = (ty + 1) * VW + tx;
+      const int i01 = ty * VW + (tx + 1);
+      T val[3], nc[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        val[c] = carry[c] + own[0][c] + cb[(0 * 3 + c) * VV + i00] + cb[(6 + c) * VV + i10] + cb[(12 + c) * VV + i01];
+        nc[c] = own[1][c] + cb[(3 + c) * VV + i00] + cb[(9 + c) * VV + i10] + cb[(15 + c) * VV + i01];
+      }
+      if (L >= 1 && k < nz) {
+        const int node = k * nxy + (y0 + ty) * nx + (x0 + tx);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          out[c * n + node] = val[c];
+          acc += (double)pk[c] * (double)val[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) carry[c] = nc[c];
+    }
+    if (L < tz) store_plane(s0);
+    lam0 = lam1;
+    mu0 = mu1;
+    lame = lame1;
+    mue = mue1;
+    __syncthreads();
+  }
+  const double bs = block_sum<NTH>(acc, sh);
+  if (tid == 0) a.red.slot_parts(RED_PQ, l)[blk] = bs;
+}
+
 // per slot: fixed-order sums of nval partial rows -> vals[slot][nval]
 __global__ __launch_bounds__(NT) void k_sum_vals(const double* parts, int maxblk, int nparts, int nval,
                                                  const int* mask, double* vals) {
@@ -361,9 +586,40 @@ static hipError_t launch_hyper_impl(const HyArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// tile of the voxel-centric tangent kernel: BX x BY nodes
+template <typename T> struct HyTile;
+template <> struct HyTile<float> {
+  static constexpr int BX = 16, BY = 16;
+};
+template <> struct HyTile<double> {
+  static constexpr int BX = 16, BY = 8;
+};
+
+// tiles along z for the voxel-centric kernel: the smallest tz >= 8 whose
+// partial count fits the reduction rows; 0 if the grid does not tile
+template <typename T>
+static int hyper_tile_tz(const Geom& g, int maxblk) {
+  constexpr int BX = HyTile<T>::BX, BY = HyTile<T>::BY;
+  if (g.dim != 3 || g.nx % BX || g.ny % BY || g.nz < 2) return 0;
+  for (int tz = 8; tz <= 256; tz *= 2) {
+    const long long parts = (long long)(g.nx / BX) * (g.ny / BY) * ((g.nz + tz - 1) / tz);
+    if (parts <= maxblk) return tz;
+  }
+  return 0;
+}
+
 template <typename T>
 hipError_t launch_hyper_tangent(const HyArgs<T>& a, hipStream_t s) {
-  return launch_hyper_impl<T, T, 0>(a, s);
+  constexpr int BX = HyTile<T>::BX, BY = HyTile<T>::BY;
+  const int tz = hyper_tile_tz<T>(a.g, a.red.maxblk);
+  if (tz == 0) return launch_hyper_impl<T, T, 0>(a, s);
+  const int nxt = a.g.nx / BX, nyt = a.g.ny / BY, nzt = (a.g.nz + tz - 1) / tz;
+  const int nparts = nxt * nyt * nzt;
+  hipLaunchKernelGGL((k_hyper3t<T, BX, BY>), dim3(xcd_grid(nparts * a.nload)), dim3(BX * BY), 0, s, a, tz, nxt, nyt,
+                     nzt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(a.red, a.st, a.res2, RED_PQ, nparts, a.nload, -1, nullptr, s);
 }
 
 hipError_t launch_hyper_tangent_residual(const HyArgs<double>& a, bool out32, hipStream_t s) {

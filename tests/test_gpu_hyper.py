@@ -32,12 +32,14 @@ def rand_case(shape, seed, amp=0.08):
     return E, nu, np.stack(F)
 
 
-@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 6, 4), (8, 6), (12, 8), (12, 4, 6)])
+@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 6, 4), (8, 6), (12, 8), (12, 4, 6), (32, 16, 12), (16, 32, 24)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_steps_match_oracle(lib, shape, prec):
     """One residual (FP64) and one tangent product (in the handle's
     precision) at a random state against the oracle's f(u), Pi(u), the
-    stress sum and the assembled K_T(u) p."""
+    stress sum and the assembled K_T(u) p.  Grids whose x and y sizes are
+    multiples of 16 run the tiled tangent kernel (several x, y and z tiles,
+    a ragged last z tile), the others the node-centric one."""
     d = len(shape)
     E, nu, Fb = rand_case(shape, 5, amp=0.1)
     grid = fem.Grid(shape, lengths=[1.0 + 0.1 * a for a in range(d)])
