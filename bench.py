@@ -217,13 +217,15 @@ def cpu_baseline_hyper(E, nu, Fb, sub=16):
 
 
 def bench_hyper(args, B, ms, progress):
-    """Neo-Hookean Newton-PCG: the grf3d geometry (E 1:1000), six 5 %
-    stretch/shear loads batched, mixed precision inner solves (tol 1e-6),
-    Newton tolerance 1e-8 of the load scale."""
+    """Neo-Hookean Newton-PCG: the grf3d geometry with phase contrast
+    args.contrast (default 1:10; at 1:1000 the tangent turns indefinite under
+    these loads and the Newton safeguards dominate), six 5 % stretch/shear
+    loads batched, mixed precision inner solves (tol 1e-6), Newton tolerance
+    1e-8 of the load scale."""
     import torch
     n1 = args.n
     n = n1 ** 3
-    E, nu = ms.two_phase_grf(n1, seed=3)
+    E, nu = ms.two_phase_grf(n1, seed=3, E_hard=args.contrast)
     Fb = hyper_loads()
     cell = B.Cell((n1, n1, n1), precision=B.MIXED, tol=1e-6)
     cell.set_material(torch.from_numpy(E.ravel()).cuda(), torch.from_numpy(nu.ravel()).cuda())
@@ -273,12 +275,14 @@ def bench_hyper(args, B, ms, progress):
         "data": "synthetic",
         "config": {
             "workload": f"hyper_grf3d_{n1}: {n1}^3 voxels, the thresholded Gaussian random field of the "
-                        "linear workload (E 1:1000, nu 0.25/0.35), compressible neo-Hookean, six loads "
+                        f"linear workload with E 1:{args.contrast:g} (nu 0.25/0.35), compressible neo-Hookean, six loads "
                         "(stretches 1.05 along x, y, z; shears 0.05 in yz, xz, xy) in one batched Newton "
                         "solve, inner PCG mixed precision tol 1e-6, Newton tol 1e-8",
             "voxels": n,
             "loads": 6,
+            "contrast": args.contrast,
             "newton_iters": info["newton_iters"],
+            "indefinite_steps": info["indefinite_steps"],
             "cg_iters": info["cg_iters"],
             "schedule": list(sched),
         },
@@ -328,6 +332,7 @@ def main():
                     help="grf3d: the 256^3 headline workload; uneven: the batch of sphere cells; "
                          "hyper: the neo-Hookean Newton-PCG on the grf3d geometry")
     ap.add_argument("--cells", type=int, default=512, help="cells of the uneven batch")
+    ap.add_argument("--contrast", type=float, default=10.0, help="phase contrast of the hyper workload")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

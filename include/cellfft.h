@@ -187,7 +187,8 @@ typedef struct {
   int cg_iters[6];       /* PCG iterations summed over the steps */
   double resnorm[6];     /* final ||f|| / max(||f_0||, |Y| max(|lambda| + 2 mu) max(|F_bar|, 1)) */
   double energy[6];      /* Pi / |Y| */
-  int negcurv_steps[6];  /* Newton steps whose inner PCG stopped on p.K_T p <= 0 */
+  int indefinite_steps[6]; /* Newton steps on an indefinite K_T: the inner PCG
+                              met p.K_T p <= 0, or returned no descent direction */
   double seconds;
 } cell_hyper_info;
 
@@ -201,7 +202,9 @@ typedef struct {
  * definite, the inner PCG stops at the first direction with p.K_T p <= 0
  * and the step is the iterate reached so far, or the preconditioned
  * residual if that is the first direction (a descent direction either
- * way).  CELL_E_BREAKDOWN if the line search finds no admissible step. */
+ * way); a converged step that is no descent direction is replaced by one
+ * PCG iteration.  CELL_E_BREAKDOWN if the line search finds no admissible
+ * step. */
 cell_status cell_solve_hyper(cell_t c, int nload, const double* F_bar, double tol, int max_newton, double* P_out,
                              cell_hyper_info* info);
 

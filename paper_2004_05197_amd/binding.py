@@ -61,14 +61,14 @@ class CellInfo(ct.Structure):
 
 class CellHyperInfo(ct.Structure):
     _fields_ = [("nload", ct.c_int), ("newton_iters", ct.c_int * 6), ("cg_iters", ct.c_int * 6),
-                ("resnorm", ct.c_double * 6), ("energy", ct.c_double * 6), ("negcurv_steps", ct.c_int * 6),
+                ("resnorm", ct.c_double * 6), ("energy", ct.c_double * 6), ("indefinite_steps", ct.c_int * 6),
                 ("seconds", ct.c_double)]
 
     def as_dict(self):
         k = self.nload
         return dict(nload=k, newton_iters=list(self.newton_iters[:k]), cg_iters=list(self.cg_iters[:k]),
                     resnorm=list(self.resnorm[:k]), energy=list(self.energy[:k]),
-                    negcurv_steps=list(self.negcurv_steps[:k]), seconds=self.seconds)
+                    indefinite_steps=list(self.indefinite_steps[:k]), seconds=self.seconds)
 
 
 _P = ct.c_void_p

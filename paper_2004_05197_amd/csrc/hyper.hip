@@ -310,6 +310,8 @@ __device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int bas
       f[path[2]][c] += Q[c][1] - Q[c][2];
       f[path[3]][c] += Q[c][2];
     }
+    // keep the next simplex's LDS reads below this point (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -339,27 +341,22 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
   const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * tz;
   const T ih[3] = {T(1.0 / a.g.h[0]), T(1.0 / a.g.h[1]), T(1.0 / a.g.h[2])};
   const T vol = T(a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0);
+  // F_bar in the arithmetic type (uniform loads: scalar registers)
   T Fb[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Fb[i][j] = (T)a.Fbar[l * 9 + i * 3 + j];
+    for (int j = 0; j < 3; ++j) Fb[i][j] = a.FbarT[l * 9 + i * 3 + j];
   const bool has_extra = tid < NEXTRA;
   const int ex = tid < BY ? BX - 1 : tid - BY - 1;
   const int ey = tid < BY ? tid - 1 : BY - 1;
-  // per prefetch slot: in-plane offset of this thread's element (field f,
-  // component c, wrapped x and y) and which field it reads, -1 if unused
-  int poff[PF];
-#pragma unroll
-  for (int q = 0; q < PF; ++q) {
-    const int e = tid + q * NTH;
-    poff[q] = -1;
-    if (e < NPL) {
-      const int fc = e / PP, rem = e - fc * PP;
-      const int py = rem / PW, px = rem - py * PW;
-      poff[q] = (fc % 3) * n + hwrap(y0 - 1 + py, ny) * nx + hwrap(x0 - 1 + px, nx);
-    }
-  }
+  // in-plane offset of prefetch element e (field e / (3 PP), component,
+  // wrapped x and y); recomputed per plane to keep registers free
+  auto poff = [&](int e) {
+    const int fc = e / PP, rem = e - fc * PP;
+    const int py = rem / PW, px = rem - py * PW;
+    return (fc % 3) * n + hwrap(y0 - 1 + py, ny) * nx + hwrap(x0 - 1 + px, nx);
+  };
   const int vown = hwrap(y0 + ty - 1, ny) * nx + hwrap(x0 + tx - 1, nx);
   const int vext = hwrap(y0 + ey, ny) * nx + hwrap(x0 + ex, nx);
   const int bown = ty * PW + tx;
@@ -376,13 +373,13 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int e = tid + q * NTH;
-      if (poff[q] >= 0) pf[q] = (e < 3 * PP ? u : p)[poff[q] + zoff];
+      if (e < NPL) pf[q] = (e < 3 * PP ? u : p)[poff(e) + zoff];
     }
   };
   auto store_plane = [&](int slot) {
 #pragma unroll
     for (int q = 0; q < PF; ++q)
-      if (poff[q] >= 0) pl[slot * NPL + tid + q * NTH] = pf[q];
+      if (tid + q * NTH < NPL) pl[slot * NPL + tid + q * NTH] = pf[q];
   };
   double acc = 0.0;
   T carry[3] = {T(0), T(0), T(0)};
@@ -412,9 +409,8 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
         mue1 = matl[2 * (zn + vext) + 1];
       }
     }
-    T pk[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) pk[c] = pl[s0 * NPL + (3 + c) * PP + (ty + 1) * PW + (tx + 1)];
+    // pass 0: the thread's own voxel, whose (1,1,*) corners stay in
+    // registers; pass 1: the halo voxel (if any); one code body
     T own[2][3];
 #pragma nounroll
     for (int pass = 0; pass < 2; ++pass) {
@@ -434,6 +430,9 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
         }
     }
     __syncthreads();
+    T pk[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pk[c] = pl[s0 * NPL + (3 + c) * PP + (ty + 1) * PW + (tx + 1)];
     {
       const int i00 = (ty + 1) * VW + (tx + 1);
       const int i10 = (ty + 1) * VW + tx;
@@ -563,6 +562,31 @@ hipError_t launch_remove_mean(double* x, long long lstride, long long n, int d, 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sub_mean, dim3(256, d, nslot), dim3(NT), 0, s, x, lstride, n, (int)nb, mask,
                      (const double*)parts);
+  return hipGetLastError();
+}
+
+// per-block maxima of |x[slot]| -> parts[slot][AMAX_BLOCKS]
+__global__ __launch_bounds__(NT) void k_amax_slots(const double* x, long long len, const int* mask, double* parts) {
+  __shared__ double sh[NT];
+  const int l = blockIdx.y;
+  if (mask && mask[l] == 0) return;
+  const long long o = (long long)l * len;
+  double m = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < len; i += (long long)gridDim.x * NT)
+    m = fmax(m, fabs(x[o + i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) parts[(long long)l * gridDim.x + blockIdx.x] = sh[0];
+}
+
+hipError_t launch_amax_slots(const double* x, long long len, int nslot, const int* mask, double* parts, int maxparts,
+                             hipStream_t s) {
+  const int nb = maxparts < AMAX_BLOCKS ? maxparts : AMAX_BLOCKS;
+  hipLaunchKernelGGL(k_amax_slots, dim3(nb, nslot), dim3(NT), 0, s, x, len, mask, parts);
   return hipGetLastError();
 }
 

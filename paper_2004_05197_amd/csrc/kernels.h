@@ -152,6 +152,7 @@ template <typename T> struct HyArgs {
   long long lstride;    // reals per slot
   Geom g;
   const double* Fbar;   // [slot][3][3] macroscopic deformation gradients (row-major)
+  const T* FbarT;       // the same in the arithmetic type
   int nload;            // slots in the launch
   int lpc;              // slots per cell
   LoadState* st;        // mode 0: per-slot state (active slots only)
@@ -177,6 +178,10 @@ hipError_t launch_round_slots(const double* x, float* y, long long len, int nslo
 // slots; parts: scratch of at least 3 * nslot * maxparts doubles
 hipError_t launch_remove_mean(double* x, long long lstride, long long n, int d, int nslot, const int* mask,
                               double* parts, int maxparts, hipStream_t s);
+// max |x[slot]| partials: parts[slot][nb], nb = min(maxparts, AMAX_BLOCKS)
+constexpr int AMAX_BLOCKS = 256;
+hipError_t launch_amax_slots(const double* x, long long len, int nslot, const int* mask, double* parts, int maxparts,
+                             hipStream_t s);
 hipError_t launch_widen_slots(const float* x, double* y, long long len, int nslot, const int* mask, hipStream_t s);
 hipError_t launch_zero_slots(double* x, long long len, int nslot, const int* mask, hipStream_t s);
 // per-slot x . y (FP64) into res2 for the masked slots

@@ -84,6 +84,7 @@ struct cell_s {
   double* hy_ut = nullptr;      // line-search trial state
   double* hy_rhs = nullptr;     // f(u) = -grad Pi [nslot][d n]
   double* hy_F = nullptr;       // [nslot][9] macroscopic deformation gradients
+  float* hy_F32 = nullptr;      // the same rounded to FP32
   double* hy_t = nullptr;       // [nslot] line-search steps
   double* hy_vparts = nullptr;  // [nslot][10][maxblk] energy / stress partials
   double* hy_vals = nullptr;    // [nslot][10]

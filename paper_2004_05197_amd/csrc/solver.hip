@@ -340,6 +340,10 @@ template <typename T> const T* hy_state(cell_s* c);
 template <> const float* hy_state<float>(cell_s* c) { return c->hy_u32; }
 template <> const double* hy_state<double>(cell_s* c) { return c->hy_u; }
 
+template <typename T> const T* fbar_of(cell_s* c);
+template <> const float* fbar_of<float>(cell_s* c) { return c->hy_F32; }
+template <> const double* fbar_of<double>(cell_s* c) { return c->hy_F; }
+
 template <typename T>
 HyArgs<T> hyargs(cell_s* c) {
   HyArgs<T> h{};
@@ -349,6 +353,7 @@ HyArgs<T> hyargs(cell_s* c) {
   h.lstride = c->lstride;
   h.g = c->g;
   h.Fbar = c->hy_F;
+  h.FbarT = fbar_of<T>(c);
   h.nload = c->nslot;
   h.lpc = c->lpc;
   h.st = c->st;
@@ -739,6 +744,7 @@ void instance_destroy(cell_s* c) {
   fr(c->hy_ut);
   fr(c->hy_rhs);
   fr(c->hy_F);
+  fr(c->hy_F32);
   fr(c->hy_t);
   fr(c->hy_vparts);
   fr(c->hy_vals);
@@ -972,7 +978,8 @@ cell_status ensure_hyper(cell_s* c) {
   const size_t fb = sizeof(double) * (size_t)c->lstride * c->nslot;
   auto dm = [&](void** p, size_t b) { return hipMalloc(p, b) == hipSuccess; };
   if (!dm((void**)&c->hy_u, fb) || !dm((void**)&c->hy_ut, fb) || !dm((void**)&c->hy_rhs, fb) ||
-      !dm((void**)&c->hy_F, sizeof(double) * 9 * c->nslot) || !dm((void**)&c->hy_t, sizeof(double) * c->nslot) ||
+      !dm((void**)&c->hy_F, sizeof(double) * 9 * c->nslot) || !dm((void**)&c->hy_F32, sizeof(float) * 9 * c->nslot) ||
+      !dm((void**)&c->hy_t, sizeof(double) * c->nslot) ||
       !dm((void**)&c->hy_vparts, sizeof(double) * 10 * (size_t)c->nslot * c->maxblk) ||
       !dm((void**)&c->hy_vals, sizeof(double) * 10 * c->nslot) ||
       (c->precision == CELL_MIXED && !dm((void**)&c->hy_u32, sizeof(float) * (size_t)c->lstride * c->nslot)))
@@ -1000,6 +1007,27 @@ cell_status hyper_eval(cell_s* c, const double* u, const int* mask) {
   return CELL_OK;
 }
 
+// per-slot macroscopic gradients in FP64 and FP32 (synchronous)
+cell_status upload_fbar(cell_s* c, const std::vector<double>& Fh) {
+  std::vector<float> f32(Fh.begin(), Fh.end());
+  HIPCHK(hipMemcpyAsync(c->hy_F, Fh.data(), sizeof(double) * Fh.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->hy_F32, f32.data(), sizeof(float) * f32.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CELL_OK;
+}
+
+// per-slot max |x| from the partials of launch_amax_slots (synchronous)
+cell_status read_amax(cell_s* c, std::vector<double>& amax) {
+  const int nb = c->maxblk < AMAX_BLOCKS ? c->maxblk : AMAX_BLOCKS;
+  std::vector<double> h((size_t)nb * c->nslot);
+  HIPCHK(hipMemcpyAsync(h.data(), c->hy_vparts, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  amax.assign(c->nslot, 0.0);
+  for (int l = 0; l < c->nslot; ++l)
+    for (int b = 0; b < nb; ++b) amax[l] = std::max(amax[l], h[(size_t)l * nb + b]);
+  return CELL_OK;
+}
+
 // the pinned mask is read by the copy when the stream reaches it: drain the
 // stream before rewriting it (an earlier queued copy would see the new mask)
 cell_status upload_mask(cell_s* c, const std::vector<int>& m) {
@@ -1021,8 +1049,10 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
   c->linear_results = false;
   std::vector<double> Fh(9 * (size_t)ns, 0.0);
   std::vector<int> act(ns, 0), done(ns, 1), searching(ns, 0);
-  std::vector<double> scale(ns, 0.0), E(ns, 0.0), fn(ns, 0.0), slope(ns, 0.0), t(ns, 1.0), dE(ns, 0.0);
+  std::vector<double> scale(ns, 0.0), E(ns, 0.0), fn(ns, 0.0), slope(ns, 0.0), t(ns, 1.0), dE(ns, 0.0),
+      lastE(ns, 0.0);
   const double vol = d == 3 ? c->g.h[0] * c->g.h[1] * c->g.h[2] * c->n : c->g.h[0] * c->g.h[1] * c->n;
+  const double hmin = std::min(c->g.h[0], std::min(c->g.h[1], d == 3 ? c->g.h[2] : c->g.h[1]));
   for (int l = 0; l < ns; ++l) {
     const int j = l % lpc;
     for (int a = 0; a < 3; ++a) Fh[9 * l + 4 * a] = 1.0;
@@ -1039,7 +1069,7 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
     // rounding level of the energy sum (terms of size modulus (|F|^2 + d))
     dE[l] = 1e-13 * vol * c->maxmod[l / lpc] * d * (1.0 + fmax * fmax);
   }
-  HIPCHK(hipMemcpyAsync(c->hy_F, Fh.data(), sizeof(double) * 9 * ns, hipMemcpyHostToDevice, s));
+  STCHK(upload_fbar(c, Fh));
   HIPCHK(launch_zero_slots(c->hy_u, len, ns, nullptr, s));
   STCHK(upload_mask(c, act));
   STCHK(hyper_eval(c, c->hy_u, c->mask));
@@ -1054,7 +1084,7 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
   std::vector<int> nit(ns, 0), ncg(ns, 0), nneg(ns, 0);
   std::vector<double> zeros(36, 0.0);
   std::vector<cell_info> cgi(c->ncell);
-  const double* du = c->precision == CELL_MIXED ? c->x64 : c->f64.x;
+  double* du = c->precision == CELL_MIXED ? c->x64 : c->f64.x;
   for (int it = 0;; ++it) {
     bool all = true;
     for (int l = 0; l < ns; ++l) {
@@ -1077,8 +1107,11 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
       STCHK(upload_mask(c, live));
       HIPCHK(launch_remove_mean(c->hy_rhs, len, c->n, d, ns, c->mask, c->hy_vparts, 10 * c->maxblk / 3, s));
     }
-    c->op = 1;
-    {
+    // inner PCG on K_T du = f (maxit > 0: at most that many iterations)
+    auto inner_solve = [&](int maxit) -> cell_status {
+      const int keep = c->max_iter;
+      if (maxit > 0) c->max_iter = maxit;
+      c->op = 1;
       SolveRun R;
       cell_status st = solve_begin(R, c, nload, zeros.data(), cgi.data());
       while (st >= 0 && !R.done) {
@@ -1091,41 +1124,122 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
       }
       if (st >= 0) st = solve_end(R);
       c->op = 0;
+      c->max_iter = keep;
       if (st < 0) return st;
-    }
-    // negative curvature in the first inner iteration leaves du = 0: take
-    // the first direction, the preconditioned residual (a descent direction)
-    std::vector<int> first_dir(ns, 0);
-    bool any_first = false;
+      // negative curvature in the first iteration leaves du = 0: take the
+      // first direction, the preconditioned residual (a descent direction)
+      std::vector<int> first_dir(ns, 0);
+      bool any_first = false;
+      for (int l = 0; l < ns; ++l)
+        if (act[l] && !done[l] && c->negcurv[l] == 1) first_dir[l] = any_first = true;
+      if (any_first) {
+        STCHK(upload_mask(c, first_dir));
+        if (c->precision == CELL_MIXED)
+          HIPCHK(launch_widen_slots(reinterpret_cast<const float*>(c->f32.p), c->x64, len, ns, c->mask, s));
+        else
+          HIPCHK(launch_copy_slots(c->f64.p, c->f64.x, len, ns, c->mask, s));
+      }
+      return CELL_OK;
+    };
+    auto slopes = [&](const std::vector<int>& m) -> cell_status {
+      STCHK(upload_mask(c, m));
+      HIPCHK(launch_dot_slots(c->hy_rhs, du, len, ns, c->mask, red_of(c), c->st, c->res2, s));
+      HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int l = 0; l < ns; ++l)
+        if (m[l]) slope[l] = c->res2_h[l];
+      return CELL_OK;
+    };
+    STCHK(inner_solve(0));
     for (int l = 0; l < ns; ++l) {
-      if (act[l] && !done[l]) ncg[l] += cgi[l / lpc].iters[l % lpc];
-      if (act[l] && !done[l] && c->negcurv[l] > 0) {
-        nneg[l] += 1;
-        if (c->negcurv[l] == 1) first_dir[l] = any_first = true;
+      searching[l] = act[l] && !done[l];
+      t[l] = 1.0;
+      if (searching[l]) {
+        ncg[l] += cgi[l / lpc].iters[l % lpc];
+        if (c->negcurv[l] > 0) nneg[l] += 1;
       }
     }
-    if (any_first) {
-      STCHK(upload_mask(c, first_dir));
-      if (c->precision == CELL_MIXED)
-        HIPCHK(launch_widen_slots(reinterpret_cast<const float*>(c->f32.p), c->x64, len, ns, c->mask, s));
-      else
-        HIPCHK(launch_copy_slots(c->f64.p, c->f64.x, len, ns, c->mask, s));
+    STCHK(slopes(searching));
+    // one PCG iteration for the masked slots (alpha_0 z_0 with z_0 = M^-1 f,
+    // or z_0 on negative curvature), keeping the du of the other searching
+    // slots; a descent direction by construction
+    auto one_step = [&](const std::vector<int>& m) -> cell_status {
+      std::vector<int> keep_du(ns, 0);
+      for (int l = 0; l < ns; ++l) keep_du[l] = searching[l] && !m[l];
+      STCHK(upload_mask(c, keep_du));
+      HIPCHK(launch_copy_slots(du, c->hy_ut, len, ns, c->mask, s));
+      STCHK(inner_solve(1));
+      STCHK(upload_mask(c, keep_du));
+      HIPCHK(launch_copy_slots(c->hy_ut, du, len, ns, c->mask, s));
+      for (int l = 0; l < ns; ++l)
+        if (m[l]) {
+          ncg[l] += cgi[l / lpc].iters[l % lpc];
+          nneg[l] += 1;
+        }
+      STCHK(slopes(m));
+      for (int l = 0; l < ns; ++l)
+        if (m[l] && !(slope[l] > 0.0))
+          return fail(CELL_E_BREAKDOWN, "no descent direction in slot " + std::to_string(l));
+      return CELL_OK;
+    };
+    // first trial step: t = 1, or the step that moves no node by more than
+    // one voxel edge (guards against the huge steps of a nearly singular K_T)
+    auto first_trial = [&](const std::vector<int>& m) -> cell_status {
+      std::vector<double> amax;
+      STCHK(upload_mask(c, m));
+      HIPCHK(launch_amax_slots(du, len, ns, c->mask, c->hy_vparts, c->maxblk, s));
+      STCHK(read_amax(c, amax));
+      for (int l = 0; l < ns; ++l)
+        if (m[l]) t[l] = amax[l] * 1.0 > hmin ? hmin / amax[l] : 1.0;
+      return CELL_OK;
+    };
+    // an indefinite K_T can also give a converged du that is no descent
+    // direction (f.du <= 0, negative curvature never met): those slots take
+    // one PCG iteration instead
+    {
+      std::vector<int> redo(ns, 0);
+      bool any_redo = false;
+      for (int l = 0; l < ns; ++l) {
+        redo[l] = searching[l] && !(slope[l] > 0.0);
+        any_redo = any_redo || redo[l];
+      }
+      if (any_redo) STCHK(one_step(redo));
     }
-    // slope f . du, then the line search on the energy
-    for (int l = 0; l < ns; ++l) searching[l] = act[l] && !done[l];
-    STCHK(upload_mask(c, searching));
-    HIPCHK(launch_dot_slots(c->hy_rhs, du, len, ns, c->mask, red_of(c), c->st, c->res2, s));
-    HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int l = 0; l < ns; ++l) {
-      slope[l] = c->res2_h[l];
-      t[l] = 1.0;
-    }
+    STCHK(first_trial(searching));
+    // backtracking line search on the energy; a slot whose search fails
+    // retries once from the one-iteration step
+    std::vector<int> retried(ns, 0);
     for (int ls = 0;; ++ls) {
       bool any = false;
       for (int l = 0; l < ns; ++l) any = any || searching[l];
       if (!any) break;
-      if (ls == 40) return fail(CELL_E_BREAKDOWN, "Newton line search found no admissible step");
+      if (ls >= 40) {
+        std::vector<int> fail_m(ns, 0);
+        bool again = true;
+        int lf = -1;
+        for (int l = 0; l < ns; ++l)
+          if (searching[l]) {
+            fail_m[l] = 1;
+            if (retried[l]) again = false, lf = l;
+          }
+        if (!again) {
+          char msg[256];
+          std::snprintf(msg, sizeof msg,
+                        "Newton line search found no admissible step (slot %d, Newton step %d: f.du %.3e, "
+                        "||f|| %.3e, energy %.9e, last trial energy %.9e)",
+                        lf, it, slope[lf], fn[lf], E[lf], lastE[lf]);
+          return fail(CELL_E_BREAKDOWN, msg);
+        }
+        // f(u) again for these slots (the trials overwrote it), zero mean
+        STCHK(upload_mask(c, fail_m));
+        STCHK(hyper_eval(c, c->hy_u, c->mask));
+        HIPCHK(launch_remove_mean(c->hy_rhs, len, c->n, d, ns, c->mask, c->hy_vparts, 10 * c->maxblk / 3, s));
+        STCHK(one_step(fail_m));
+        STCHK(first_trial(fail_m));
+        for (int l = 0; l < ns; ++l)
+          if (fail_m[l]) retried[l] = 1;
+        ls = 0;
+      }
       STCHK(upload_mask(c, searching));
       HIPCHK(hipMemcpyAsync(c->hy_t, t.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
       HIPCHK(launch_axpy_slots(c->hy_u, c->hy_t, du, c->hy_ut, len, ns, c->mask, s));
@@ -1134,6 +1248,7 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
       for (int l = 0; l < ns; ++l) {
         if (!searching[l]) continue;
         const double Et = c->hy_vals_h[10 * l], fnt = std::sqrt(c->res2_h[l]);
+        lastE[l] = Et;
         // Armijo on the energy; where the change is below the energy's
         // rounding level, a decrease of the residual norm instead
         const bool armijo = Et <= E[l] - 1e-4 * t[l] * slope[l];
@@ -1170,7 +1285,7 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
       I.nload = nload;
       I.newton_iters[j] = nit[l];
       I.cg_iters[j] = ncg[l];
-      I.negcurv_steps[j] = nneg[l];
+      I.indefinite_steps[j] = nneg[l];
       I.resnorm[j] = ref[l] > 0 ? fn[l] / ref[l] : 0.0;
       I.energy[j] = E[l] / vol;
     }
@@ -1280,7 +1395,7 @@ cell_status hyper_step_t(cell_s* c, const double* Fbar, const double* u, const d
     for (int a = 0; a < 3; ++a) Fh[9 * l + 4 * a] = 1.0;
   for (int a = 0; a < c->d; ++a)
     for (int b = 0; b < c->d; ++b) Fh[3 * a + b] = Fbar[a * c->d + b];
-  HIPCHK(hipMemcpyAsync(c->hy_F, Fh.data(), sizeof(double) * 9 * c->nslot, hipMemcpyHostToDevice, c->stream));
+  STCHK(upload_fbar(c, Fh));
   HIPCHK(hipMemcpyAsync(c->hy_u, u, sizeof(double) * c->lstride, hipMemcpyHostToDevice, c->stream));
   if (c->hy_u32) HIPCHK(launch_round_slots(c->hy_u, c->hy_u32, c->lstride, 1, c->stream));
   diag_state(c);
