@@ -56,6 +56,33 @@ __device__ __forceinline__ T inv3(const T (&F)[3][3], T (&Fi)[3][3]) {
   return det;
 }
 
+// FP32 tangent arithmetic uses the hardware reciprocal and logarithm (about
+// 1 ulp); FP64 keeps the correctly rounded division and log
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+__device__ __forceinline__ float log_t(float x) { return __logf(x); }
+__device__ __forceinline__ double log_t(double x) { return log(x); }
+
+// inverse via cofactors and rcp_t(det); returns det
+template <typename T>
+__device__ __forceinline__ T inv3r(const T (&F)[3][3], T (&Fi)[3][3]) {
+  const T c00 = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  const T c01 = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  const T c02 = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  const T det = F[0][0] * c00 + F[0][1] * c01 + F[0][2] * c02;
+  const T id = rcp_t(det);
+  Fi[0][0] = c00 * id;
+  Fi[1][0] = c01 * id;
+  Fi[2][0] = c02 * id;
+  Fi[0][1] = (F[0][2] * F[2][1] - F[0][1] * F[2][2]) * id;
+  Fi[1][1] = (F[0][0] * F[2][2] - F[0][2] * F[2][0]) * id;
+  Fi[2][1] = (F[0][1] * F[2][0] - F[0][0] * F[2][1]) * id;
+  Fi[0][2] = (F[0][1] * F[1][2] - F[0][2] * F[1][1]) * id;
+  Fi[1][2] = (F[0][2] * F[1][0] - F[0][0] * F[1][2]) * id;
+  Fi[2][2] = (F[0][0] * F[1][1] - F[0][1] * F[1][0]) * id;
+  return det;
+}
+
 template <typename T>
 __device__ __forceinline__ T inv2(const T (&F)[2][2], T (&Fi)[2][2]) {
   const T det = F[0][0] * F[1][1] - F[0][1] * F[1][0];
@@ -253,10 +280,12 @@ __global__ __launch_bounds__(NT) void k_hyper(HyArgs<T> a) {
 
 // nodal forces of one voxel: f[corner][c] += K_T-product contributions of
 // the six Kuhn simplices (corners as bit masks x | y << 1 | z << 2); u and p
-// of corner (ox, oy, oz) at lds[oz][field * 3 + c][base + oy * PW + ox]
-template <typename T, int PW, int PP>
-__device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int base, const T (&Fb)[3][3], T lam,
-                                             T mu, const T (&ih)[3], T vol, T (&f)[8][3]) {
+// of corner (ox, oy, oz) at lds[oz][field * 3 + c][base + oy * PW + ox].
+// lam, mu arrive multiplied by w: |s| h^-2 on uniform grids (UNI: all
+// 1/h factors of grad p, dP and the nodal gradient folded into w), |s| else.
+template <typename T, int PW, int PP, bool UNI>
+__device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int base, const T (&Fb)[3][3], T lamw,
+                                             T muw, const T (&ih)[3], T (&f)[8][3]) {
 #pragma unroll
   for (int q = 0; q < 8; ++q)
 #pragma unroll
@@ -272,6 +301,7 @@ __device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int bas
     path[0] = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) path[m + 1] = path[m] | (1 << perm[t][m]);
+    // F = F_bar + grad u; dG = grad p (UNI: h dG, the edge differences)
     T F[3][3], dG[3][3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -279,19 +309,20 @@ __device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int bas
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         F[c][ax] = Fb[c][ax] + (ld(path[m + 1], 0, c) - ld(path[m], 0, c)) * ih[ax];
-        dG[c][ax] = (ld(path[m + 1], 1, c) - ld(path[m], 1, c)) * ih[ax];
+        const T dp = ld(path[m + 1], 1, c) - ld(path[m], 1, c);
+        dG[c][ax] = UNI ? dp : dp * ih[ax];
       }
     }
     T Fi[3][3];
-    const T J = inv3(F, Fi);
-    const T lnJ = J > T(0) ? log(J) : T(NAN);
+    const T J = inv3r(F, Fi);
+    const T lnJ = J > T(0) ? log_t(J) : T(NAN);
     T M[3][3], tr = T(0);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) M[r][c] = Fi[r][0] * dG[0][c] + Fi[r][1] * dG[1][c] + Fi[r][2] * dG[2][c];
     tr = M[0][0] + M[1][1] + M[2][2];
-    const T cm = mu - lam * lnJ, cl = lam * tr;
+    const T cm = muw - lamw * lnJ, cl = lamw * tr;
     // Q[c][m] = |s| dP[c][p_m] / h_{p_m}; dP[r][c] = mu dG + cm (M Fi)^T + cl Fi^T
     T Q[3][3];
 #pragma unroll
@@ -300,7 +331,8 @@ __device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int bas
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T N = M[ax][0] * Fi[0][c] + M[ax][1] * Fi[1][c] + M[ax][2] * Fi[2][c];  // (M Fi)[ax][c]
-        Q[c][m] = (mu * dG[c][ax] + cm * N + cl * Fi[ax][c]) * (vol * ih[ax]);
+        const T v = muw * dG[c][ax] + cm * N + cl * Fi[ax][c];
+        Q[c][m] = UNI ? v : v * ih[ax];
       }
     }
 #pragma unroll
@@ -315,12 +347,82 @@ __device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int bas
   }
 }
 
-template <typename T, int BX, int BY>
+// nodal forces of one voxel in residual form, f[corner][c] += |s| P(F) g,
+// F = F_bar + grad u (u of corner (ox, oy, oz) at lds[oz][c][base + oy PW +
+// ox]); with count, the voxel's sums of |s| W and |s| P go to own10
+template <typename T, int PW, int PP>
+__device__ __forceinline__ void hyper_voxel3_res(const T* pl0, const T* pl1, int base, const T (&Fb)[3][3], T lam,
+                                                 T mu, const T (&ih)[3], T vol, T (&f)[8][3], bool count,
+                                                 double (&own10)[10]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) f[q][c] = T(0);
+  auto ld = [&](int q, int c) -> T {
+    const T* pl = (q & 4) ? pl1 : pl0;
+    return pl[c * PP + base + ((q >> 1) & 1) * PW + (q & 1)];
+  };
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    constexpr int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int path[4];
+    path[0] = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) path[m + 1] = path[m] | (1 << perm[t][m]);
+    T F[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int ax = perm[t][m];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c][ax] = Fb[c][ax] + (ld(path[m + 1], c) - ld(path[m], c)) * ih[ax];
+    }
+    T Fi[3][3];
+    const T J = inv3(F, Fi);
+    const T lnJ = J > T(0) ? log(J) : T(NAN);
+    T P[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) P[r][c] = mu * (F[r][c] - Fi[c][r]) + lam * lnJ * Fi[c][r];
+    if (count) {
+      T ff = T(0);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          ff += F[r][c] * F[r][c];
+          own10[1 + 3 * r + c] += (double)(vol * P[r][c]);
+        }
+      own10[0] += (double)(vol * (T(0.5) * lam * lnJ * lnJ - mu * lnJ + T(0.5) * mu * (ff - T(3))));
+    }
+    T Q[3][3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int ax = perm[t][m];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Q[c][m] = P[c][ax] * (vol * ih[ax]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      f[path[0]][c] -= Q[c][0];
+      f[path[1]][c] += Q[c][0] - Q[c][1];
+      f[path[2]][c] += Q[c][1] - Q[c][2];
+      f[path[3]][c] += Q[c][2];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// MODE 0: q = K_T(u) p (T), p.q partials.  MODE 1: r = rhs - K_T(u) du
+// (FP64 arithmetic, written as TO; du == nullptr: zero), ||r||^2.  MODE 2:
+// f = -sum |s| B^T P(F) (FP64), ||f||^2 and the |s| W, |s| P sums of the
+// voxels owned by the tile (voxel below-left-behind each of its nodes).
+template <typename T, typename TO, int MODE, bool UNI, int BX, int BY>
 __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt, int nyt, int nzt) {
   constexpr int NTH = BX * BY;
   constexpr int PW = BX + 2, PP = PW * (BY + 2);
   constexpr int VW = BX + 1, VV = VW * (BY + 1);
-  constexpr int NPL = 6 * PP;  // u and p, three components each, per node plane
+  constexpr int NPL = (MODE == 2 ? 3 : 6) * PP;  // u (and p), three components each, per node plane
   constexpr int PF = (NPL + NTH - 1) / NTH;
   constexpr int NEXTRA = BX + BY + 1;
   __shared__ T pl[2 * NPL];
@@ -336,11 +438,13 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
   if (item < 0) return;
   const int l = item % a.nload;
   const int blk = item / a.nload;
-  if (a.st[l].state != ST_ACTIVE) return;
+  if (MODE == 0 ? a.st[l].state != ST_ACTIVE : (a.mask && a.mask[l] == 0)) return;
   const int bxi = blk % nxt, byi = (blk / nxt) % nyt, bzi = blk / (nxt * nyt);
   const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * tz;
   const T ih[3] = {T(1.0 / a.g.h[0]), T(1.0 / a.g.h[1]), T(1.0 / a.g.h[2])};
   const T vol = T(a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0);
+  // material weight of the tangent: |s| (UNI: |s| / h^2)
+  const T wt = UNI ? T(a.g.h[0] * a.g.h[1] * a.g.h[2] / (6.0 * a.g.h[0] * a.g.h[0])) : vol;
   // F_bar in the arithmetic type (uniform loads: scalar registers)
   T Fb[3][3];
 #pragma unroll
@@ -364,8 +468,9 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
   const int cown = ty * VW + tx;
   const int cext = (ey + 1) * VW + (ex + 1);
   const T* u = a.u + l * a.lstride;
-  const T* p = a.p + l * a.lstride;
-  T* out = reinterpret_cast<T*>(a.out) + l * a.lstride;
+  const T* p = (MODE != 2 && a.p) ? a.p + l * a.lstride : nullptr;
+  TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
+  const double* rhs = MODE == 1 ? a.rhs + l * a.lstride : nullptr;
   const T* matl = a.mat + (long long)(l / a.lpc) * a.mat_stride;
   T pf[PF];
   auto fetch_plane = [&](int zp) {
@@ -373,7 +478,7 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int e = tid + q * NTH;
-      if (e < NPL) pf[q] = (e < 3 * PP ? u : p)[poff(e) + zoff];
+      if (e < NPL) pf[q] = e < 3 * PP ? u[poff(e) + zoff] : (p ? p[poff(e) + zoff] : T(0));
     }
   };
   auto store_plane = [&](int slot) {
@@ -382,6 +487,7 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
       if (tid + q * NTH < NPL) pl[slot * NPL + tid + q * NTH] = pf[q];
   };
   double acc = 0.0;
+  double own10[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   T carry[3] = {T(0), T(0), T(0)};
   fetch_plane(z0 - 1);
   store_plane(0);
@@ -416,8 +522,15 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1 && !has_extra) break;
       T f[8][3];
-      hyper_voxel3<T, PW, PP>(pl + s0 * NPL, pl + s1 * NPL, pass == 0 ? bown : bext, Fb, pass == 0 ? lam0 : lame,
-                              pass == 0 ? mu0 : mue, ih, vol, f);
+      if constexpr (MODE == 2) {
+        // the voxel of layer k belongs to the node above it (plane k + 1)
+        const bool count = pass == 0 && L < tz && z0 + L < nz;
+        hyper_voxel3_res<T, PW, PP>(pl + s0 * NPL, pl + s1 * NPL, pass == 0 ? bown : bext, Fb,
+                                    pass == 0 ? lam0 : lame, pass == 0 ? mu0 : mue, ih, vol, f, count, own10);
+      } else {
+        hyper_voxel3<T, PW, PP, UNI>(pl + s0 * NPL, pl + s1 * NPL, pass == 0 ? bown : bext, Fb,
+                                     (pass == 0 ? lam0 : lame) * wt, (pass == 0 ? mu0 : mue) * wt, ih, f);
+      }
       const int ci = pass == 0 ? cown : cext;
 #pragma unroll
       for (int oz = 0; oz < 2; ++oz)
@@ -430,9 +543,11 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
         }
     }
     __syncthreads();
-    T pk[3];
+    T pk[3] = {T(0), T(0), T(0)};
+    if constexpr (MODE == 0) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) pk[c] = pl[s0 * NPL + (3 + c) * PP + (ty + 1) * PW + (tx + 1)];
+      for (int c = 0; c < 3; ++c) pk[c] = pl[s0 * NPL + (3 + c) * PP + (ty + 1) * PW + (tx + 1)];
+    }
     {
       const int i00 = (ty + 1) * VW + (tx + 1);
       const int i10 = (ty + 1) * VW + tx;
@@ -447,8 +562,18 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
         const int node = k * nxy + (y0 + ty) * nx + (x0 + tx);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          out[c * n + node] = val[c];
-          acc += (double)pk[c] * (double)val[c];
+          if constexpr (MODE == 0) {
+            out[c * n + node] = (TO)val[c];
+            acc += (double)pk[c] * (double)val[c];
+          } else if constexpr (MODE == 1) {
+            const double r = rhs[c * n + node] - (double)val[c];
+            out[c * n + node] = (TO)r;
+            acc += r * r;
+          } else {
+            const double fv = -(double)val[c];
+            out[c * n + node] = (TO)fv;
+            acc += fv * fv;
+          }
         }
       }
 #pragma unroll
@@ -462,7 +587,13 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
     __syncthreads();
   }
   const double bs = block_sum<NTH>(acc, sh);
-  if (tid == 0) a.red.slot_parts(RED_PQ, l)[blk] = bs;
+  if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
+  if constexpr (MODE == 2) {
+    for (int v = 0; v < 10; ++v) {
+      const double sv = block_sum<NTH>(own10[v], sh);
+      if (tid == 0) a.vparts[((long long)l * 10 + v) * a.red.maxblk + blk] = sv;
+    }
+  }
 }
 
 // per slot: fixed-order sums of nval partial rows -> vals[slot][nval]
@@ -565,6 +696,38 @@ hipError_t launch_remove_mean(double* x, long long lstride, long long n, int d, 
   return hipGetLastError();
 }
 
+// r = rhs (the residual at du = 0) as TO for the masked slots, ||r||^2 partials
+template <typename TO>
+__global__ __launch_bounds__(NT) void k_rhs_residual(const double* rhs, TO* r, long long lstride, long long m,
+                                                     const int* mask, RedBuf red) {
+  __shared__ double sh[NT / WAVE];
+  const int l = blockIdx.y;
+  if (mask && mask[l] == 0) return;
+  const long long o = (long long)l * lstride;
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < m; i += (long long)gridDim.x * NT) {
+    const double v = rhs[o + i];
+    r[o + i] = (TO)v;
+    s += v * v;
+  }
+  s = block_sum<NT>(s, sh);
+  if (threadIdx.x == 0) red.slot_parts(RED_RES, l)[blockIdx.x] = s;
+}
+
+hipError_t launch_rhs_residual(const double* rhs, void* r, bool out32, long long lstride, long long m, int nslot,
+                               const int* mask, const RedBuf& red, LoadState* st, double* res2, hipStream_t s) {
+  const int nb = red.maxblk < 1024 ? red.maxblk : 1024;
+  if (out32)
+    hipLaunchKernelGGL(k_rhs_residual<float>, dim3(nb, nslot), dim3(NT), 0, s, rhs, static_cast<float*>(r), lstride, m,
+                       mask, red);
+  else
+    hipLaunchKernelGGL(k_rhs_residual<double>, dim3(nb, nslot), dim3(NT), 0, s, rhs, static_cast<double*>(r), lstride,
+                       m, mask, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(red, st, res2, RED_RES, nb, nslot, -1, mask, s);
+}
+
 // per-block maxima of |x[slot]| -> parts[slot][AMAX_BLOCKS]
 __global__ __launch_bounds__(NT) void k_amax_slots(const double* x, long long len, const int* mask, double* parts) {
   __shared__ double sh[NT];
@@ -632,26 +795,42 @@ static int hyper_tile_tz(const Geom& g, int maxblk) {
   return 0;
 }
 
-template <typename T>
-hipError_t launch_hyper_tangent(const HyArgs<T>& a, hipStream_t s) {
+// tiled kernel where the grid tiles (3D), else the node-centric one
+template <typename T, typename TO, int MODE>
+static hipError_t launch_hyper_any(const HyArgs<T>& a, hipStream_t s) {
   constexpr int BX = HyTile<T>::BX, BY = HyTile<T>::BY;
   const int tz = hyper_tile_tz<T>(a.g, a.red.maxblk);
-  if (tz == 0) return launch_hyper_impl<T, T, 0>(a, s);
+  if (tz == 0) return launch_hyper_impl<T, TO, MODE>(a, s);
   const int nxt = a.g.nx / BX, nyt = a.g.ny / BY, nzt = (a.g.nz + tz - 1) / tz;
   const int nparts = nxt * nyt * nzt;
-  hipLaunchKernelGGL((k_hyper3t<T, BX, BY>), dim3(xcd_grid(nparts * a.nload)), dim3(BX * BY), 0, s, a, tz, nxt, nyt,
-                     nzt);
+  const bool uni = a.g.h[0] == a.g.h[1] && a.g.h[1] == a.g.h[2];
+  if (uni)
+    hipLaunchKernelGGL((k_hyper3t<T, TO, MODE, true, BX, BY>), dim3(xcd_grid(nparts * a.nload)), dim3(BX * BY), 0, s,
+                       a, tz, nxt, nyt, nzt);
+  else
+    hipLaunchKernelGGL((k_hyper3t<T, TO, MODE, false, BX, BY>), dim3(xcd_grid(nparts * a.nload)), dim3(BX * BY), 0, s,
+                       a, tz, nxt, nyt, nzt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_finalize(a.red, a.st, a.res2, RED_PQ, nparts, a.nload, -1, nullptr, s);
+  e = launch_finalize(a.red, a.st, a.res2, MODE == 0 ? RED_PQ : RED_RES, nparts, a.nload, -1,
+                      MODE == 0 ? nullptr : a.mask, s);
+  if (e != hipSuccess || MODE != 2) return e;
+  hipLaunchKernelGGL(k_sum_vals, dim3(10, a.nload), dim3(NT), 0, s, (const double*)a.vparts, a.red.maxblk, nparts, 10,
+                     a.mask, a.vals);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hyper_tangent(const HyArgs<T>& a, hipStream_t s) {
+  return launch_hyper_any<T, T, 0>(a, s);
 }
 
 hipError_t launch_hyper_tangent_residual(const HyArgs<double>& a, bool out32, hipStream_t s) {
-  return out32 ? launch_hyper_impl<double, float, 1>(a, s) : launch_hyper_impl<double, double, 1>(a, s);
+  return out32 ? launch_hyper_any<double, float, 1>(a, s) : launch_hyper_any<double, double, 1>(a, s);
 }
 
 hipError_t launch_hyper_residual(const HyArgs<double>& a, hipStream_t s) {
-  return launch_hyper_impl<double, double, 2>(a, s);
+  return launch_hyper_any<double, double, 2>(a, s);
 }
 
 hipError_t launch_axpy_slots(const double* x, const double* t, const double* d, double* y, long long len, int nslot,

@@ -178,6 +178,10 @@ hipError_t launch_round_slots(const double* x, float* y, long long len, int nslo
 // slots; parts: scratch of at least 3 * nslot * maxparts doubles
 hipError_t launch_remove_mean(double* x, long long lstride, long long n, int d, int nslot, const int* mask,
                               double* parts, int maxparts, hipStream_t s);
+// r = rhs over the first m reals of every masked slot (float if out32),
+// ||r||^2 -> res2 (the Newton residual at du = 0)
+hipError_t launch_rhs_residual(const double* rhs, void* r, bool out32, long long lstride, long long m, int nslot,
+                               const int* mask, const RedBuf& red, LoadState* st, double* res2, hipStream_t s);
 // max |x[slot]| partials: parts[slot][nb], nb = min(maxparts, AMAX_BLOCKS)
 constexpr int AMAX_BLOCKS = 256;
 hipError_t launch_amax_slots(const double* x, long long len, int nslot, const int* mask, double* parts, int maxparts,

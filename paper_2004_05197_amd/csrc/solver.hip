@@ -449,7 +449,11 @@ cell_status residual(cell_s* c, const double* u, const int* mask) {
     ha.mask = mask;
     {
       ProfScope ps(c, CELL_K_RESIDUAL);
-      HIPCHK(launch_hyper_tangent_residual(ha, sizeof(T) == 4, c->stream));
+      if (u)
+        HIPCHK(launch_hyper_tangent_residual(ha, sizeof(T) == 4, c->stream));
+      else  // du = 0: r = f
+        HIPCHK(launch_rhs_residual(c->hy_rhs, F.r, sizeof(T) == 4, c->lstride, (long long)c->d * c->n, c->nslot, mask,
+                                   red_of(c), c->st, c->res2, c->stream));
     }
     HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * c->nslot, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
