@@ -56,21 +56,36 @@ __device__ __forceinline__ T inv3(const T (&F)[3][3], T (&Fi)[3][3]) {
   return det;
 }
 
-// FP32 tangent arithmetic uses the hardware reciprocal and logarithm (about
-// 1 ulp); FP64 keeps the correctly rounded division and log
-__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
-__device__ __forceinline__ float log_t(float x) { return __logf(x); }
-__device__ __forceinline__ double log_t(double x) { return log(x); }
+// Tangent arithmetic.  FP32: the hardware reciprocal and logarithm (about
+// 1 ulp).  FP64 with FASTLN (the FP64 residual refreshes of mixed-precision
+// solves, whose iterated operator is the FP32 tangent anyway): a reciprocal
+// refined by one Newton step (FP64-accurate) and ln J to FP32 accuracy, which
+// only perturbs the coefficient mu - lambda ln J, by ~1e-7 relative, the
+// size of the FP32 tangent's own rounding.  FP64 otherwise: the correctly
+// rounded division and log (the FP64 solve iterates this same operator).
+template <bool FASTLN> __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+template <bool FASTLN> __device__ __forceinline__ double rcp_t(double x) {
+  if constexpr (FASTLN) {
+    const double r = (double)__builtin_amdgcn_rcpf((float)x);
+    return r * (2.0 - x * r);
+  } else {
+    return 1.0 / x;
+  }
+}
+template <bool FASTLN> __device__ __forceinline__ float log_t(float x) { return __logf(x); }
+template <bool FASTLN> __device__ __forceinline__ double log_t(double x) {
+  if constexpr (FASTLN) return (double)__logf((float)x);
+  else return log(x);
+}
 
 // inverse via cofactors and rcp_t(det); returns det
-template <typename T>
+template <bool FASTLN, typename T>
 __device__ __forceinline__ T inv3r(const T (&F)[3][3], T (&Fi)[3][3]) {
   const T c00 = F[1][1] * F[2][2] - F[1][2] * F[2][1];
   const T c01 = F[1][2] * F[2][0] - F[1][0] * F[2][2];
   const T c02 = F[1][0] * F[2][1] - F[1][1] * F[2][0];
   const T det = F[0][0] * c00 + F[0][1] * c01 + F[0][2] * c02;
-  const T id = rcp_t(det);
+  const T id = rcp_t<FASTLN>(det);
   Fi[0][0] = c00 * id;
   Fi[1][0] = c01 * id;
   Fi[2][0] = c02 * id;
@@ -283,7 +298,7 @@ __global__ __launch_bounds__(NT) void k_hyper(HyArgs<T> a) {
 // of corner (ox, oy, oz) at lds[oz][field * 3 + c][base + oy * PW + ox].
 // lam, mu arrive multiplied by w: |s| h^-2 on uniform grids (UNI: all
 // 1/h factors of grad p, dP and the nodal gradient folded into w), |s| else.
-template <typename T, int PW, int PP, bool UNI>
+template <typename T, int PW, int PP, bool UNI, bool FASTLN>
 __device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int base, const T (&Fb)[3][3], T lamw,
                                              T muw, const T (&ih)[3], T (&f)[8][3]) {
 #pragma unroll
@@ -314,8 +329,8 @@ __device__ __forceinline__ void hyper_voxel3(const T* pl0, const T* pl1, int bas
       }
     }
     T Fi[3][3];
-    const T J = inv3r(F, Fi);
-    const T lnJ = J > T(0) ? log_t(J) : T(NAN);
+    const T J = inv3r<FASTLN>(F, Fi);
+    const T lnJ = J > T(0) ? log_t<FASTLN>(J) : T(NAN);
     T M[3][3], tr = T(0);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
@@ -528,7 +543,8 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
         hyper_voxel3_res<T, PW, PP>(pl + s0 * NPL, pl + s1 * NPL, pass == 0 ? bown : bext, Fb,
                                     pass == 0 ? lam0 : lame, pass == 0 ? mu0 : mue, ih, vol, f, count, own10);
       } else {
-        hyper_voxel3<T, PW, PP, UNI>(pl + s0 * NPL, pl + s1 * NPL, pass == 0 ? bown : bext, Fb,
+        constexpr bool FASTLN = sizeof(T) == 4 || sizeof(TO) == 4;
+        hyper_voxel3<T, PW, PP, UNI, FASTLN>(pl + s0 * NPL, pl + s1 * NPL, pass == 0 ? bown : bext, Fb,
                                      (pass == 0 ? lam0 : lame) * wt, (pass == 0 ? mu0 : mue) * wt, ih, f);
       }
       const int ci = pass == 0 ? cown : cext;
