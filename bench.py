@@ -290,8 +290,8 @@ def bench_hyper(args, B, ms, progress):
         "roofline": {
             "bound": "alu", "kernel": "k_apply (neo-Hookean tangent)", "achieved": round(achieved, 2),
             "peak": round(ALU_F32_PEAK_TFLOPS, 1), "unit": "TFLOP/s", "frac": round(achieved / ALU_F32_PEAK_TFLOPS, 4),
-            "traffic": None, "avg_launch_ms": round(ms_k / launches_k, 4), "launches": launches_k,
-            "flops_per_voxel": HYPER_FLOPS_PER_VOXEL, "dominant_kernel": dom,
+            "traffic": measured_traffic("k_apply", f"hyper_grf3d_{n1}"), "avg_launch_ms": round(ms_k / launches_k, 4),
+            "launches": launches_k, "flops_per_voxel": HYPER_FLOPS_PER_VOXEL, "dominant_kernel": dom,
         },
         "kernel_ms": {k: round(v[0], 2) for k, v in prof.items()},
         "gpu_busy_frac": round(sum(v[0] for v in prof.values()) * 1e-3 / dt, 4),
@@ -351,6 +351,13 @@ def main():
     def progress(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     if args.workload == "uneven":
         print(json.dumps(bench_uneven(args, B, ms, progress)), flush=True)
         return
@@ -364,12 +371,6 @@ def main():
     nud = torch.from_numpy(nu.ravel()).cuda()
     torch.cuda.synchronize()
 
-    if args.copy_probe:
-        a = torch.empty(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
 
     # ---------------------------------------------------------------- mixed
     cell = B.Cell((n1, n1, n1), precision=B.MIXED, tol=1e-6)
