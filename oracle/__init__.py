@@ -26,7 +26,11 @@ What it computes (plain definitions, written out slowly):
                  stress, its derivative, explicit tangent assembly and
                  Newton's method (Sec. 4, nonlinear problems) with direct
                  sparse solves and an Armijo line search.
+  * ``surrogate`` the stencil functions of the assembled K (Sec. 3.2), their
+                 B-spline interpolants from every M-th node (Sec. 3.3), the
+                 symmetric kernel-preserving surrogate matrix (Sec. 3.4) and
+                 its constrained direct solve.
 
 Every function states the passage or the standard mathematics it follows.
 """
-from . import fem, hyper, matfree  # noqa: F401
+from . import fem, hyper, matfree, surrogate  # noqa: F401
