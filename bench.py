@@ -299,6 +299,82 @@ def bench_hyper(args, B, ms, progress):
     }
 
 
+def bench_surrogate(args, B, ms, progress):
+    """Surrogate stencil operator: log-normal E (sigma 1, correlation length
+    args.ell voxels) at args.n^3, nu 0.3, the six unit loads, mixed precision
+    tol 1e-6; C* of the surrogate solutions (sampling step args.M, cubic
+    B-splines) against the exact matrix-free path on the same field."""
+    import torch
+    n1 = args.n
+    n = n1 ** 3
+    E, nu = ms.lognormal_field(n1, 7, ell=args.ell, sigma=1.0)
+    cell = B.Cell((n1, n1, n1), precision=B.MIXED, tol=1e-6)
+    cell.set_material(torch.from_numpy(E.ravel()).cuda(), torch.from_numpy(nu.ravel()).cuda())
+    if not args.no_tune:
+        cell.autotune()
+    C_exact, info_exact = cell.effective_stiffness()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C_exact, info_exact = cell.effective_stiffness()
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t0
+    setup = cell.set_surrogate(args.M, 3)
+    progress(f"exact {t_exact:.3f} s iters {info_exact['iters']}; surrogate setup {setup:.2f} s")
+    for i in range(args.warmup):
+        cell.effective_stiffness()
+    cell.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for i in range(args.steps):
+        C_sr, info = cell.effective_stiffness()
+        iters += sum(info["iters"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = cell.profile_read()
+    cell.profile(False)
+    cell.close()
+    ms_k, launches = prof["k_apply"]
+    # algorithmic bytes per launch with 6 active loads: the stencil (63 FP32
+    # values per node) once, p read and q written per load
+    alg = 63 * 4 * n + 6 * 24 * n
+    achieved = alg / (ms_k / launches * 1e-3) / 1e9
+    err = float(np.abs(C_sr - C_exact).max() / np.abs(C_exact).max())
+    progress(f"timed {args.steps} steps in {dt:.3f} s, iters {info['iters']}, C error {err:.3e}")
+    return {
+        "metric": "DOF-CG-iterations/sec of the surrogate-stencil solve at 256^3 (mixed, tol 1e-6)",
+        "value": 3 * n * iters / dt,
+        "unit": "DOF-CG-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"surrogate_lognormal_{n1}: {n1}^3 voxels, log-normal E (sigma 1, correlation length "
+                        f"{args.ell:g} voxels, seed 7), nu 0.3, six unit loads, surrogate stencil functions "
+                        f"sampled every {args.M} nodes with cubic B-splines, mixed precision tol 1e-6",
+            "voxels": n, "M": args.M, "q": 3, "iters": info["iters"],
+            "exact_iters": info_exact["iters"],
+        },
+        "surrogate_setup_s": round(setup, 3),
+        "exact_time_to_solution_s": round(t_exact, 4),
+        "surrogate_time_to_solution_s": round(dt / args.steps, 4),
+        "C_rel_err_surrogate_vs_exact": err,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_apply (surrogate stencil)", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(ms_k / launches, 4), "launches": launches, "bytes_per_launch": alg,
+        },
+        "kernel_ms": {k: round(v[0], 2) for k, v in prof.items()},
+        "cpu_baseline": None,
+    }
+
+
 def copy_bandwidth(torch, mib=1024, reps=5):
     """Device-to-device copy rate (GB/s of read + write traffic) of a plain
     torch copy of `mib` MiB, best of `reps`: the practically reachable HBM
@@ -328,11 +404,13 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
     ap.add_argument("--schedule", default=None,
                     help="six comma-separated ints: use this kernel schedule instead of tuning")
-    ap.add_argument("--workload", default="grf3d", choices=["grf3d", "uneven", "hyper"],
+    ap.add_argument("--workload", default="grf3d", choices=["grf3d", "uneven", "hyper", "surrogate"],
                     help="grf3d: the 256^3 headline workload; uneven: the batch of sphere cells; "
                          "hyper: the neo-Hookean Newton-PCG on the grf3d geometry")
     ap.add_argument("--cells", type=int, default=512, help="cells of the uneven batch")
     ap.add_argument("--contrast", type=float, default=10.0, help="phase contrast of the hyper workload")
+    ap.add_argument("--M", type=int, default=4, help="sampling step of the surrogate workload")
+    ap.add_argument("--ell", type=float, default=32.0, help="correlation length of the surrogate workload")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -363,6 +441,9 @@ def main():
         return
     if args.workload == "hyper":
         print(json.dumps(bench_hyper(args, B, ms, progress)), flush=True)
+        return
+    if args.workload == "surrogate":
+        print(json.dumps(bench_surrogate(args, B, ms, progress)), flush=True)
         return
     n1 = args.n
     n = n1 ** 3

@@ -217,6 +217,29 @@ cell_status cell_apply_hyper_tangent(cell_t c, int precision, const double* F_ba
                                      double* q_out);
 cell_status cell_hyper_residual(cell_t c, const double* F_bar, const double* u, double* f_out, double* sums_out);
 
+/* ---- surrogate stencil operator (Sec. 3.3, 3.4) ----------------------------
+ * Replaces the operator of later cell_solve / cell_effective_stiffness calls
+ * by its surrogate: the stencil functions K_delta(x_i) (the 3 x 3 blocks of K
+ * coupling node i with node i + delta, delta in the seven nonzero 0/1
+ * offsets x, y, z, xy, yz, xz, xyz) are computed exactly at every M-th node
+ * along each axis and interpolated everywhere by periodic cardinal
+ * B-splines of degree q (1 or 3) with knots at those nodes; the off-diagonal
+ * blocks at -delta are the transposes, the diagonal block is minus the
+ * symmetric part of the block row sum (eq.
+ * DefinitionOfSurrogateMatrixSymmetricKernel).  The PCG then solves the
+ * surrogate system over fluctuations with zero nodal mean, with the exact
+ * load vectors; the reported C* is the exact energy form of the surrogate
+ * solutions' strain fields (>= the exact C*, by the quadratic consistency
+ * error), the mean stresses and residuals those of the exact operator at
+ * them.  M = 0 switches the surrogate off (as does cell_set_material).
+ * 3D single-cell handles; M must divide every grid size.  The stencil takes
+ * 63 FP64 + 63 FP32 values per node of device memory.  cell_adjoint returns
+ * CELL_E_STATE while a surrogate is set.  setup_seconds (may be NULL): time
+ * of the sampling, the spline coefficients and the expansion. */
+cell_status cell_set_surrogate(cell_t c, int M, int q, double* setup_seconds);
+/* the interpolated stencil blocks, host [7][3][3][n] (FP64), offset order above */
+cell_status cell_get_surrogate_stencil(cell_t c, double* blocks_out);
+
 /* ---- autotuner ------------------------------------------------------------
  *
  * A schedule picks the compiled variant of each iteration kernel; all

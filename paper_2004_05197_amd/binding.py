@@ -103,6 +103,8 @@ _SIGS = {
     "cell_autotune": (ct.c_int, [_P, ct.c_int]),
     "cell_solve_hyper": (ct.c_int, [_P, ct.c_int, _P, ct.c_double, ct.c_int, _P, ct.POINTER(CellHyperInfo)]),
     "cell_apply_hyper_tangent": (ct.c_int, [_P, ct.c_int, _P, _P, _P, _P]),
+    "cell_set_surrogate": (ct.c_int, [_P, ct.c_int, ct.c_int, _P]),
+    "cell_get_surrogate_stencil": (ct.c_int, [_P, _P]),
     "cell_hyper_residual": (ct.c_int, [_P, _P, _P, _P, _P]),
     "cell_get_schedule": (ct.c_int, [_P, _P]),
     "cell_set_schedule": (ct.c_int, [_P, _P]),
@@ -258,6 +260,19 @@ class Cell:
         _check(_lib.cell_apply_hyper_tangent(self._h, int(pr), Fb.ctypes.data_as(ct.c_void_p), u.ctypes.data_as(ct.c_void_p),
                                              p.ctypes.data_as(ct.c_void_p), q.ctypes.data_as(ct.c_void_p)))
         return q
+
+    def set_surrogate(self, M, q=3):
+        """Surrogate stencil operator for later solves (M = 0: off); returns
+        the setup time in seconds."""
+        t = ct.c_double(0.0)
+        _check(_lib.cell_set_surrogate(self._h, int(M), int(q), ct.byref(t)))
+        return t.value
+
+    def surrogate_stencil(self):
+        """The interpolated stencil blocks (7, 3, 3, n) (FP64)."""
+        out = np.zeros((7, 3, 3, self.n))
+        _check(_lib.cell_get_surrogate_stencil(self._h, out.ctypes.data_as(ct.c_void_p)))
+        return out
 
     def hyper_residual(self, F_bar, u):
         Fb = np.ascontiguousarray(np.asarray(F_bar, dtype=np.float64).reshape(self.dim, self.dim))

@@ -228,6 +228,7 @@ cell_status cell_effective_stiffness(cell_t c, double* C_out, cell_info* info) {
 
 cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int on_device) {
   if (!c || !dJ_dC || !dJ_dE_out) return fail(CELL_E_ARG, "null argument");
+  if (c->sr_M > 0) return fail(CELL_E_STATE, "the adjoint needs the exact operator (a surrogate stencil operator is set)");
   if (!c->solved_unit) return fail(CELL_E_STATE, "cell_adjoint needs a preceding cell_effective_stiffness");
   DevGuard dg(c->dev);
   const int nv = c->nv;
@@ -342,6 +343,19 @@ cell_status cell_hyper_residual(cell_t c, const double* F_bar, const double* u, 
   if (!c->have_mat[0]) return fail(CELL_E_STATE, "cell_set_material has not been called");
   DevGuard dg(c->dev);
   return instance_hyper_step(c, CELL_FP64, F_bar, u, nullptr, f_out, sums_out);
+}
+
+cell_status cell_set_surrogate(cell_t c, int M, int q, double* setup_seconds) {
+  if (!c) return fail(CELL_E_ARG, "null argument");
+  DevGuard dg(c->dev);
+  const cell_status st = instance_set_surrogate(c, M, q);
+  if (st >= 0 && setup_seconds) *setup_seconds = c->sr_setup_s;
+  return st;
+}
+
+cell_status cell_get_surrogate_stencil(cell_t c, double* blocks_out) {
+  if (!c || !blocks_out) return fail(CELL_E_ARG, "null argument");
+  return instance_get_surrogate(c, blocks_out);
 }
 
 cell_status cell_autotune(cell_t c, int force) {

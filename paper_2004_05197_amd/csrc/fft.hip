@@ -103,7 +103,13 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
     cpx<T>* Z = buf + rr * RS;
     if (k == 0) {
       const cpx<T> z0 = Z[0];
-      Z[0] = {z0.re + z0.im, z0.re - z0.im};
+      T dc = z0.re + z0.im;
+      if (MODE == 0 && a.qmean) {
+        // projected operator: q's per-component mean leaves the DC term only
+        const int row = row0 + rr;
+        if (row < a.nrows) dc -= (T)(2.0 * M * a.qmean[l * 3 + row / a.comp_rows]);
+      }
+      Z[0] = {dc, z0.re - z0.im};
     } else {
       const cpx<T> zk = Z[pad8(k)], zm = Z[pad8(M - k)];
       const cpx<T> E = (zk + conj(zm)) * T(0.5);

@@ -76,6 +76,9 @@ template <typename T> struct XArgs {
   const int* mask;
   LoadState* st;
   RedBuf red;
+  const double* qmean;  // xfwd mode 0, nullptr or [slot][3]: per-component mean of q,
+                        // removed from its transform (the projected operator P K P)
+  int comp_rows;        // rows per component (ny nz) for qmean
 };
 
 // ---------------------------------------------------------------- y pass (3D)
@@ -178,6 +181,36 @@ hipError_t launch_round_slots(const double* x, float* y, long long len, int nslo
 // slots; parts: scratch of at least 3 * nslot * maxparts doubles
 hipError_t launch_remove_mean(double* x, long long lstride, long long n, int d, int nslot, const int* mask,
                               double* parts, int maxparts, hipStream_t s);
+// ------------------------------------------------- surrogate stencil operator
+// Stencil functions of the 3D operator: the 3 x 3 block coupling node i with
+// node i + delta for the seven offsets delta in {x, y, z, xy, yz, xz, xyz}
+// (0/1 vectors), stored [delta][a][b][n] (k = 9 delta + 3 a + b).
+constexpr int SR_NOFF = 7;
+constexpr int SR_NVAL = 63;
+template <typename T> struct SArgs {
+  const T* s;           // surrogate stencil blocks [63][n]
+  const T* p;           // mode 0: direction; mode 1: iterate u [slot][3][n]
+  void* out;            // mode 0: q (T); mode 1: r (TO)
+  const double* rhs;    // mode 1: load vectors f [slot][3][n]
+  long long lstride;
+  Geom g;
+  int nslot;            // <= 6
+  LoadState* st;        // mode 0 liveness
+  const int* mask;      // mode 1 slots
+  double* cparts;       // per-block component sums [slot][3][nb]
+  double* mean;         // [slot][3] component means of the output
+  RedBuf red;
+};
+// B-spline expansion of the stencil coefficients on the lattice of every
+// M-th node (degree q in {1, 3}) to every node, FP64 and FP32 copies
+hipError_t launch_sr_expand(const double* coef, int ncx, int ncy, int ncz, int M, int q, const Geom& g, double* s64,
+                            float* s32, hipStream_t s);
+// q = Kt p for the active slots, p.q partials, per-component means of q
+template <typename T> hipError_t launch_sr_apply(const SArgs<T>& a, hipStream_t s);
+// r = P (f - Kt u) in FP64 (written as float if out32) for the masked
+// slots, ||r||^2 -> res2
+hipError_t launch_sr_residual(const SArgs<double>& a, bool out32, double* res2, hipStream_t s);
+
 // r = rhs over the first m reals of every masked slot (float if out32),
 // ||r||^2 -> res2 (the Newton residual at du = 0)
 hipError_t launch_rhs_residual(const double* rhs, void* r, bool out32, long long lstride, long long m, int nslot,

@@ -78,13 +78,24 @@ struct cell_s {
   double* scratch = nullptr;
   int hblk = 0;
   // neo-Hookean Newton path
-  int op = 0;                   // PCG operator: 0 linear elasticity, 1 neo-Hookean tangent
+  int op = 0;                   // PCG operator: 0 linear elasticity, 1 neo-Hookean tangent,
+                                // 2 surrogate stencil (while one is set)
   double* hy_u = nullptr;       // Newton state [nslot][d n]
   float* hy_u32 = nullptr;      // its FP32 rounding (mixed-precision tangent)
   double* hy_ut = nullptr;      // line-search trial state
   double* hy_rhs = nullptr;     // f(u) = -grad Pi [nslot][d n]
   double* hy_F = nullptr;       // [nslot][9] macroscopic deformation gradients
   float* hy_F32 = nullptr;      // the same rounded to FP32
+  // surrogate stencil operator (op 2): sampling step, spline degree, the
+  // interpolated stencil blocks [63][n] (FP64, FP32), exact load vectors
+  // [slot][3][n], per-block component sums and component means [slot][3]
+  int sr_M = 0, sr_q = 0;
+  double* sr64 = nullptr;
+  float* sr32 = nullptr;
+  double* sr_rhs = nullptr;
+  double* sr_parts = nullptr;
+  double* sr_mean = nullptr;
+  double sr_setup_s = 0.0;
   double* hy_t = nullptr;       // [nslot] line-search steps
   double* hy_vparts = nullptr;  // [nslot][10][maxblk] energy / stress partials
   double* hy_vals = nullptr;    // [nslot][10]
@@ -134,6 +145,11 @@ cell_status instance_apply_precond(cell_s* c, int precision, const double* r, do
 // p == nullptr: out = f(u) = -grad Pi in FP64, vals[10] = sum |s| W, sum |s| P
 cell_status instance_hyper_step(cell_s* c, int precision, const double* Fbar, const double* u, const double* p,
                                 double* out, double* vals);
+// surrogate stencil operator: M = 0 switches it off; else sample every M-th
+// node, B-spline degree q; later solves use it (op 2)
+cell_status instance_set_surrogate(cell_s* c, int M, int q);
+// the interpolated stencil blocks [7][3][3][n] (host, FP64)
+cell_status instance_get_surrogate(cell_s* c, double* out);
 cell_status instance_profile(cell_s* c, int enable);
 cell_status instance_profile_read(cell_s* c, double* ms_out, long long* launches_out);
 // autotuner: schedule from the cache (unless force) or by timing the variants

@@ -332,6 +332,8 @@ XArgs<T> xargs(cell_s* c) {
   xa.mask = nullptr;
   xa.st = c->st;
   xa.red = red_of(c);
+  xa.qmean = c->op == 2 ? c->sr_mean : nullptr;
+  xa.comp_rows = c->g.ny * (c->d == 3 ? c->g.nz : 1);
   return xa;
 }
 
@@ -365,6 +367,25 @@ HyArgs<T> hyargs(cell_s* c) {
   return h;
 }
 
+// surrogate stencil operator arguments (stencil copy in the arithmetic type)
+template <typename T> const T* sr_stencil(cell_s* c);
+template <> const float* sr_stencil<float>(cell_s* c) { return c->sr32; }
+template <> const double* sr_stencil<double>(cell_s* c) { return c->sr64; }
+
+template <typename T>
+SArgs<T> sargs(cell_s* c) {
+  SArgs<T> a{};
+  a.s = sr_stencil<T>(c);
+  a.lstride = c->lstride;
+  a.g = c->g;
+  a.nslot = c->nslot;
+  a.st = c->st;
+  a.cparts = c->sr_parts;
+  a.mean = c->sr_mean;
+  a.red = red_of(c);
+  return a;
+}
+
 // one PCG iteration over all slots (or the initial preconditioning if !kapply)
 template <typename T>
 cell_status iteration(cell_s* c, bool kapply) {
@@ -378,6 +399,11 @@ cell_status iteration(cell_s* c, bool kapply) {
       ha.p = F.p;
       ha.out = F.q;
       HIPCHK(launch_hyper_tangent<T>(ha, s));
+    } else if (c->op == 2) {
+      SArgs<T> sa = sargs<T>(c);
+      sa.p = F.p;
+      sa.out = F.q;
+      HIPCHK(launch_sr_apply<T>(sa, s));
     } else {
       KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c));
       HIPCHK(launch_stencil<T>(ka, c->sched, s));
@@ -459,6 +485,26 @@ cell_status residual(cell_s* c, const double* u, const int* mask) {
     HIPCHK(hipStreamSynchronize(c->stream));
     return CELL_OK;
   }
+  if (c->op == 2) {
+    // surrogate: r = P (f - Kt u) (f exact, computed at the start of the solve)
+    {
+      ProfScope ps(c, CELL_K_RESIDUAL);
+      if (u) {
+        SArgs<double> sa = sargs<double>(c);
+        sa.p = u;
+        sa.out = F.r;
+        sa.rhs = c->sr_rhs;
+        sa.mask = mask;
+        HIPCHK(launch_sr_residual(sa, sizeof(T) == 4, c->res2, c->stream));
+      } else {
+        HIPCHK(launch_rhs_residual(c->sr_rhs, F.r, sizeof(T) == 4, c->lstride, (long long)c->d * c->n, c->nslot,
+                                   mask, red_of(c), c->st, c->res2, c->stream));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(c->res2_h, c->res2, sizeof(double) * c->nslot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return CELL_OK;
+  }
   KArgs<double> ka = kargs<double>(c, 1, u, nullptr, c->mat64);
   ka.mask = mask;
   ka.sparts = c->sparts;
@@ -489,6 +535,13 @@ cell_status begin_t(SolveRun& R) {
   HIPCHK(hipMemsetAsync(F.p, 0, fb, s));
   HIPCHK(hipMemsetAsync(F.q, 0, fb, s));
   if (c->precision == CELL_MIXED) HIPCHK(hipMemsetAsync(c->x64, 0, sizeof(double) * (size_t)c->lstride * ns, s));
+  if (c->op == 2) {
+    // the exact load vectors f = -B^T D eps_bar (FP64) for the surrogate path
+    KArgs<double> ka = kargs<double>(c, 1, nullptr, nullptr, c->mat64);
+    ka.out = c->sr_rhs;
+    ProfScope ps(c, CELL_K_RESIDUAL);
+    HIPCHK(launch_stencil<double>(ka, c->sched, s));
+  }
   // load vectors f = -B^T D eps_bar and ||f||^2 for every slot
   STCHK(residual<T>(c, nullptr, nullptr));
   R.fn2.assign(ns, 0.0);
@@ -749,6 +802,11 @@ void instance_destroy(cell_s* c) {
   fr(c->hy_rhs);
   fr(c->hy_F);
   fr(c->hy_F32);
+  fr(c->sr64);
+  fr(c->sr32);
+  fr(c->sr_rhs);
+  fr(c->sr_parts);
+  fr(c->sr_mean);
   fr(c->hy_t);
   fr(c->hy_vparts);
   fr(c->hy_vals);
@@ -880,6 +938,9 @@ cell_status instance_set_material(cell_s* c, int cell, const double* E, const do
   if (!c || !E || !nu) return fail(CELL_E_ARG, "null argument");
   if (cell < 0 || cell >= c->ncell) return fail(CELL_E_ARG, "cell index out of range");
   DevGuard dg(c->dev);
+  // a surrogate built from the previous material no longer applies
+  c->sr_M = 0;
+  if (c->op == 2) c->op = 0;
   const long long n = c->n;
   std::vector<double> Eh(n), nh(n);
   if (on_device) {
@@ -954,7 +1015,16 @@ cell_status solve_end(SolveRun& R) {
   cell_s* c = R.c;
   const cell_status st = end_t(R);
   if (st < 0) return st;
-  if (c->op == 0) {
+  if (c->op == 2) {
+    // surrogate solutions: the exact residual and stress sums at u~ for the
+    // energy-form C* of their strain fields
+    const double* u = c->precision == CELL_MIXED ? c->x64 : c->f64.x;
+    c->op = 0;
+    const cell_status sr = c->precision == CELL_MIXED ? residual<float>(c, u, nullptr) : residual<double>(c, u, nullptr);
+    c->op = 2;
+    STCHK(sr);
+  }
+  if (c->op == 0 || c->op == 2) {
     STCHK(homogenize(c, R.nload));
     c->linear_results = true;
   }
@@ -1127,7 +1197,7 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
         if (st >= 0) st = solve_poll(R);
       }
       if (st >= 0) st = solve_end(R);
-      c->op = 0;
+      c->op = c->sr_M > 0 ? 2 : 0;
       c->max_iter = keep;
       if (st < 0) return st;
       // negative curvature in the first iteration leaves du = 0: take the
@@ -1314,10 +1384,164 @@ cell_status instance_hyper_solve(cell_s* c, int nload, const double* Fbar, doubl
   if (infos) std::memset(infos, 0, sizeof(cell_hyper_info) * c->ncell);
   const double t0 = now_s();
   const cell_status st = hyper_run(c, nload, Fbar, tol, max_newton, P_out, infos);
-  c->op = 0;
+  c->op = c->sr_M > 0 ? 2 : 0;
   if (infos && st >= 0)
     for (int cell = 0; cell < c->ncell; ++cell) infos[cell].seconds = now_s() - t0;
   return st;
+}
+
+// ============================================ surrogate stencil operator
+namespace {
+
+// periodic system a x_{i-1} + b x_i + a x_{i+1} = d_i with a = 1/6, b = 2/3:
+// the cubic B-spline interpolation conditions along one lattice axis.
+// Sherman-Morrison on the Thomas algorithm: A = T + u v^T with the corners
+// of A moved into u v^T, u = (g, 0, .., 0, a), v = (1, 0, .., 0, a / g),
+// g = -b, and T's first and last diagonal entries b - g and b - a^2 / g.
+void cubic_line(double* v, long long stride, int n, std::vector<double>& y, std::vector<double>& z,
+                std::vector<double>& cp) {
+  const double a = 1.0 / 6.0, b = 2.0 / 3.0;
+  if (n == 1) return;  // the periodic sum of the spline over all shifts is 1
+  if (n == 2) {
+    const double d0 = v[0], d1 = v[stride], det = b * b - 4.0 * a * a;
+    v[0] = (b * d0 - 2.0 * a * d1) / det;
+    v[stride] = (b * d1 - 2.0 * a * d0) / det;
+    return;
+  }
+  const double g = -b;
+  auto diag = [&](int i) { return i == 0 ? b - g : (i == n - 1 ? b - a * a / g : b); };
+  auto thomas = [&](const double* rhs, long long rs, std::vector<double>& x) {
+    double den = diag(0);
+    cp[0] = a / den;
+    x[0] = rhs[0] / den;
+    for (int i = 1; i < n; ++i) {
+      den = diag(i) - a * cp[i - 1];
+      cp[i] = a / den;
+      x[i] = (rhs[i * rs] - a * x[i - 1]) / den;
+    }
+    for (int i = n - 2; i >= 0; --i) x[i] -= cp[i] * x[i + 1];
+  };
+  std::vector<double> u(n, 0.0);
+  u[0] = g;
+  u[n - 1] = a;
+  thomas(v, stride, y);
+  thomas(u.data(), 1, z);
+  const double fact = (y[0] + a / g * y[n - 1]) / (1.0 + z[0] + a / g * z[n - 1]);
+  for (int i = 0; i < n; ++i) v[i * stride] = y[i] - fact * z[i];
+}
+
+}  // namespace
+
+cell_status instance_set_surrogate(cell_s* c, int M, int q) {
+  if (M == 0) {
+    c->sr_M = 0;
+    if (c->op == 2) c->op = 0;
+    return CELL_OK;
+  }
+  if (c->d != 3) return fail(CELL_E_UNSUPPORTED, "the surrogate stencil operator is implemented in 3D");
+  if (c->ncell != 1 || c->nslot > 6) return fail(CELL_E_UNSUPPORTED, "the surrogate stencil operator needs a single-cell handle");
+  if (!c->have_mat[0]) return fail(CELL_E_STATE, "cell_set_material has not been called");
+  if (M < 0 || (q != 1 && q != 3)) return fail(CELL_E_ARG, "M must be >= 0 and q 1 or 3");
+  const int nx = c->g.nx, ny = c->g.ny, nz = c->g.nz;
+  if (nx % M || ny % M || nz % M) return fail(CELL_E_ARG, "M must divide every grid size");
+  DevGuard dg(c->dev);
+  const double t0 = now_s();
+  const long long n = c->n;
+  std::vector<double> mat(2 * n);
+  HIPCHK(hipMemcpyAsync(mat.data(), c->mat64, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const int ncx = nx / M, ncy = ny / M, ncz = nz / M;
+  const long long nc = (long long)ncx * ncy * ncz;
+  std::vector<double> S((size_t)SR_NVAL * nc, 0.0);
+  const double ih[3] = {1.0 / c->g.h[0], 1.0 / c->g.h[1], 1.0 / c->g.h[2]};
+  const double vol = c->g.h[0] * c->g.h[1] * c->g.h[2] / 6.0;
+  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  static const int offm[SR_NOFF] = {1, 2, 4, 3, 6, 5, 7};  // offsets as corner bit masks (x | y << 1 | z << 2)
+  // barycentric gradient of path vertex m of simplex t
+  auto grad = [&](int t, int m, double* gv) {
+    gv[0] = gv[1] = gv[2] = 0.0;
+    if (m > 0) gv[perm[t][m - 1]] += ih[perm[t][m - 1]];
+    if (m < 3) gv[perm[t][m]] -= ih[perm[t][m]];
+  };
+  // stencil functions at the lattice nodes: K[X, X + delta] = sum over the
+  // simplices holding both nodes of |s| (lam g1 g2^T + mu g2 g1^T + mu g1.g2 I)
+  for (int cz = 0; cz < ncz; ++cz)
+    for (int cy = 0; cy < ncy; ++cy)
+      for (int cx = 0; cx < ncx; ++cx) {
+        const int X[3] = {cx * M, cy * M, cz * M};
+        const long long ci = ((long long)cz * ncy + cy) * ncx + cx;
+        for (int k = 0; k < SR_NOFF; ++k) {
+          double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+          for (int c1 = 0; c1 < 8; ++c1) {
+            if (c1 & offm[k]) continue;
+            const int c2 = c1 | offm[k];
+            const int vx = (X[0] - (c1 & 1) + nx) % nx, vy = (X[1] - ((c1 >> 1) & 1) + ny) % ny;
+            const int vz = (X[2] - ((c1 >> 2) & 1) + nz) % nz;
+            const long long vid = ((long long)vz * ny + vy) * nx + vx;
+            const double lam = mat[2 * vid], mu = mat[2 * vid + 1];
+            for (int t = 0; t < 6; ++t) {
+              int path[4] = {0, 0, 0, 0}, m1 = -1, m2 = -1;
+              for (int m = 0; m < 3; ++m) path[m + 1] = path[m] | (1 << perm[t][m]);
+              for (int m = 0; m < 4; ++m) {
+                if (path[m] == c1) m1 = m;
+                if (path[m] == c2) m2 = m;
+              }
+              if (m1 < 0 || m2 < 0) continue;
+              double g1[3], g2[3];
+              grad(t, m1, g1);
+              grad(t, m2, g2);
+              const double dg = g1[0] * g2[0] + g1[1] * g2[1] + g1[2] * g2[2];
+              for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                  blk[3 * a + b] += vol * (lam * g1[a] * g2[b] + mu * g1[b] * g2[a] + (a == b ? mu * dg : 0.0));
+            }
+          }
+          for (int e = 0; e < 9; ++e) S[(size_t)(9 * k + e) * nc + ci] = blk[e];
+        }
+      }
+  if (q == 3) {
+    // interpolation coefficients: the cubic system along x, then y, then z
+    const int nmax = std::max(ncx, std::max(ncy, ncz));
+    std::vector<double> y(nmax), z(nmax), cp(nmax);
+    for (int v = 0; v < SR_NVAL; ++v) {
+      double* f = S.data() + (size_t)v * nc;
+      for (int cz = 0; cz < ncz; ++cz)
+        for (int cy = 0; cy < ncy; ++cy) cubic_line(f + ((long long)cz * ncy + cy) * ncx, 1, ncx, y, z, cp);
+      for (int cz = 0; cz < ncz; ++cz)
+        for (int cx = 0; cx < ncx; ++cx) cubic_line(f + (long long)cz * ncy * ncx + cx, ncx, ncy, y, z, cp);
+      for (int cy = 0; cy < ncy; ++cy)
+        for (int cx = 0; cx < ncx; ++cx) cubic_line(f + (long long)cy * ncx + cx, (long long)ncx * ncy, ncz, y, z, cp);
+    }
+  }
+  auto dm = [&](void** p, size_t bytes) { return *p != nullptr || hipMalloc(p, bytes) == hipSuccess; };
+  if (!dm((void**)&c->sr64, sizeof(double) * SR_NVAL * n) || !dm((void**)&c->sr32, sizeof(float) * SR_NVAL * n) ||
+      !dm((void**)&c->sr_rhs, sizeof(double) * (size_t)c->lstride * c->nslot) ||
+      !dm((void**)&c->sr_parts, sizeof(double) * 3 * (size_t)c->nslot * c->maxblk) ||
+      !dm((void**)&c->sr_mean, sizeof(double) * 3 * c->nslot))
+    return fail(CELL_E_NOMEM, "device allocation of the surrogate stencil failed");
+  double* coef = nullptr;
+  if (hipMalloc((void**)&coef, sizeof(double) * S.size()) != hipSuccess)
+    return fail(CELL_E_NOMEM, "device allocation of the spline coefficients failed");
+  hipError_t e = hipMemcpyAsync(coef, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_sr_expand(coef, ncx, ncy, ncz, M, q, c->g, c->sr64, c->sr32, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->sr_mean, 0, sizeof(double) * 3 * c->nslot, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(coef);
+  if (e != hipSuccess) return fail(CELL_E_DEVICE, hipGetErrorString(e));
+  c->sr_M = M;
+  c->sr_q = q;
+  c->op = 2;
+  c->solved = c->solved_unit = c->linear_results = false;
+  c->sr_setup_s = now_s() - t0;
+  return CELL_OK;
+}
+
+cell_status instance_get_surrogate(cell_s* c, double* out) {
+  if (c->sr_M == 0) return fail(CELL_E_STATE, "no surrogate stencil operator is set");
+  DevGuard dg(c->dev);
+  HIPCHK(hipMemcpyAsync(out, c->sr64, sizeof(double) * SR_NVAL * c->n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CELL_OK;
 }
 
 // ============================================ single-step entry points (tests)
@@ -1363,6 +1587,13 @@ cell_status apply_operator_t(cell_s* c, const double* u, double* q) {
   HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * c->nslot, hipMemcpyHostToDevice, c->stream));
   for (int l = 0; l < 6; ++l)
     for (int i = 0; i < 6; ++i) c->eps_v[l][i] = 0.0;
+  if (c->op == 2) {  // the surrogate operator while one is set (output before projection)
+    SArgs<T> sa = sargs<T>(c);
+    sa.p = F.p;
+    sa.out = F.q;
+    HIPCHK(launch_sr_apply<T>(sa, c->stream));
+    return download_field<T>(c, q, F.q);
+  }
   KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c));
   HIPCHK(launch_stencil<T>(ka, c->sched, c->stream));
   return download_field<T>(c, q, F.q);
