@@ -30,7 +30,10 @@ What it computes (plain definitions, written out slowly):
                  B-spline interpolants from every M-th node (Sec. 3.3), the
                  symmetric kernel-preserving surrogate matrix (Sec. 3.4) and
                  its constrained direct solve.
+  * ``strainproj`` the strain-based Fourier projection variant: CG on
+                 compatible strain fields with the FE-gradient projection
+                 B (B^T D0 B)^-1 B^T D, a cross-check of the PCG iteration.
 
 Every function states the passage or the standard mathematics it follows.
 """
-from . import fem, hyper, matfree, surrogate  # noqa: F401
+from . import fem, hyper, matfree, strainproj, surrogate  # noqa: F401
