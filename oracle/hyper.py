@@ -127,6 +127,35 @@ def residual(grid, E, nu, u, Fbar):
     return f
 
 
+def residual_at_nodes(grid, E, nu, u, Fbar, nodes):
+    """f = -sum |s| B^T P(F_s) at selected nodes only (spot checks of fields
+    too large for the full evaluation): node = vertex j of simplex type s in
+    the voxel at node - V_s[j]; its row of -|s| P g_j, summed over (s, j).
+    u: (d n,) or (d, n); nodes: flat indices.  Returns (len(nodes), d)."""
+    d = grid.d
+    u = np.asarray(u, dtype=np.float64).reshape(d, grid.n)
+    nodes = np.asarray(nodes, dtype=np.int64)
+    lam, mu = lame(np.ravel(E), np.ravel(nu))
+    comps, idx = [], nodes.copy()
+    for N in grid.shape:
+        comps.append(idx % N)
+        idx = idx // N
+    out = np.zeros((len(nodes), d))
+    for V in kuhn_simplices(d):
+        X = V * np.asarray(grid.h)[None, :]
+        g, vol = p1_gradients(X)
+        for j in range(d + 1):
+            vox = [comps[a] - V[j, a] for a in range(d)]
+            vflat = grid.flat(vox)
+            F = np.tile(np.asarray(Fbar, dtype=np.float64), (len(nodes), 1, 1))
+            for k in range(d + 1):
+                nk = grid.flat([vox[a] + V[k, a] for a in range(d)])
+                F += np.einsum("av,b->vab", u[:, nk], g[k])
+            P = piola(F, lam[vflat], mu[vflat])
+            out -= vol * np.einsum("vab,b->va", P, g[j])
+    return out
+
+
 def assemble_tangent(grid, E, nu, u, Fbar):
     """Sparse K_T = sum |s| G^T A(F_s) G over the (d n) dofs (CSR)."""
     lam, mu = lame(np.ravel(E), np.ravel(nu))

@@ -52,6 +52,17 @@ def test_tangent_is_residual_derivative(shape):
     assert np.abs(fd - Kd).max() <= 1e-6 * np.abs(Kd).max()
 
 
+@pytest.mark.parametrize("shape", [(4, 3, 5), (5, 4)])
+def test_sampled_residual_equals_full(shape):
+    """The per-node gather used for spot checks of large fields equals the
+    full scatter evaluation at every node."""
+    grid = fem.Grid(shape, lengths=[1.0 + 0.1 * a for a in range(len(shape))])
+    E, nu, Fbar, u = rand_case(shape, 11)
+    f = hyper.residual(grid, E, nu, u, Fbar)
+    fs = hyper.residual_at_nodes(grid, E, nu, u, Fbar, np.arange(grid.n))
+    assert np.abs(fs.T - f).max() < 1e-14 * np.abs(f).max()
+
+
 def test_material_law_closed_forms():
     """P and A at F = I reduce to the linear law; P by differences of W."""
     lam, mu = np.array([1.3]), np.array([0.7])
