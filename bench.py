@@ -375,6 +375,64 @@ def bench_surrogate(args, B, ms, progress):
     }
 
 
+def bench_adjoint(args, B, ms, progress):
+    """Adjoint gradient: 128^3 log-normal E (correlation length 6 voxels,
+    sigma 1, seed 5), nu 0.3, J = C*_1111 + C*_2323; one step = the six
+    unit-load solve (FP64, tol 1e-10) plus dJ/dE over all voxels."""
+    import torch
+    n1 = args.n if args.n != 256 else 128
+    n = n1 ** 3
+    E, nu = ms.lognormal_field(n1, seed=5)
+    cell = B.Cell((n1, n1, n1), precision=B.FP64, tol=1e-10)
+    cell.set_material(torch.from_numpy(E.ravel()).cuda(), torch.from_numpy(nu.ravel()).cuda())
+    dJ = np.zeros((6, 6))
+    dJ[0, 0] = dJ[3, 3] = 1.0
+    g = torch.empty(n, dtype=torch.float64, device="cuda")
+    if not args.no_tune:
+        cell.autotune()
+    for i in range(args.warmup):
+        cell.effective_stiffness()
+        cell.adjoint(dJ, out=g)
+    torch.cuda.synchronize()
+    t_solve = t_grad = 0.0
+    iters = 0
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        C, info = cell.effective_stiffness()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cell.adjoint(dJ, out=g)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_solve += t1 - t0
+        t_grad += t2 - t1
+        iters += sum(info["iters"])
+    cell.close()
+    gh = g.cpu().numpy()
+    J = C[0, 0] + C[3, 3]
+    euler = abs(float(np.dot(gh, E.ravel())) - J) / J
+    progress(f"{args.steps} steps: solve {t_solve:.3f} s, gradient {t_grad * 1e3:.2f} ms, Euler gap {euler:.2e}")
+    dt = t_solve + t_grad
+    return {
+        "metric": "DOF-CG-iterations/sec of the 128^3 FP64 solve with the adjoint gradient",
+        "value": 3 * n * iters / dt,
+        "unit": "DOF-CG-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {
+            "workload": f"adjoint_lognormal_{n1}: {n1}^3 voxels, log-normal E (correlation length 6 voxels, "
+                        "sigma 1, seed 5), nu 0.3, six unit loads in FP64 to tol 1e-10, J = C*_1111 + C*_2323, "
+                        "dJ/dE over every voxel",
+            "voxels": n, "iters": info["iters"],
+        },
+        "gradient_ms": round(t_grad / args.steps * 1e3, 3),
+        "solve_ms": round(t_solve / args.steps * 1e3, 3),
+        "euler_identity_gap": euler,
+        "cpu_baseline": None,
+    }
+
+
 def copy_bandwidth(torch, mib=1024, reps=5):
     """Device-to-device copy rate (GB/s of read + write traffic) of a plain
     torch copy of `mib` MiB, best of `reps`: the practically reachable HBM
@@ -404,7 +462,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
     ap.add_argument("--schedule", default=None,
                     help="six comma-separated ints: use this kernel schedule instead of tuning")
-    ap.add_argument("--workload", default="grf3d", choices=["grf3d", "uneven", "hyper", "surrogate"],
+    ap.add_argument("--workload", default="grf3d", choices=["grf3d", "uneven", "hyper", "surrogate", "adjoint"],
                     help="grf3d: the 256^3 headline workload; uneven: the batch of sphere cells; "
                          "hyper: the neo-Hookean Newton-PCG on the grf3d geometry")
     ap.add_argument("--cells", type=int, default=512, help="cells of the uneven batch")
@@ -444,6 +502,9 @@ def main():
         return
     if args.workload == "surrogate":
         print(json.dumps(bench_surrogate(args, B, ms, progress)), flush=True)
+        return
+    if args.workload == "adjoint":
+        print(json.dumps(bench_adjoint(args, B, ms, progress)), flush=True)
         return
     n1 = args.n
     n = n1 ** 3
