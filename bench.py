@@ -299,6 +299,44 @@ def bench_hyper(args, B, ms, progress):
     }
 
 
+def cpu_baseline_surrogate(E, nu, M, sub=12):
+    from oracle import fem, surrogate as sg
+    Es = np.ascontiguousarray(E[:sub, :sub, :sub])
+    nus = np.ascontiguousarray(nu[:sub, :sub, :sub])
+    g = fem.Grid((sub, sub, sub))
+    t0 = time.perf_counter()
+    sg.effective_stiffness(g, Es, nus, M, 3)
+    dt = time.perf_counter() - t0
+    return {
+        "value": 6 * 3 * g.n / dt,
+        "unit": "DOF-solves/s",
+        "cores": len(os.sched_getaffinity(0)),
+        "kind": "oracle",
+        "sample": f"surrogate stencils (M {M}, cubic), surrogate matrix and bordered direct solve of the six unit "
+                  f"loads (numpy/scipy FP64, SuperLU) on a {sub}^3 periodic sub-block of the {E.shape[0]}^3 field, "
+                  f"{dt:.1f} s",
+    }
+
+
+def cpu_baseline_adjoint(E, nu, sub=16):
+    from oracle import fem
+    Es = np.ascontiguousarray(E[:sub, :sub, :sub])
+    nus = np.ascontiguousarray(nu[:sub, :sub, :sub])
+    g = fem.Grid((sub, sub, sub))
+    t0 = time.perf_counter()
+    _, _, u = fem.effective_stiffness(g, Es, nus)
+    fem.dC_dE(g, Es, nus, u, fem.unit_loads(3))
+    dt = time.perf_counter() - t0
+    return {
+        "value": 6 * 3 * g.n / dt,
+        "unit": "DOF-solves/s",
+        "cores": len(os.sched_getaffinity(0)),
+        "kind": "oracle",
+        "sample": f"direct solve of the six unit loads and dC*/dE over all voxels (numpy/scipy FP64, SuperLU) "
+                  f"on a {sub}^3 periodic sub-block of the {E.shape[0]}^3 field, {dt:.1f} s",
+    }
+
+
 def bench_surrogate(args, B, ms, progress):
     """Surrogate stencil operator: log-normal E (sigma 1, correlation length
     args.ell voxels) at args.n^3, nu 0.3, the six unit loads, mixed precision
@@ -361,6 +399,7 @@ def bench_surrogate(args, B, ms, progress):
             "voxels": n, "M": args.M, "q": 3, "iters": info["iters"],
             "exact_iters": info_exact["iters"],
         },
+        "dof_solves_per_s": 6 * 3 * n / (dt / args.steps),
         "surrogate_setup_s": round(setup, 3),
         "exact_time_to_solution_s": round(t_exact, 4),
         "surrogate_time_to_solution_s": round(dt / args.steps, 4),
@@ -371,7 +410,7 @@ def bench_surrogate(args, B, ms, progress):
             "avg_launch_ms": round(ms_k / launches, 4), "launches": launches, "bytes_per_launch": alg,
         },
         "kernel_ms": {k: round(v[0], 2) for k, v in prof.items()},
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_surrogate(E, nu, args.M),
     }
 
 
@@ -429,7 +468,8 @@ def bench_adjoint(args, B, ms, progress):
         "gradient_ms": round(t_grad / args.steps * 1e3, 3),
         "solve_ms": round(t_solve / args.steps * 1e3, 3),
         "euler_identity_gap": euler,
-        "cpu_baseline": None,
+        "dof_solves_per_s": 6 * 3 * n / (dt / args.steps),
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_adjoint(E, nu),
     }
 
 
