@@ -243,3 +243,14 @@ def test_hyper_errors(lib):
         with pytest.raises(lib.CellError) as e:
             c.solve_hyper(np.eye(3)[None], tol=-1.0)
         assert e.value.status == lib.CELL_E_ARG
+        for bad in (np.zeros((0, 3, 3)), np.tile(np.eye(3), (7, 1, 1)), np.full((1, 3, 3), np.nan)):
+            with pytest.raises(lib.CellError) as e:
+                c.solve_hyper(bad)
+            assert e.value.status == lib.CELL_E_ARG
+        # a Newton iteration cap that is too small reports CELL_NOT_CONVERGED
+        # with the iterate reached, and the linear results stay unavailable
+        E = np.where(np.arange(512) % 3 == 0, 10.0, 1.0)
+        c.set_material(E, np.full(512, 0.3))
+        P, info = c.solve_hyper(np.diag([1.2, 1.0, 1.0])[None], tol=1e-12, max_newton=1)
+        assert info["status"] == "CELL_NOT_CONVERGED" and info["newton_iters"][0] == 1
+        assert np.all(np.isfinite(P))
