@@ -184,11 +184,19 @@ hipError_t launch_remove_mean(double* x, long long lstride, long long n, int d, 
 // ------------------------------------------------- surrogate stencil operator
 // Stencil functions of the 3D operator: the 3 x 3 block coupling node i with
 // node i + delta for the seven offsets delta in {x, y, z, xy, yz, xz, xyz}
-// (0/1 vectors), stored [delta][a][b][n] (k = 9 delta + 3 a + b).
+// (0/1 vectors), value k = 9 delta + 3 a + b (row a, column b).
 constexpr int SR_NOFF = 7;
 constexpr int SR_NVAL = 63;
+// Stencil layout: runs of SR_CHUNK consecutive nodes store their 63 values
+// value-major (value v of node i at sr_chunk(i) + v * SR_CHUNK), so one
+// wavefront's stencil reads cover one contiguous 16 KB (FP32) region
+constexpr int SR_CHUNK = 64;
+__host__ __device__ inline long long sr_chunk(long long node) {
+  return (node / SR_CHUNK) * (SR_NVAL * SR_CHUNK) + node % SR_CHUNK;
+}
+inline long long sr_len(long long n) { return (n + SR_CHUNK - 1) / SR_CHUNK * SR_CHUNK * SR_NVAL; }
 template <typename T> struct SArgs {
-  const T* s;           // surrogate stencil blocks [63][n]
+  const T* s;           // surrogate stencil blocks, chunked layout (sr_chunk)
   const T* p;           // mode 0: direction; mode 1: iterate u [slot][3][n]
   void* out;            // mode 0: q (T); mode 1: r (TO)
   const double* rhs;    // mode 1: load vectors f [slot][3][n]
@@ -205,6 +213,9 @@ template <typename T> struct SArgs {
 // M-th node (degree q in {1, 3}) to every node, FP64 and FP32 copies
 hipError_t launch_sr_expand(const double* coef, int ncx, int ncy, int ncz, int M, int q, const Geom& g, double* s64,
                             float* s32, hipStream_t s);
+// partial sums written by the surrogate operator's launches (for the
+// reduction buffers)
+int sr_max_blocks(const Geom& g);
 // q = Kt p for the active slots, p.q partials, per-component means of q
 template <typename T> hipError_t launch_sr_apply(const SArgs<T>& a, hipStream_t s);
 // r = P (f - Kt u) in FP64 (written as float if out32) for the masked

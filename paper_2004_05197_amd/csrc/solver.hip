@@ -1514,7 +1514,7 @@ cell_status instance_set_surrogate(cell_s* c, int M, int q) {
     }
   }
   auto dm = [&](void** p, size_t bytes) { return *p != nullptr || hipMalloc(p, bytes) == hipSuccess; };
-  if (!dm((void**)&c->sr64, sizeof(double) * SR_NVAL * n) || !dm((void**)&c->sr32, sizeof(float) * SR_NVAL * n) ||
+  if (!dm((void**)&c->sr64, sizeof(double) * sr_len(n)) || !dm((void**)&c->sr32, sizeof(float) * sr_len(n)) ||
       !dm((void**)&c->sr_rhs, sizeof(double) * (size_t)c->lstride * c->nslot) ||
       !dm((void**)&c->sr_parts, sizeof(double) * 3 * (size_t)c->nslot * c->maxblk) ||
       !dm((void**)&c->sr_mean, sizeof(double) * 3 * c->nslot))
@@ -1539,8 +1539,13 @@ cell_status instance_set_surrogate(cell_s* c, int M, int q) {
 cell_status instance_get_surrogate(cell_s* c, double* out) {
   if (c->sr_M == 0) return fail(CELL_E_STATE, "no surrogate stencil operator is set");
   DevGuard dg(c->dev);
-  HIPCHK(hipMemcpyAsync(out, c->sr64, sizeof(double) * SR_NVAL * c->n, hipMemcpyDeviceToHost, c->stream));
+  const long long n = c->n;
+  std::vector<double> buf(sr_len(n));
+  HIPCHK(hipMemcpyAsync(buf.data(), c->sr64, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  // chunked device layout -> [value][node]
+  for (long long i = 0; i < n; ++i)
+    for (int v = 0; v < SR_NVAL; ++v) out[(long long)v * n + i] = buf[sr_chunk(i) + (long long)v * SR_CHUNK];
   return CELL_OK;
 }
 

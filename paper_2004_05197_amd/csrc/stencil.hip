@@ -976,7 +976,7 @@ int max_reduction_blocks(const Geom& g) {
         mb = std::max(mb, stencil_blocks(g, sc, fp64));
       }
   }
-  return mb;
+  return std::max(mb, sr_max_blocks(g));
 }
 
 template <typename T, typename TO, int MODE, int BX, int BY>

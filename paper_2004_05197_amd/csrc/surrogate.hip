@@ -14,6 +14,8 @@
 // the kernel by that small skew part, so the PCG iterates the projected operator P Kt P (P:
 // zero nodal mean per component): every launch also returns the component
 // means of its output, which the x pass removes from the transform.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace cellfft {
@@ -71,8 +73,9 @@ __global__ __launch_bounds__(NT) void k_sr_expand(const double* coef, int ncx, i
           const double wzy = wz[mz] * wy[my];
           for (int mx = 0; mx < np; ++mx) s += wzy * wx[mx] * row[jx[mx]];
         }
-      s64[(long long)v * n + node] = s;
-      s32[(long long)v * n + node] = (float)s;
+      const long long o = sr_chunk(node) + (long long)v * SR_CHUNK;
+      s64[o] = s;
+      s32[o] = (float)s;
     }
   }
 }
@@ -80,100 +83,174 @@ __global__ __launch_bounds__(NT) void k_sr_expand(const double* coef, int ncx, i
 // MODE 0: q = Kt p (T) for the active slots, p.q partials.
 // MODE 1: r = f - Kt u (FP64, written as TO) for the masked slots.
 // Both: per-block component sums of the output (for its mean).
-template <typename T, typename TO, int MODE>
-__global__ __launch_bounds__(NT) void k_sr_apply(SArgs<T> a) {
-  __shared__ double sh[NT / WAVE];
+//
+// A block owns a BX x BY tile of nodes in tz planes and applies all six
+// slots, so every stencil value is read from HBM once per launch.  Its
+// neighbours' blocks A_d(i - d) and the direction vectors around the tile
+// are read by the blocks running beside it on the same XCD (tiles are dealt
+// to XCDs in contiguous runs, ordered so that those blocks form a short
+// stack of planes) and mostly come from L2.  The stencil is laid out in
+// 64-node chunks (sr_chunk), so one wavefront's 63 stencil loads read one
+// contiguous 16 KB region.
+template <typename T, typename TO, int MODE, int BX, int BY>
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_sr_apply3t(SArgs<T> a, int tz, int nxt, int nyt, int nzt, int gy) {
+  static_assert(BX * BY == NT, "one tile row per thread");
+  constexpr int NSUM = 24;  // per slot: p.q and the three component sums
+  __shared__ double sh[(NT / WAVE) * NSUM];
   const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
   const long long n = a.g.n;
+  const int blk = xcd_order(blockIdx.x, nxt * nyt * nzt);
+  if (blk < 0) return;  // whole block
+  // tile order: x tiles fastest, then gy tiles in y, then z, then the
+  // groups of gy tile rows, so that the blocks running together on one XCD
+  // cover a short stack of planes and reuse each other's planes from L2
+  int r = blk;
+  const int xi = r % nxt;
+  r /= nxt;
+  const int yl = r % gy;
+  r /= gy;
+  const int zi = r % nzt, yi = (r / nzt) * gy + yl;
+  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  const int x = xi * BX + tx, y = yi * BY + ty;
+  const int z0 = zi * tz, z1 = min(z0 + tz, nz);
   bool live[6];
 #pragma unroll
   for (int l = 0; l < 6; ++l)
     live[l] = l < a.nslot && (MODE == 0 ? a.st[l].state == ST_ACTIVE : (a.mask ? a.mask[l] != 0 : true));
-  double dot[6] = {0, 0, 0, 0, 0, 0};
-  double csum[6][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (long long node = (long long)blockIdx.x * NT + threadIdx.x; node < n; node += (long long)gridDim.x * NT) {
-    const int i = (int)(node % nx), j = (int)((node / nx) % ny), k = (int)(node / ((long long)nx * ny));
-    T acc[6][3];
+  // per-thread sums over the column's tz nodes in T, across the block in
+  // FP64
+  T dot[6], csum[6][3];
 #pragma unroll
-    for (int l = 0; l < 6; ++l)
+  for (int l = 0; l < 6; ++l) {
+    dot[l] = T(0);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[l][c] = T(0);
-    // skew part of the block row sum (its diagonal correction)
-    T rs[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+    for (int c = 0; c < 3; ++c) csum[l][c] = T(0);
+  }
+  // every slot is computed (a slot beyond nslot reads slot 0): no branch
+  // on liveness splits the loads of one offset into dependent groups;
+  // only live slots are stored and summed
+  const T* pv[6];
 #pragma unroll
-    for (int d = 0; d < SR_NOFF; ++d) {
-      const long long jp =
-          ((long long)swrap(k + SOFF[d][2], nz) * ny + swrap(j + SOFF[d][1], ny)) * nx + swrap(i + SOFF[d][0], nx);
-      const long long jm =
-          ((long long)swrap(k - SOFF[d][2], nz) * ny + swrap(j - SOFF[d][1], ny)) * nx + swrap(i - SOFF[d][0], nx);
-      T A[3][3], B[3][3];
+  for (int l = 0; l < 6; ++l) pv[l] = a.p + (l < a.nslot ? l : 0) * a.lstride;
+  if (x < nx && y < ny) {
+    const int xs[3] = {swrap(x - 1, nx), x, swrap(x + 1, nx)};
+    const int ys[3] = {swrap(y - 1, ny), y, swrap(y + 1, ny)};
+    for (int z = z0; z < z1; ++z) {
+      const int zs[3] = {swrap(z - 1, nz), z, swrap(z + 1, nz)};
+      const long long node = ((long long)z * ny + y) * nx + x;
+      const T* so = a.s + sr_chunk(node);
+      T acc[6][3], pi[6][3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+      for (int l = 0; l < 6; ++l)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          A[r][c] = a.s[(long long)(9 * d + 3 * r + c) * n + node];  // A_d(i)
-          B[r][c] = a.s[(long long)(9 * d + 3 * r + c) * n + jm];    // A_d(i - d)
+          acc[l][c] = T(0);
+          pi[l][c] = pv[l][c * n + node];
+        }
+      // the edge form below applies -R_i to p_i; the diagonal is -sym(R_i):
+      // the skew part of the block row sum R_i is added at the end
+      T rs[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+      // one offset at a time keeps the live registers to one pair of blocks;
+      // BELOW: an offset with a z component, whose A_d(i - d) lies in the
+      // plane below
+      auto offset = [&](const int d, auto below) {
+        constexpr bool BELOW = decltype(below)::value;
+        const int m = (0x7563421 >> (4 * d)) & 7;  // offset d as bits x | y << 1 | z << 2
+        const int ox = m & 1, oy = (m >> 1) & 1, oz = m >> 2;
+        const long long jp = ((long long)zs[1 + oz] * ny + ys[1 + oy]) * nx + xs[1 + ox];
+        const long long jm = ((long long)zs[1 - oz] * ny + ys[1 - oy]) * nx + xs[1 - ox];
+        const T* sm = a.s + sr_chunk(jm);
+        // all 54 loads of the offset first, then the arithmetic: the
+        // scheduler would otherwise interleave them one load per wait.
+        // A_d(i) is read once per launch, and the blocks of the plane below
+        // were last touched a whole plane of the XCD's tiles ago: both
+        // stream past L2 (non-temporal), which keeps L2 for the direction
+        // vectors and the in-plane neighbour blocks
+        T A[3][3], B[3][3], pp[6][3], pm[6][3];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+          A[e / 3][e % 3] = __builtin_nontemporal_load(so + (9 * d + e) * SR_CHUNK);  // A_d(i)
+          if constexpr (BELOW) B[e / 3][e % 3] = __builtin_nontemporal_load(sm + (9 * d + e) * SR_CHUNK);
+          else B[e / 3][e % 3] = sm[(9 * d + e) * SR_CHUNK];  // A_d(i - d)
         }
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+        for (int l = 0; l < 6; ++l)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rs[r][c] += A[r][c] + B[c][r];
+          for (int c = 0; c < 3; ++c) {
+            pp[l][c] = pv[l][c * n + jp];
+            pm[l][c] = pv[l][c * n + jm];
+          }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) rs[r][c] += A[r][c] + B[c][r];
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+          T dp[3], dm[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            dp[c] = pp[l][c] - pi[l][c];
+            dm[c] = pm[l][c] - pi[l][c];
+          }
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            acc[l][r] += A[r][0] * dp[0] + A[r][1] * dp[1] + A[r][2] * dp[2] + B[0][r] * dm[0] + B[1][r] * dm[1] +
+                         B[2][r] * dm[2];
+        }
+      };
+      // the in-plane offsets x, y, xy, then z, yz, xz, xyz
+#pragma unroll 1
+      for (int k = 0; k < 3; ++k) offset((0x310 >> (4 * k)) & 15, std::false_type());
+#pragma unroll 1
+      for (int k = 0; k < 4; ++k) offset((0x6542 >> (4 * k)) & 15, std::true_type());
 #pragma unroll
       for (int l = 0; l < 6; ++l) {
         if (!live[l]) continue;
-        const T* p = a.p + l * a.lstride;
-        T pi[3], dp[3], dm[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          pi[c] = p[c * n + node];
-          dp[c] = p[c * n + jp] - pi[c];
-          dm[c] = p[c * n + jm] - pi[c];
-        }
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-          acc[l][r] += A[r][0] * dp[0] + A[r][1] * dp[1] + A[r][2] * dp[2] + B[0][r] * dm[0] + B[1][r] * dm[1] +
-                       B[2][r] * dm[2];
-      }
-    }
-    // the edge form above applies -R_i to p_i; the diagonal is -sym(R_i):
-    // add skew(R_i) p_i
+          acc[l][r] += T(0.5) * ((rs[r][0] - rs[0][r]) * pi[l][0] + (rs[r][1] - rs[1][r]) * pi[l][1] +
+                                 (rs[r][2] - rs[2][r]) * pi[l][2]);
 #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      if (!live[l]) continue;
-      const T* p = a.p + l * a.lstride;
-      T pi[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) pi[c] = p[c * n + node];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-        acc[l][r] += T(0.5) * ((rs[r][0] - rs[0][r]) * pi[0] + (rs[r][1] - rs[1][r]) * pi[1] +
-                               (rs[r][2] - rs[2][r]) * pi[2]);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const long long o = l * a.lstride + c * n + node;
-        if (MODE == 0) {
-          reinterpret_cast<T*>(a.out)[o] = acc[l][c];
-          dot[l] += (double)pi[c] * (double)acc[l][c];
-          csum[l][c] += (double)acc[l][c];
-        } else {
-          const double r = a.rhs[o] - (double)acc[l][c];
-          reinterpret_cast<TO*>(a.out)[o] = (TO)r;
-          csum[l][c] += r;
+        for (int c = 0; c < 3; ++c) {
+          const long long o = l * a.lstride + c * n + node;
+          if (MODE == 0) {
+            reinterpret_cast<T*>(a.out)[o] = acc[l][c];
+            dot[l] += pi[l][c] * acc[l][c];
+            csum[l][c] += acc[l][c];
+          } else {
+            const double r = a.rhs[o] - (double)acc[l][c];
+            reinterpret_cast<TO*>(a.out)[o] = (TO)r;
+            csum[l][c] += r;
+          }
         }
       }
     }
   }
-  const int nb = gridDim.x;
+  // the 24 block sums in one pass: wave sums, one barrier, one thread each
+  const int nb = nxt * nyt * nzt;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
 #pragma unroll
   for (int l = 0; l < 6; ++l) {
-    if (!live[l]) continue;  // uniform across the block
-    if (MODE == 0) {
-      const double s = block_sum<NT>(dot[l], sh);
-      if (threadIdx.x == 0) a.red.slot_parts(RED_PQ, l)[blockIdx.x] = s;
-    }
+    const double dw = wave_sum((double)dot[l]);
+    if (lane == 0) sh[wv * NSUM + l] = dw;
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double s = block_sum<NT>(csum[l][c], sh);
-      if (threadIdx.x == 0) a.cparts[((long long)l * 3 + c) * nb + blockIdx.x] = s;
+      const double cw = wave_sum((double)csum[l][c]);
+      if (lane == 0) sh[wv * NSUM + 6 + 3 * l + c] = cw;
+    }
+  }
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < NSUM) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / WAVE; ++w) s += sh[w * NSUM + k];
+    if (k < 6) {
+      if (MODE == 0 && live[k]) a.red.slot_parts(RED_PQ, k)[blk] = s;
+    } else {
+      const int l = (k - 6) / 3, c = (k - 6) % 3;
+      if (live[l]) a.cparts[((long long)l * 3 + c) * nb + blk] = s;
     }
   }
 }
@@ -220,35 +297,58 @@ hipError_t launch_sr_expand(const double* coef, int ncx, int ncy, int ncz, int M
   return hipGetLastError();
 }
 
-static int sr_blocks(const Geom& g, int maxblk) {
-  long long nb = (g.n + NT - 1) / NT;
-  if (nb > 4096) nb = 4096;
-  if (nb > maxblk) nb = maxblk;
-  return (int)nb;
+namespace {
+constexpr int SR_BX = 64, SR_BY = 4;
+
+struct SrGrid {
+  int tz, nxt, nyt, nzt, gy, nb;
+};
+
+SrGrid sr_grid(const Geom& g) {
+  SrGrid t;
+  t.nxt = (g.nx + SR_BX - 1) / SR_BX;
+  t.nyt = (g.ny + SR_BY - 1) / SR_BY;
+  // one plane per block, groups of up to 4 tile rows (4 x 4 = 16 rows): the
+  // order that measured fastest at 256^3 (planes per block 1 to 16, groups
+  // of 1 to 64 tile rows); gy divides nyt so the order covers every tile once
+  t.tz = 1;
+  t.gy = t.nyt % 4 == 0 ? 4 : (t.nyt % 2 == 0 ? 2 : 1);
+  t.nzt = g.nz;
+  t.nb = t.nxt * t.nyt * t.nzt;
+  return t;
 }
+}  // namespace
 
 template <typename T>
 hipError_t launch_sr_apply(const SArgs<T>& a, hipStream_t s) {
-  if (a.nslot > 6) return hipErrorInvalidValue;
-  const int nb = sr_blocks(a.g, a.red.maxblk);
-  hipLaunchKernelGGL((k_sr_apply<T, T, 0>), dim3(nb), dim3(NT), 0, s, a);
+  if (a.nslot > 6 || a.g.dim != 3) return hipErrorInvalidValue;
+  const SrGrid t = sr_grid(a.g);
+  if (t.nb > a.red.maxblk) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sr_apply3t<T, T, 0, SR_BX, SR_BY>), dim3(xcd_grid(t.nb)), dim3(NT), 0, s, a, t.tz, t.nxt,
+                     t.nyt, t.nzt, t.gy);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sr_mean<0>, dim3(3, a.nslot), dim3(NT), 0, s, (const double*)a.cparts, nb,
+  hipLaunchKernelGGL(k_sr_mean<0>, dim3(3, a.nslot), dim3(NT), 0, s, (const double*)a.cparts, t.nb,
                      a.g.n, (const LoadState*)a.st, (const int*)nullptr, a.mean);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_finalize(a.red, a.st, nullptr, RED_PQ, nb, a.nslot, -1, nullptr, s);
+  return launch_finalize(a.red, a.st, nullptr, RED_PQ, t.nb, a.nslot, -1, nullptr, s);
 }
 
 hipError_t launch_sr_residual(const SArgs<double>& a, bool out32, double* res2, hipStream_t s) {
-  if (a.nslot > 6) return hipErrorInvalidValue;
-  const int nb = sr_blocks(a.g, a.red.maxblk);
-  if (out32) hipLaunchKernelGGL((k_sr_apply<double, float, 1>), dim3(nb), dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL((k_sr_apply<double, double, 1>), dim3(nb), dim3(NT), 0, s, a);
+  if (a.nslot > 6 || a.g.dim != 3) return hipErrorInvalidValue;
+  const SrGrid t = sr_grid(a.g);
+  if (t.nb > a.red.maxblk) return hipErrorInvalidValue;
+  const dim3 grid(xcd_grid(t.nb));
+  if (out32)
+    hipLaunchKernelGGL((k_sr_apply3t<double, float, 1, SR_BX, SR_BY>), grid, dim3(NT), 0, s, a, t.tz, t.nxt, t.nyt,
+                       t.nzt, t.gy);
+  else
+    hipLaunchKernelGGL((k_sr_apply3t<double, double, 1, SR_BX, SR_BY>), grid, dim3(NT), 0, s, a, t.tz, t.nxt, t.nyt,
+                       t.nzt, t.gy);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sr_mean<1>, dim3(3, a.nslot), dim3(NT), 0, s, (const double*)a.cparts, nb,
+  hipLaunchKernelGGL(k_sr_mean<1>, dim3(3, a.nslot), dim3(NT), 0, s, (const double*)a.cparts, t.nb,
                      a.g.n, (const LoadState*)a.st, a.mask, a.mean);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -263,6 +363,8 @@ hipError_t launch_sr_residual(const SArgs<double>& a, bool out32, double* res2, 
   if (e != hipSuccess) return e;
   return launch_finalize(a.red, a.st, res2, RED_RES, nf, a.nslot, -1, a.mask, s);
 }
+
+int sr_max_blocks(const Geom& g) { return g.dim == 3 ? sr_grid(g).nb : 0; }
 
 template hipError_t launch_sr_apply<float>(const SArgs<float>&, hipStream_t);
 template hipError_t launch_sr_apply<double>(const SArgs<double>&, hipStream_t);

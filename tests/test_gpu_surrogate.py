@@ -30,8 +30,10 @@ def smooth_field(shape, seed, amp=0.5):
     return np.exp(amp * g / g.std())
 
 
+# lattice sizes per axis from 1 (one sample: constant interpolant) to 6,
+# both degrees, cubic and stretched cells
 CASES = [((8, 8, 8), 2, 1, None), ((8, 8, 8), 2, 3, None), ((12, 8, 4), 4, 3, (1.0, 1.1, 0.6)),
-         ((12, 12, 6), 3, 1, (1.2, 1.0, 0.5))]
+         ((12, 12, 6), 3, 1, (1.2, 1.0, 0.5)), ((8, 8, 8), 8, 3, None), ((24, 12, 12), 4, 3, None)]
 
 
 def case_data(shape, lengths, seed=1):
