@@ -255,6 +255,211 @@ __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(sizeof(T
   }
 }
 
+// FP32 operator for grids with nx a multiple of 64: one wavefront per tile
+// row of 64 nodes, so the x neighbours of a direction-vector row are the
+// next and previous lanes.  Each (load, component) row the stencil needs is
+// read once per node (own row, y +- 1, z +- 1, (y+1, z+1), (y-1, z-1): 7
+// instead of 15 gathered positions), the +-x shifted copies come from DPP
+// wave rotations, and the 8 values beyond the row ends (lane 63's right and
+// lane 0's left neighbour of the shifted rows) are gathered by lanes 0-7 in
+// one load and put in place with readlane before the rotation.
+namespace {
+// lane i <- lane i + 1 (LEFT) or i - 1, and the lane at the far end
+// receives edge (a wave-uniform value): the value rotated out of lane 0
+// (LEFT) or 63 is replaced by edge first, then the row is rotated by one
+template <bool LEFT>
+__device__ __forceinline__ float wshift(float v, int lane, float edge) {
+  const float t = lane == (LEFT ? 0 : WAVE - 1) ? edge : v;
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(t), LEFT ? 0x134 : 0x13C, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_value(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+}  // namespace
+
+template <int BY>
+__global__ __launch_bounds__(WAVE* BY) __attribute__((amdgpu_waves_per_eu(3))) void k_sr_apply3w(SArgs<float> a, int nxt,
+                                                                                                 int nyt, int nzt,
+                                                                                                 int gy) {
+  static_assert(WAVE * BY == NT, "one tile row per wavefront");
+  constexpr int NSUM = 24;
+  __shared__ double sh[(NT / WAVE) * NSUM];
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const long long n = a.g.n;
+  const int blk = xcd_order(blockIdx.x, nxt * nyt * nzt);
+  if (blk < 0) return;  // whole block
+  int r = blk;
+  const int xi = r % nxt;
+  r /= nxt;
+  const int yl = r % gy;
+  r /= gy;
+  const int z = r % nzt, yi = (r / nzt) * gy + yl;
+  const int lane = threadIdx.x % WAVE;
+  const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  const int x0 = xi * WAVE, x = x0 + lane, y = yi * BY + ty;
+  bool live[6];
+#pragma unroll
+  for (int l = 0; l < 6; ++l) live[l] = l < a.nslot && a.st[l].state == ST_ACTIVE;
+  float dot[6], csum[6][3];
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    dot[l] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) csum[l][c] = 0.f;
+  }
+  const float* pv[6];
+#pragma unroll
+  for (int l = 0; l < 6; ++l) pv[l] = a.p + (l < a.nslot ? l : 0) * a.lstride;
+  if (y < ny) {  // whole wavefront
+    const int ym = swrap(y - 1, ny), yp = swrap(y + 1, ny);
+    const int zm = swrap(z - 1, nz), zp = swrap(z + 1, nz);
+    // row starts (flat index of x = 0) of the seven rows
+    const long long r00 = ((long long)z * ny + y) * nx, rp0 = ((long long)z * ny + yp) * nx;
+    const long long rm0 = ((long long)z * ny + ym) * nx, r0p = ((long long)zp * ny + y) * nx;
+    const long long r0m = ((long long)zm * ny + y) * nx, rpp = ((long long)zp * ny + yp) * nx;
+    const long long rmm = ((long long)zm * ny + ym) * nx;
+    const long long node = r00 + x;
+    const int xr = swrap(x0 + WAVE, nx), xl = swrap(x0 - 1, nx);
+    // lanes 0-7 gather the row-end values: +x / -x of the own row, then the
+    // shifted rows of xy, xz, xyz (right end of the + row, left end of the - row)
+    long long eidx = node;
+    switch (lane) {
+      case 0: eidx = r00 + xr; break;
+      case 1: eidx = r00 + xl; break;
+      case 2: eidx = rp0 + xr; break;
+      case 3: eidx = rm0 + xl; break;
+      case 4: eidx = r0p + xr; break;
+      case 5: eidx = r0m + xl; break;
+      case 6: eidx = rpp + xr; break;
+      case 7: eidx = rmm + xl; break;
+      default: break;
+    }
+    const float* so = a.s + sr_chunk(node);
+    float acc[6][3], pi[6][3], E[6][3];
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[l][c] = 0.f;
+        pi[l][c] = pv[l][c * n + node];
+        E[l][c] = pv[l][c * n + eidx];
+      }
+    float rs[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    // offset d: A_d(i) from the own chunk, A_d(i - d) from the chunk of
+    // jm, then the update with p_{i+d} = pp, p_{i-d} = pm
+    auto stencil = [&](int d, long long jm, float (&A)[3][3], float (&B)[3][3], bool below) {
+      const float* sm = a.s + sr_chunk(jm);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        A[e / 3][e % 3] = __builtin_nontemporal_load(so + (9 * d + e) * SR_CHUNK);
+        if (below) B[e / 3][e % 3] = __builtin_nontemporal_load(sm + (9 * d + e) * SR_CHUNK);
+        else B[e / 3][e % 3] = sm[(9 * d + e) * SR_CHUNK];
+      }
+    };
+    // pp(l, c), pm(l, c): p_{i+d} and p_{i-d} of load l, component c
+    auto update = [&](const float (&A)[3][3], const float (&B)[3][3], auto pp, auto pm) {
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rs[rr][c] += A[rr][c] + B[c][rr];
+#pragma unroll
+      for (int l = 0; l < 6; ++l) {
+        float dp[3], dm[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          dp[c] = pp(l, c) - pi[l][c];
+          dm[c] = pm(l, c) - pi[l][c];
+        }
+#pragma unroll
+        for (int rr = 0; rr < 3; ++rr)
+          acc[l][rr] += A[rr][0] * dp[0] + A[rr][1] * dp[1] + A[rr][2] * dp[2] + B[0][rr] * dm[0] +
+                        B[1][rr] * dm[1] + B[2][rr] * dm[2];
+      }
+    };
+    // a pair of rows (+, -): the aligned offset d0 and the x-shifted offset
+    // d1 (edges ke, ke + 1 of the gather); the own row pairs with itself
+    auto pair = [&](long long rplus, long long rminus, int d0, int d1, int ke, auto below) {
+      constexpr bool BELOW = decltype(below)::value;
+      __builtin_amdgcn_sched_barrier(0);
+      float rp[6][3], rm[6][3];
+      float A[3][3], B[3][3];
+      if (d0 >= 0) {
+#pragma unroll
+        for (int l = 0; l < 6; ++l)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            rp[l][c] = pv[l][c * n + rplus + x];
+            rm[l][c] = pv[l][c * n + rminus + x];
+          }
+        stencil(d0, rminus + x, A, B, BELOW);
+        __builtin_amdgcn_sched_barrier(0);
+        update(A, B, [&](int l, int c) { return rp[l][c]; }, [&](int l, int c) { return rm[l][c]; });
+      } else {
+#pragma unroll
+        for (int l = 0; l < 6; ++l)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) rp[l][c] = rm[l][c] = pi[l][c];
+      }
+      stencil(d1, rminus + (lane ? x - 1 : xl), A, B, BELOW);
+      __builtin_amdgcn_sched_barrier(0);
+      update(
+          A, B, [&](int l, int c) { return wshift<true>(rp[l][c], lane, lane_value(E[l][c], ke)); },
+          [&](int l, int c) { return wshift<false>(rm[l][c], lane, lane_value(E[l][c], ke + 1)); });
+    };
+    // offsets in the stencil order x 0, y 1, z 2, xy 3, yz 4, xz 5, xyz 6
+    pair(r00, r00, -1, 0, 0, std::false_type());
+    pair(rp0, rm0, 1, 3, 2, std::false_type());
+    pair(r0p, r0m, 2, 5, 4, std::true_type());
+    pair(rpp, rmm, 4, 6, 6, std::true_type());
+    // every slot is finished and stored without a branch (a per-slot
+    // branch here let the compiler sink work into six blocks and spill): a
+    // converged slot's q is not read again, and a slot beyond nslot, which
+    // computed slot 0's q from slot 0's p, stores it over slot 0's q
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr)
+        acc[l][rr] += 0.5f * ((rs[rr][0] - rs[0][rr]) * pi[l][0] + (rs[rr][1] - rs[1][rr]) * pi[l][1] +
+                              (rs[rr][2] - rs[2][rr]) * pi[l][2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dot[l] += pi[l][c] * acc[l][c];
+        csum[l][c] += acc[l][c];
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        reinterpret_cast<float*>(a.out)[(l < a.nslot ? l : 0) * a.lstride + c * n + node] = acc[l][c];
+  }
+  const int nb = nxt * nyt * nzt;
+  const int wv = threadIdx.x / WAVE;
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    const double dw = wave_sum((double)dot[l]);
+    if (lane == 0) sh[wv * NSUM + l] = dw;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double cw = wave_sum((double)csum[l][c]);
+      if (lane == 0) sh[wv * NSUM + 6 + 3 * l + c] = cw;
+    }
+  }
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < NSUM) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / WAVE; ++w) s2 += sh[w * NSUM + k];
+    if (k < 6) {
+      if (live[k]) a.red.slot_parts(RED_PQ, k)[blk] = s2;
+    } else {
+      const int l = (k - 6) / 3, c = (k - 6) % 3;
+      if (live[l]) a.cparts[((long long)l * 3 + c) * nb + blk] = s2;
+    }
+  }
+}
+
 // component means of the output from the partial sums (fixed order); the
 // same liveness as the launch that wrote them
 template <int MODE>
@@ -324,8 +529,16 @@ hipError_t launch_sr_apply(const SArgs<T>& a, hipStream_t s) {
   if (a.nslot > 6 || a.g.dim != 3) return hipErrorInvalidValue;
   const SrGrid t = sr_grid(a.g);
   if (t.nb > a.red.maxblk) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sr_apply3t<T, T, 0, SR_BX, SR_BY>), dim3(xcd_grid(t.nb)), dim3(NT), 0, s, a, t.tz, t.nxt,
-                     t.nyt, t.nzt, t.gy);
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.g.nx % WAVE == 0 && t.tz == 1)
+      hipLaunchKernelGGL(k_sr_apply3w<SR_BY>, dim3(xcd_grid(t.nb)), dim3(NT), 0, s, a, t.nxt, t.nyt, t.nzt, t.gy);
+    else
+      hipLaunchKernelGGL((k_sr_apply3t<T, T, 0, SR_BX, SR_BY>), dim3(xcd_grid(t.nb)), dim3(NT), 0, s, a, t.tz,
+                         t.nxt, t.nyt, t.nzt, t.gy);
+  } else {
+    hipLaunchKernelGGL((k_sr_apply3t<T, T, 0, SR_BX, SR_BY>), dim3(xcd_grid(t.nb)), dim3(NT), 0, s, a, t.tz, t.nxt,
+                       t.nyt, t.nzt, t.gy);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sr_mean<0>, dim3(3, a.nslot), dim3(NT), 0, s, (const double*)a.cparts, t.nb,

@@ -31,9 +31,12 @@ def smooth_field(shape, seed, amp=0.5):
 
 
 # lattice sizes per axis from 1 (one sample: constant interpolant) to 6,
-# both degrees, cubic and stretched cells
+# both degrees, cubic and stretched cells; nx = 64 runs the FP32 operator
+# with one wavefront per row (full tiles of 4 rows, and ny = 6: a partial
+# tile)
 CASES = [((8, 8, 8), 2, 1, None), ((8, 8, 8), 2, 3, None), ((12, 8, 4), 4, 3, (1.0, 1.1, 0.6)),
-         ((12, 12, 6), 3, 1, (1.2, 1.0, 0.5)), ((8, 8, 8), 8, 3, None), ((24, 12, 12), 4, 3, None)]
+         ((12, 12, 6), 3, 1, (1.2, 1.0, 0.5)), ((8, 8, 8), 8, 3, None), ((24, 12, 12), 4, 3, None),
+         ((64, 8, 4), 4, 3, None), ((64, 6, 4), 2, 1, (1.0, 0.7, 0.9))]
 
 
 def case_data(shape, lengths, seed=1):
