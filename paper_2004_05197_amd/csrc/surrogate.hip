@@ -462,17 +462,25 @@ __global__ __launch_bounds__(WAVE* BY) __attribute__((amdgpu_waves_per_eu(3))) v
 
 // component means of the output from the partial sums (fixed order); the
 // same liveness as the launch that wrote them
+// (one partial per tile: tens of thousands per slot and component, so each
+// thread keeps 8 independent sums and issues 8 loads per round trip)
+constexpr int NTM = 1024;
 template <int MODE>
-__global__ __launch_bounds__(NT) void k_sr_mean(const double* cparts, int nb, long long n, const LoadState* st,
-                                                 const int* mask, double* mean) {
-  __shared__ double sh[NT / WAVE];
+__global__ __launch_bounds__(NTM) void k_sr_mean(const double* cparts, int nb, long long n, const LoadState* st,
+                                                  const int* mask, double* mean) {
+  __shared__ double sh[NTM / WAVE];
   const int c = blockIdx.x, l = blockIdx.y;
   const bool live = MODE == 0 ? st[l].state == ST_ACTIVE : (mask ? mask[l] != 0 : true);
   if (!live) return;
   const double* row = cparts + ((long long)l * 3 + c) * nb;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += NT) s += row[b];
-  s = block_sum<NT>(s, sh);
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int b = threadIdx.x;
+  for (; b + 7 * NTM < nb; b += 8 * NTM)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += row[b + k * NTM];
+  for (; b < nb; b += NTM) acc[0] += row[b];
+  double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  s = block_sum<NTM>(s, sh);
   if (threadIdx.x == 0) mean[l * 3 + c] = s / (double)n;
 }
 
@@ -541,7 +549,7 @@ hipError_t launch_sr_apply(const SArgs<T>& a, hipStream_t s) {
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sr_mean<0>, dim3(3, a.nslot), dim3(NT), 0, s, (const double*)a.cparts, t.nb,
+  hipLaunchKernelGGL(k_sr_mean<0>, dim3(3, a.nslot), dim3(NTM), 0, s, (const double*)a.cparts, t.nb,
                      a.g.n, (const LoadState*)a.st, (const int*)nullptr, a.mean);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -561,7 +569,7 @@ hipError_t launch_sr_residual(const SArgs<double>& a, bool out32, double* res2, 
                        t.nzt, t.gy);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sr_mean<1>, dim3(3, a.nslot), dim3(NT), 0, s, (const double*)a.cparts, t.nb,
+  hipLaunchKernelGGL(k_sr_mean<1>, dim3(3, a.nslot), dim3(NTM), 0, s, (const double*)a.cparts, t.nb,
                      a.g.n, (const LoadState*)a.st, a.mask, a.mean);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
