@@ -79,6 +79,28 @@ def test_solve_matches_oracle(lib, case, prec):
     assert relerr(U, uref) < (1e-8 if prec == 0 else 1e-5)
 
 
+@pytest.mark.parametrize("max_loads", [1, 2, 4])
+def test_fewer_load_slots(lib, max_loads):
+    """nx = 64 with fewer than six load slots (the unit loads solved in
+    rounds): the FP32 operator computes all six slot positions and stores
+    the unused ones over slot 0's output with slot 0's values; the surrogate
+    solutions must match the oracle's as with six slots."""
+    shape, M, q, lengths = CASES[6]
+    g, E, nu = case_data(shape, lengths)
+    _, uref = sg.effective_stiffness(g, E, nu, M, q)
+    eb = fem.unit_loads(3)
+    U = np.zeros_like(uref)
+    with lib.Cell(shape, precision=lib.MIXED, tol=1e-7, max_loads=max_loads) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        c.set_surrogate(M, q)
+        for j0 in range(0, 6, max_loads):
+            loads = eb[j0:j0 + max_loads]
+            c.solve(loads)
+            for k in range(len(loads)):
+                U[j0 + k] = c.displacement(k).ravel()
+    assert relerr(U, uref) < 1e-5
+
+
 def test_M1_and_homogeneous_equal_the_exact_path(lib):
     shape = (8, 8, 8)
     g, E, nu = case_data(shape, None, seed=3)
