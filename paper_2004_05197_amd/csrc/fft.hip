@@ -79,20 +79,29 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
   const T2* in2 = reinterpret_cast<const T2*>((MODE == 0 ? a.q : a.r) + l * a.lstride);
   cpx<T>* R = a.R + l * (a.lstride / 2);
   cpx<T> rv[QX];  // mode 0: this thread's R values, loaded with q
+  {
+    // every load first, then the LDS stores (a loop that stores each value
+    // as it arrives waits out one memory latency per element)
+    cpx<T> v[QX];
 #pragma unroll
-  for (int q = 0; q < QX; ++q) {
-    const int e = tid + q * NT;
-    if (e >= RPB * M) break;
-    const int rr = e / M, m = e - rr * M;
-    const int row = row0 + rr;
-    cpx<T> v = {T(0), T(0)};
-    if (row < a.nrows) {
-      const long long off = (long long)row * M + m;
-      const T2 w = in2[off];
-      v = {w.x, w.y};
-      if (MODE == 0) rv[q] = R[off];
+    for (int q = 0; q < QX; ++q) {
+      const int e = tid + q * NT;
+      const int rr = e / M, m = e - rr * M;
+      const int row = row0 + rr;
+      v[q] = {T(0), T(0)};
+      if (e < RPB * M && row < a.nrows) {
+        const long long off = (long long)row * M + m;
+        const T2 w = in2[off];
+        v[q] = {w.x, w.y};
+        if (MODE == 0) rv[q] = R[off];
+      }
     }
-    buf[rr * RS + pad8(m)] = v;
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+      const int e = tid + q * NT;
+      const int rr = e / M, m = e - rr * M;
+      if (e < RPB * M) buf[rr * RS + pad8(m)] = v[q];
+    }
   }
   __syncthreads();
   fft_lds<T, M, false, RPB, NT, 2, RowTileP<RS>, RP>(buf, tws);
@@ -171,20 +180,33 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
   const cpx<T>* S = a.S + l * a.lsS;
   // S rows live in padded (component, z) planes of zsS complex values
   const int zr0 = row0 / a.ny, yb = row0 - zr0 * a.ny;
-  for (int e = tid; e < RPB * M; e += NT) {
-    const int rr = e / M, m = e - rr * M;
-    const int row = row0 + rr;
-    int y = yb + rr, zr = zr0;
-    if (RPB <= a.ny) {
-      if (y >= a.ny) {
-        y -= a.ny;
-        ++zr;
+  {
+    // every load first, then the LDS stores (see the forward pass)
+    constexpr int QX = (RPB * M + NT - 1) / NT;
+    cpx<T> v[QX];
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+      const int e = tid + q * NT;
+      const int rr = e / M, m = e - rr * M;
+      const int row = row0 + rr;
+      int y = yb + rr, zr = zr0;
+      if (RPB <= a.ny) {
+        if (y >= a.ny) {
+          y -= a.ny;
+          ++zr;
+        }
+      } else {
+        zr += y / a.ny;
+        y -= (y / a.ny) * a.ny;
       }
-    } else {
-      zr += y / a.ny;
-      y -= (y / a.ny) * a.ny;
+      v[q] = (e < RPB * M && row < a.nrows) ? S[(long long)zr * a.zsS + (long long)y * M + m] : cpx<T>{T(0), T(0)};
     }
-    buf[rr * RS + pad8(m)] = row < a.nrows ? S[(long long)zr * a.zsS + (long long)y * M + m] : cpx<T>{T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < QX; ++q) {
+      const int e = tid + q * NT;
+      const int rr = e / M, m = e - rr * M;
+      if (e < RPB * M) buf[rr * RS + pad8(m)] = v[q];
+    }
   }
   __syncthreads();
   constexpr int KH = M / 2 + 1;
@@ -206,20 +228,35 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
   fft_lds<T, M, true, RPB, NT, 2, RowTileP<RS>, RP>(buf, tws);
   T2* x2 = reinterpret_cast<T2*>(a.x + l * a.lstride);
   T2* p2 = reinterpret_cast<T2*>(a.p + l * a.lstride);
-  for (int e = tid; e < RPB * M; e += NT) {
+  // x += alpha p, p = z + beta p: all of a thread's p and x loads first
+  constexpr int QO = (RPB * M + NT - 1) / NT;
+  T2 po[QO], xv[QO];
+#pragma unroll
+  for (int q = 0; q < QO; ++q) {
+    const int e = tid + q * NT;
     const int rr = e / M, m = e - rr * M;
     const int row = row0 + rr;
-    if (row < a.nrows) {
+    if (e < RPB * M && row < a.nrows) {
+      const long long off = (long long)row * M + m;
+      po[q] = p2[off];
+      xv[q] = x2[off];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < QO; ++q) {
+    const int e = tid + q * NT;
+    const int rr = e / M, m = e - rr * M;
+    const int row = row0 + rr;
+    if (e < RPB * M && row < a.nrows) {
       const long long off = (long long)row * M + m;
       const cpx<T> z = buf[rr * RS + pad8(m)];
-      const T2 po = p2[off];
-      T2 xv = x2[off];
-      xv.x += alpha * po.x;
-      xv.y += alpha * po.y;
-      x2[off] = xv;
+      T2 xn = xv[q];
+      xn.x += alpha * po[q].x;
+      xn.y += alpha * po[q].y;
+      x2[off] = xn;
       T2 pn;
-      pn.x = z.re + beta * po.x;
-      pn.y = z.im + beta * po.y;
+      pn.x = z.re + beta * po[q].x;
+      pn.y = z.im + beta * po[q].y;
       p2[off] = pn;
     }
   }
@@ -248,9 +285,21 @@ __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
   for (int i = tid; i < N; i += NTY) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lsS + (long long)(c * a.nz + z) * a.zsS + s0;
   const cpx<T>* src = (!INV && a.Sin) ? a.Sin + l * a.lstrideC + ((long long)(c * a.nz + z) * a.ny) * M + s0 : base;
-  for (int e = tid; e < N * TX; e += NTY) {
-    const int y = e / TX, s = e - y * TX;
-    buf[e] = (s0 + s < M) ? src[(long long)y * M + s] : cpx<T>{T(0), T(0)};
+  // all of a thread's loads before the first LDS store (see the z pass)
+  {
+    constexpr int PER = (N * TX + NTY - 1) / NTY;
+    cpx<T> v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTY;
+      const int y = e / TX, s = e - y * TX;
+      v[q] = (e < N * TX && s0 + s < M) ? src[(long long)y * M + s] : cpx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTY;
+      if (e < N * TX) buf[e] = v[q];
+    }
   }
   __syncthreads();
   if (INV && s0 == 0) {
@@ -552,14 +601,29 @@ __global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
   cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
   const long long cstride = (long long)a.nz * a.zsS;      // component
   const long long zstride = a.zsS;                        // z plane (padded)
-  for (int e = tid; e < N * NC; e += NTH) {
-    const int z = e / NC, rem = e - z * NC;
-    const int c = rem / TX, s = rem - c * TX;
-    buf[e] = (s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
+  // all of a thread's loads are issued before the first LDS store (a
+  // strided loop that stores each value as it arrives waits out one memory
+  // latency per element)
+  constexpr int PER = (N * NC + NTH - 1) / NTH;
+  {
+    cpx<T> v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTH;
+      const int z = e / NC, rem = e - z * NC;
+      const int c = rem / TX, s = rem - c * TX;
+      v[q] = (e < N * NC && s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTH;
+      if (e < N * NC) buf[e] = v[q];
+    }
   }
   __syncthreads();
   double acc = 0.0;
   zpass_tile<T, N, TX, RP, NTH>(a, l, y, s0, buf, tws, acc);
+  // (a plain loop: unrolled, its addresses would stay live through the FFT)
   for (int e = tid; e < N * NC; e += NTH) {
     const int z = e / NC, rem = e - z * NC;
     const int c = rem / TX, s = rem - c * TX;
