@@ -504,18 +504,41 @@ __device__ __forceinline__ void zpass_tile(const PArgs<T>& a, int l, int y, int 
   fft_lds<T, N, false, NC, NTH, 1, ColTile<NC>, RP>(buf, tws);
   const bool pair_row = (s0 == 0) && (y == 0 || y == a.ny / 2);
   // ordinary wavevectors (weight 2: each stands for itself and its conjugate)
-  for (int e = tid; e < N * TX; e += NTH) {
+  constexpr int QS = (N * TX + NTH - 1) / NTH;
+  if (a.tab) {
+    // all of a thread's table entries are loaded before the first use
+    const T* tab = a.tab + (long long)(l / a.lpc) * a.tab_stride;
+    T m[QS][6];
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int e = tid + q * NTH;
+      const int kz = e / TX, s = e - kz * TX;
+      const int slot = s0 + s;
+      if (e < N * TX && slot < M) sym_load(tab, ((long long)y * a.nz + kz) * M + slot, m[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+      const int e = tid + q * NTH;
+      const int kz = e / TX, s = e - kz * TX;
+      const int slot = s0 + s;
+      if (e >= N * TX || slot >= M || (slot == 0 && pair_row)) continue;
+      cpx<T> r[3], z[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c] = buf[kz * NC + c * TX + s];
+      sym_apply3(m[q], r, z);
+      acc += 2.0 * (double)redot<T, 3>(r, z);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) buf[kz * NC + c * TX + s] = z[c];
+    }
+  }
+  for (int e = tid; e < N * TX && !a.tab; e += NTH) {
     const int kz = e / TX, s = e - kz * TX;
     const int slot = s0 + s;
     if (slot >= M || (slot == 0 && pair_row)) continue;
     cpx<T> r[3], z[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = buf[kz * NC + c * TX + s];
-    if (a.tab) {
-      T m[6];
-      sym_load(a.tab + (long long)(l / a.lpc) * a.tab_stride, ((long long)y * a.nz + kz) * M + slot, m);
-      sym_apply3(m, r, z);
-    } else {
+    {
       const int kx = slot == 0 ? (y < a.ny / 2 ? 0 : M) : slot;
       sym_solve3(a, kx, y, kz, r, z);
     }
