@@ -38,8 +38,16 @@ sample lattice); every grid size is at least 3 (i + delta != i - delta).
 The load vectors stay exact, and the effective stiffness of a surrogate
 solution u~ is the energy form of the exact material law on its strain
 field (``fem.homogenize``), which exceeds C* by (u~ - u).K(u~ - u)/|Y|.
+
+For grids too large to assemble, ``stencil_blocks_at``, ``evaluate_at`` and
+``apply_at`` compute the same quantities at chosen nodes only: the stencil
+blocks from the element matrices of the simplices holding both nodes, the
+interpolants from the same coefficients, and rows of Kt p from their
+definition above.
 """
 from __future__ import annotations
+
+import itertools
 
 import numpy as np
 import scipy.sparse as sp
@@ -214,3 +222,122 @@ def effective_stiffness(grid, E, nu, M, q):
     Kt = surrogate_matrix(grid, St)
     u, _ = solve(grid, E, nu, eb, Kt)
     return fem.homogenize(grid, E, nu, u, eb)["C_energy"], u
+
+
+# --------------------------------------------------------------------------
+# the same quantities at chosen nodes (grids too large to assemble)
+# --------------------------------------------------------------------------
+
+
+def node_multi_index(grid, nodes):
+    """(i_x, i_y[, i_z]) of flat node indices."""
+    idx = np.asarray(nodes, dtype=np.int64)
+    out = []
+    for N in grid.shape:
+        out.append(idx % N)
+        idx = idx // N
+    return out
+
+
+def stencil_blocks_at(grid, lam, mu, nodes):
+    """K_delta(x_i) = K[i, i + delta] for chosen nodes: (len(nodes), noff, d, d).
+
+    Node i and node i + delta share a simplex exactly where they are vertices
+    j < k of it with V_k - V_j = delta (the vertices of a Kuhn simplex follow
+    a monotone path); the block entry (a, b) collects |s| (lam B^T m m^T B +
+    mu B^T S B) at rows (a, vertex j), columns (b, vertex k) over those
+    simplices, with the (lam, mu) of the voxel at i - V_j.  lam, mu: per voxel
+    (n,)."""
+    d = grid.d
+    offs = [tuple(o) for o in offsets(d)]
+    comps = node_multi_index(grid, nodes)
+    m = fem.voigt_m(d)
+    S = np.diag(fem.voigt_s(d))
+    nv1 = d + 1
+    out = np.zeros((len(comps[0]), len(offs), d, d))
+    for V, vol, B in fem.element_data(grid):
+        Kl = vol * (B.T @ np.outer(m, m) @ B)
+        Km = vol * (B.T @ S @ B)
+        for j in range(nv1):
+            vflat = grid.flat([comps[a] - V[j, a] for a in range(d)])
+            lv, mv = lam[vflat], mu[vflat]
+            for k in range(j + 1, nv1):
+                di = offs.index(tuple(int(x) for x in V[k] - V[j]))
+                for a in range(d):
+                    for b in range(d):
+                        out[:, di, a, b] += lv * Kl[a * nv1 + j, b * nv1 + k] + mv * Km[a * nv1 + j, b * nv1 + k]
+    return out
+
+
+def evaluate_at(coef, q, M, fine_shape, nodes_multi):
+    """The B-spline of ``evaluate`` at chosen fine nodes only.  coef: (..., coarse
+    lattice in (z, y, x) order); nodes_multi: (i_x, i_y[, i_z]) arrays.
+    Returns (len(nodes), ...)."""
+    d = len(fine_shape)
+    lead = coef.shape[:-d]
+    coarse = coef.shape[len(lead):]           # (z, y, x)
+    n_nodes = len(nodes_multi[0])
+    out = np.zeros((n_nodes,) + lead)
+    for t in range(n_nodes):
+        # per axis in (z, y, x) order: lattice indices and weights
+        taps = []
+        for ax in range(d):
+            i = int(nodes_multi[d - 1 - ax][t])
+            Nc = coarse[ax]
+            x = i / M
+            js = range(int(np.floor(x)) - 2, int(np.floor(x)) + 3)
+            taps.append([(j % Nc, bspline(q, x - j)) for j in js if bspline(q, x - j) != 0.0])
+        val = np.zeros(lead)
+        for combo in itertools.product(*taps):
+            w = 1.0
+            for _, wa in combo:
+                w *= wa
+            val = val + w * coef[(Ellipsis,) + tuple(j for j, _ in combo)]
+        out[t] = val
+    return out
+
+
+def surrogate_blocks_at(grid, E, nu, M, q, nodes):
+    """Kt_delta(x_i) at chosen nodes: stencil blocks sampled on the lattice of
+    every M-th node, their interpolation coefficients, the interpolant at the
+    nodes.  Returns (len(nodes), noff, d, d)."""
+    if any(N % M for N in grid.shape):
+        raise ValueError("M must divide every grid size")
+    lam, mu = fem.lame(np.ravel(E), np.ravel(nu))
+    d = grid.d
+    cshape = tuple(N // M for N in grid.shape)                       # (x, y[, z])
+    cgrid = np.meshgrid(*[np.arange(Nc) * M for Nc in reversed(cshape)], indexing="ij")  # (z, y, x)
+    cm = [cgrid[d - 1 - a].ravel() for a in range(d)]                # i_x, i_y[, i_z]
+    cflat = grid.flat(cm)
+    Sc = stencil_blocks_at(grid, lam, mu, cflat)                     # (nc, noff, d, d)
+    samp = np.moveaxis(Sc, 0, -1).reshape(Sc.shape[1:] + tuple(reversed(cshape)))
+    coef = interpolation_coefficients(samp, q, d)
+    return evaluate_at(coef, q, M, grid.nshape, node_multi_index(grid, nodes))
+
+
+def apply_at(grid, E, nu, M, q, p, nodes):
+    """Rows of Kt p at chosen nodes (the matrix of ``surrogate_matrix``):
+    (Kt p)_i = sum_delta [Kt_delta(x_i) p_{i+delta} + Kt_delta(x_{i-delta})^T p_{i-delta}]
+               - sym(R_i) p_i,  R_i = sum_delta [Kt_delta(x_i) + Kt_delta(x_{i-delta})^T].
+    p: (d n,) component-major.  Returns (len(nodes), d)."""
+    d, n = grid.d, grid.n
+    offs = offsets(d)
+    nodes = np.asarray(nodes, dtype=np.int64)
+    mi = node_multi_index(grid, nodes)
+    minus = [grid.flat([mi[a] - o[a] for a in range(d)]) for o in offs]
+    plus = [grid.flat([mi[a] + o[a] for a in range(d)]) for o in offs]
+    allnodes = np.concatenate([nodes] + minus)
+    blocks = surrogate_blocks_at(grid, E, nu, M, q, allnodes)
+    nn = len(nodes)
+    A = blocks[:nn]                                                  # Kt_delta(x_i)
+    P = p.reshape(d, n)
+    out = np.zeros((nn, d))
+    R = np.zeros((nn, d, d))
+    for k in range(len(offs)):
+        Bm = blocks[nn * (k + 1):nn * (k + 2), k]                    # Kt_delta(x_{i-delta})
+        out += np.einsum("tab,bt->ta", A[:, k], P[:, plus[k]])
+        out += np.einsum("tba,bt->ta", Bm, P[:, minus[k]])
+        R += A[:, k] + np.transpose(Bm, (0, 2, 1))
+    Rs = 0.5 * (R + np.transpose(R, (0, 2, 1)))
+    out -= np.einsum("tab,bt->ta", Rs, P[:, nodes])
+    return out

@@ -1,7 +1,8 @@
 """Surrogate stencil operator on the GPU against the oracle: the
 interpolated stencil blocks, the operator, the constrained surrogate
-solution and its C*, M = 1 and homogeneous material against the exact
-path, the consistency error on a smooth field, and the error paths.
+solution and its C*, fewer load slots, sampled operator rows at the full
+256^3 bench size, M = 1 and homogeneous material against the exact path,
+the consistency error on a smooth field, and the error paths.
 
 Tolerances: stencil blocks and the FP64 operator 1e-12 (the same sums in a
 different order); FP32 operator 2e-5 (as the exact FP32 operator); C* of
@@ -141,6 +142,31 @@ def test_consistency_error_64(lib):
             c.set_surrogate(0, 1)
             assert all(a > b for a, b in zip(errs[:-1], errs[1:])), errs
             assert errs[-1] < 1e-3
+
+
+def test_full_size_sampled_rows(lib):
+    """The 256^3 bench configuration (log-normal E, sigma 1, correlation
+    length 32 voxels, seed 7; M 4, cubic): rows of the surrogate operator at
+    40 nodes (box corners and tile edges among them) against the oracle's
+    per-node evaluation.  FP32 operator (one wavefront per row) within 2e-5,
+    FP64 operator within 1e-11 of the largest sampled value; p is FP32-exact
+    so that both see the same direction."""
+    from paper_2004_05197_amd import microstructures as ms
+    n = 256
+    E, nu = ms.lognormal_field(n, 7, ell=32.0, sigma=1.0)
+    g = fem.Grid((n, n, n))
+    rng = np.random.default_rng(3)
+    p = rng.standard_normal(3 * g.n).astype(np.float32).astype(np.float64)
+    special = [(0, 0, 0), (255, 255, 255), (0, 255, 128), (255, 0, 0), (63, 3, 17), (64, 4, 200), (127, 0, 255),
+               (128, 255, 1), (191, 100, 0), (192, 7, 254)]
+    nodes = np.array([x + n * (y + n * z) for x, y, z in special] + list(rng.choice(g.n, size=30, replace=False)))
+    ref = sg.apply_at(g, E, nu, 4, 3, p, nodes)
+    with lib.Cell((n, n, n), precision=lib.MIXED) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        c.set_surrogate(4, 3)
+        for prec, tol in ((lib.MIXED, 2e-5), (lib.FP64, 1e-11)):
+            q = c.apply_operator(p, precision=prec).reshape(3, g.n)[:, nodes].T
+            assert relerr(q, ref) < tol, (prec, relerr(q, ref))
 
 
 def test_surrogate_errors(lib):

@@ -2,7 +2,9 @@
 against scipy's periodic splines and numpy's periodic linear interpolation,
 M = 1 and homogeneous material reproduce K exactly, symmetry, the translation
 kernel where the stencil blocks are symmetric, the energy-form upper bound
-C~* - C* >= 0 with its quadratic size, and convergence as M decreases."""
+C~* - C* >= 0 with its quadratic size, convergence as M decreases, and the
+per-node versions (stencil blocks from element matrices, interpolants and
+rows of Kt p at chosen nodes) against the assembled sparse matrices."""
 import numpy as np
 import pytest
 from scipy.interpolate import make_interp_spline
@@ -115,3 +117,27 @@ def test_consistency_error(shape, Ms, q):
         errs.append(abs(dC).max() / abs(C).max())
     assert errs[-1] < 1e-13
     assert all(a > b for a, b in zip(errs[:-1], errs[1:]))
+
+
+@pytest.mark.parametrize("shape,M,q,lengths", [((6, 4, 4), 2, 3, None), ((8, 4, 6), 2, 1, (1.0, 0.8, 1.3)),
+                                                ((4, 6, 4), 1, 3, None), ((6, 6), 3, 3, None)])
+def test_per_node_versions_match_assembly(shape, M, q, lengths):
+    """stencil_blocks_at against K read off the assembled matrix, and
+    surrogate_blocks_at / apply_at against surrogate_stencils /
+    surrogate_matrix @ p (sparse assembly) at random nodes."""
+    rng = np.random.default_rng(11)
+    g = fem.Grid(shape, lengths=lengths)
+    E = rng.uniform(1, 3, g.nshape)
+    nu = rng.uniform(0.2, 0.35, g.nshape)
+    lam, mu = fem.lame(E.ravel(), nu.ravel())
+    K = fem.assemble_K(g, E, nu)
+    Sf = sg.stencil_functions(g, K)
+    Sa = sg.stencil_blocks_at(g, lam, mu, np.arange(g.n))
+    assert np.abs(np.moveaxis(Sa, 0, -1) - Sf).max() < 1e-14 * np.abs(Sf).max()
+    St = sg.surrogate_stencils(g, E, nu, M, q, K=K)
+    nodes = rng.choice(g.n, size=10, replace=False)
+    Sb = sg.surrogate_blocks_at(g, E, nu, M, q, nodes)
+    assert np.abs(np.moveaxis(Sb, 0, -1) - St[..., nodes]).max() < 1e-14 * np.abs(St).max()
+    p = rng.standard_normal(g.d * g.n)
+    ref = (sg.surrogate_matrix(g, St) @ p).reshape(g.d, g.n)[:, nodes].T
+    assert np.abs(sg.apply_at(g, E, nu, M, q, p, nodes) - ref).max() < 1e-14 * np.abs(ref).max()
