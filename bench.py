@@ -80,7 +80,7 @@ def measured_traffic(kind, workload):
     return round(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
 
 
-def cpu_baseline(E, nu, sub=128, iters=3):
+def cpu_baseline(E, nu, sub=128, iters=6):
     from oracle import fem, matfree
     Es = np.ascontiguousarray(E[:sub, :sub, :sub])
     nus = np.ascontiguousarray(nu[:sub, :sub, :sub])
@@ -196,7 +196,7 @@ def hyper_loads(d=3, amp=0.05):
     return F
 
 
-def cpu_baseline_hyper(E, nu, Fb, sub=16):
+def cpu_baseline_hyper(E, nu, Fb, sub=18):
     from oracle import fem, hyper
     Es = np.ascontiguousarray(E[:sub, :sub, :sub])
     nus = np.ascontiguousarray(nu[:sub, :sub, :sub])
@@ -299,8 +299,9 @@ def bench_hyper(args, B, ms, progress):
     }
 
 
-def cpu_baseline_surrogate(E, nu, M, sub=12):
+def cpu_baseline_surrogate(E, nu, M, sub=16):
     from oracle import fem, surrogate as sg
+    sub = M * max(1, sub // M)  # the sampling step divides the sub-block
     Es = np.ascontiguousarray(E[:sub, :sub, :sub])
     nus = np.ascontiguousarray(nu[:sub, :sub, :sub])
     g = fem.Grid((sub, sub, sub))
@@ -318,7 +319,7 @@ def cpu_baseline_surrogate(E, nu, M, sub=12):
     }
 
 
-def cpu_baseline_adjoint(E, nu, sub=16):
+def cpu_baseline_adjoint(E, nu, sub=18):
     from oracle import fem
     Es = np.ascontiguousarray(E[:sub, :sub, :sub])
     nus = np.ascontiguousarray(nu[:sub, :sub, :sub])
