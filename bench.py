@@ -515,8 +515,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the cell solve is not sharded "
-              "across GPUs); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the cell solve runs on one GPU (it is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
