@@ -20,7 +20,7 @@ Besides the headline line it reports (same JSON object):
     mixed over FP64) and the normwise C* error of both against an FP64
     solve at tol 1e-10;
   * cpu_baseline: the CPU oracle (numpy/scipy FP64) timed on this host on a
-    bounded sample: 3 PCG iterations on one load of a 128^3 periodic
+    bounded sample: 6 PCG iterations on one load of a 128^3 periodic
     sub-block of the same field.
 """
 import argparse
