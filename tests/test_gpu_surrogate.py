@@ -169,6 +169,28 @@ def test_full_size_sampled_rows(lib):
             assert relerr(q, ref) < tol, (prec, relerr(q, ref))
 
 
+@pytest.mark.parametrize("shape,M,q,lengths", [((192, 8, 6), 2, 3, None), ((128, 4, 12), 4, 1, (1.3, 0.9, 1.0))])
+def test_sampled_rows_wide_grids(lib, shape, M, q, lengths):
+    """Grids of 2 and 3 wavefront-wide tiles per row (the FP32 operator with
+    one wavefront per row, tile seams at x = 63/64 and 127/128) and a
+    stretched cell: 60 sampled rows of the surrogate operator against the
+    oracle's per-node evaluation, FP32 2e-5 and FP64 1e-11 of the largest."""
+    g, E, nu = case_data(shape, lengths, seed=4)
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(3 * g.n).astype(np.float32).astype(np.float64)
+    nx, ny, nz = shape
+    seams = [(x, y, z) for x in (0, 63, 64, 127, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1) if x < nx]
+    nodes = np.array([x + nx * (y + ny * z) for x, y, z in seams] + list(rng.choice(g.n, size=60 - len(seams),
+                                                                                    replace=False)))
+    ref = sg.apply_at(g, E, nu, M, q, p, nodes)
+    with lib.Cell(shape, precision=lib.MIXED, lengths=g.L) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        c.set_surrogate(M, q)
+        for prec, tol in ((lib.MIXED, 2e-5), (lib.FP64, 1e-11)):
+            got = c.apply_operator(p, precision=prec).reshape(3, g.n)[:, nodes].T
+            assert relerr(got, ref) < tol, (prec, relerr(got, ref))
+
+
 def test_surrogate_errors(lib):
     with lib.Cell((8, 8)) as c:
         c.set_material(np.full(64, 2.0), np.full(64, 0.3))
