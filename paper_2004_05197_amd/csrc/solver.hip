@@ -1543,9 +1543,14 @@ cell_status instance_get_surrogate(cell_s* c, double* out) {
   std::vector<double> buf(sr_len(n));
   HIPCHK(hipMemcpyAsync(buf.data(), c->sr64, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  // chunked device layout -> [value][node]
-  for (long long i = 0; i < n; ++i)
-    for (int v = 0; v < SR_NVAL; ++v) out[(long long)v * n + i] = buf[sr_chunk(i) + (long long)v * SR_CHUNK];
+  // chunked device layout -> [value][node]: each chunk holds a run of up to
+  // SR_CHUNK consecutive nodes per value
+  for (long long i0 = 0; i0 < n; i0 += SR_CHUNK) {
+    const long long len = std::min<long long>(SR_CHUNK, n - i0);
+    const double* src = buf.data() + sr_chunk(i0);
+    for (int v = 0; v < SR_NVAL; ++v)
+      std::copy(src + (long long)v * SR_CHUNK, src + (long long)v * SR_CHUNK + len, out + (long long)v * n + i0);
+  }
   return CELL_OK;
 }
 
