@@ -230,6 +230,7 @@ cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int o
   if (!c || !dJ_dC || !dJ_dE_out) return fail(CELL_E_ARG, "null argument");
   if (c->sr_M > 0) return fail(CELL_E_STATE, "the adjoint needs the exact operator (a surrogate stencil operator is set)");
   if (!c->solved_unit) return fail(CELL_E_STATE, "cell_adjoint needs a preceding cell_effective_stiffness");
+  if (c->solved_op != 0) return fail(CELL_E_STATE, "the last solve did not use the exact operator");
   DevGuard dg(c->dev);
   const int nv = c->nv;
   HArgs h{};

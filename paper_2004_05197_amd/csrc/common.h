@@ -58,26 +58,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// Thread 0 of each block calls this after storing its partial.  Returns true
-// in exactly one block (the last to arrive).  Release/acquire at agent scope
-// makes every block's partial visible to the finalising block across XCDs.
-__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned nblocks) {
-  __threadfence();
-  unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-  return prev == nblocks - 1;
-}
-
-// Fixed-order sum of nparts partials by the whole (finalising) block.
-// Call only in the finalising block, after a barrier that follows
-// arrive_last; every thread takes an agent-scope acquire before reading.
-template <int NT>
-__device__ __forceinline__ double sum_partials(const double* parts, int nparts, double* sh) {
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += NT) v += parts[i];
-  return block_sum<NT>(v, sh);
-}
-
 // ---------------------------------------------------------------- XCD order
 // Workgroups of a launch are dealt round-robin to the 8 XCDs (each with its
 // own L2).  xcd_order maps the hardware block id so that every XCD receives

@@ -11,17 +11,14 @@ namespace cellfft {
 
 constexpr int NT = 256;  // threads per block of every kernel
 
-// Reduction plumbing: partials[slot][load][blk], counters[slot][load]
+// Reduction plumbing: per-block partials[slot][load][blk], summed in fixed
+// order by a finalize kernel
 struct RedBuf {
   double* parts;
-  unsigned* cnt;
   int maxblk;
   int maxload;
   __host__ __device__ double* slot_parts(int slot, int load) const {
     return parts + ((long long)slot * maxload + load) * maxblk;
-  }
-  __host__ __device__ unsigned* slot_cnt(int slot, int load) const {
-    return cnt + slot * maxload + load;
   }
 };
 
@@ -141,6 +138,7 @@ template <typename T> struct KArgs {
                         // block's own voxels, [load][6][maxblk] (tensor storage
                         // 00,11,22,12,02,01); nullptr = not accumulated
   double* sbar;         // mode 1 (optional): [load][6] finalised stress sums
+  int negate;           // mode 0, debugging only: 1 writes -K u (forces a CG breakdown)
   RedBuf red;
 };
 

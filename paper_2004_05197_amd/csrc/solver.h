@@ -49,6 +49,7 @@ struct cell_s {
   int ncell = 1;  // cells of this grid
   int nslot = 6;  // ncell * lpc
   bool use_graphs = true;
+  int dbg_negate_q = 0;     // CELLFFT_DEBUG_NEGATE_Q=1: the linear K-apply writes -K p
   cellfft::Sched sched{};  // kernel variants (autotuner)
   bool tuned = false;
   // material, per cell
@@ -64,7 +65,6 @@ struct cell_s {
   cellfft::LoadState* st = nullptr;
   cellfft::LoadState* st_h = nullptr;
   double* parts = nullptr;
-  unsigned* cnt = nullptr;
   int maxblk = 0;
   double* res2 = nullptr;
   double* res2_h = nullptr;
@@ -107,6 +107,7 @@ struct cell_s {
   double eps_v[6][6] = {};
   bool solved = false;
   bool solved_unit = false;
+  int solved_op = 0;          // operator of the last solve (op values above)
   std::vector<double> homog;  // [ncell][nval] from the last solve
   // per-kernel event timing
   bool prof = false;

@@ -75,7 +75,7 @@ double now_s() {
 
 namespace {
 
-RedBuf red_of(cell_s* c) { return RedBuf{c->parts, c->cnt, c->maxblk, c->nslot}; }
+RedBuf red_of(cell_s* c) { return RedBuf{c->parts, c->maxblk, c->nslot}; }
 
 template <typename T> Fields<T>& fields(cell_s* c);
 template <> Fields<float>& fields<float>(cell_s* c) { return c->f32; }
@@ -228,6 +228,7 @@ KArgs<T> kargs(cell_s* c, int mode, const T* u, void* out, const T* mat) {
   a.res2 = c->res2;
   a.sparts = nullptr;
   a.sbar = nullptr;
+  a.negate = c->dbg_negate_q;
   a.red = red_of(c);
   return a;
 }
@@ -787,7 +788,6 @@ void instance_destroy(cell_s* c) {
   fr(c->x64);
   fr(c->st);
   fr(c->parts);
-  fr(c->cnt);
   fr(c->res2);
   fr(c->sparts);
   fr(c->sbar);
@@ -879,6 +879,10 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
   c->nslot = ncell * c->lpc;
   const char* ge = std::getenv("CELLFFT_GRAPHS");
   c->use_graphs = !(ge && ge[0] == '0');
+  // debugging aid for the failure path: the linear K-apply returns -K p, so
+  // the first p.Kp is negative and every solve ends in CELL_E_BREAKDOWN
+  const char* nq = std::getenv("CELLFFT_DEBUG_NEGATE_Q");
+  c->dbg_negate_q = (nq && nq[0] == '1') ? 1 : 0;
   c->have_mat.assign(ncell, 0);
   c->lam0.assign(ncell, 0.0);
   c->mu0.assign(ncell, 0.0);
@@ -902,7 +906,6 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
   const int ns = c->nslot;
   auto dmalloc = [&](void** p, size_t bytes) -> bool { return hipMalloc(p, bytes) == hipSuccess; };
   if (!dmalloc((void**)&c->parts, sizeof(double) * (size_t)RED_NSLOT * ns * mb) ||
-      !dmalloc((void**)&c->cnt, sizeof(unsigned) * RED_NSLOT * ns) ||
       !dmalloc((void**)&c->st, sizeof(LoadState) * ns) || !dmalloc((void**)&c->res2, sizeof(double) * ns) ||
       !dmalloc((void**)&c->sparts, sizeof(double) * 6 * (size_t)ns * mb) ||
       !dmalloc((void**)&c->sbar, sizeof(double) * 6 * ns) || !dmalloc((void**)&c->mask, sizeof(int) * ns) ||
@@ -923,8 +926,7 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
       hipHostMalloc((void**)&c->mask_h, sizeof(int) * ns) != hipSuccess)
     return bail(fail(CELL_E_NOMEM, "pinned host allocation failed"));
   c->negcurv.assign(ns, 0);
-  if (hipMemset(c->cnt, 0, sizeof(unsigned) * RED_NSLOT * ns) != hipSuccess ||
-      hipMemset(c->st, 0, sizeof(LoadState) * ns) != hipSuccess ||
+  if (hipMemset(c->st, 0, sizeof(LoadState) * ns) != hipSuccess ||
       hipMemset(c->mask, 0, sizeof(int) * ns) != hipSuccess)
     return bail(fail(CELL_E_DEVICE, "hipMemset failed"));
   cell_status st = c->precision == CELL_MIXED ? ensure_fields<float>(c) : ensure_fields<double>(c);
@@ -1029,6 +1031,7 @@ cell_status solve_end(SolveRun& R) {
     c->linear_results = true;
   }
   c->solved = true;
+  c->solved_op = c->op;
   c->nload_solved = R.nload;
   return st;
 }
@@ -1368,6 +1371,7 @@ cell_status hyper_run(cell_s* c, int nload, const double* Fb, double tol, int ma
   HIPCHK(launch_copy_slots(c->hy_u, sol, len, ns, nullptr, s));
   HIPCHK(hipStreamSynchronize(s));
   c->solved = true;
+  c->solved_op = 1;
   c->nload_solved = nload;
   bool conv = true;
   for (int l = 0; l < ns; ++l)
@@ -1434,6 +1438,9 @@ void cubic_line(double* v, long long stride, int n, std::vector<double>& y, std:
 
 cell_status instance_set_surrogate(cell_s* c, int M, int q) {
   if (M == 0) {
+    // results of a surrogate solve are not those of the exact operator:
+    // drop them so that no getter or the adjoint reports them as exact
+    if (c->sr_M > 0) c->solved = c->solved_unit = c->linear_results = false;
     c->sr_M = 0;
     if (c->op == 2) c->op = 0;
     return CELL_OK;

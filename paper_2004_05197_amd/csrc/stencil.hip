@@ -192,7 +192,7 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
   const int x0 = blockIdx.x * bx, y0 = blockIdx.y * by, z0 = blockIdx.z * tz;
   const T ih[3] = {(T)(1.0 / a.g.h[0]), (T)(1.0 / a.g.h[1]), (T)(1.0 / a.g.h[2])};
   const double wd = a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0;
-  const T w = (T)(UNI ? wd / (a.g.h[0] * a.g.h[0]) : wd);
+  const T w = (T)((UNI ? wd / (a.g.h[0] * a.g.h[0]) : wd) * (MODE == 0 && a.negate ? -1.0 : 1.0));
   const T msc = (T)(UNI ? a.g.h[0] : 1.0);  // macro stress scale relative to lw, mw
   const int nextra = bx + by + 1;
   const bool has_extra = tid < nextra;
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
   const int x0 = bxi * BX, y0 = byi * BY, z0 = bzi * tz;
   const T ih[3] = {(T)(1.0 / a.g.h[0]), (T)(1.0 / a.g.h[1]), (T)(1.0 / a.g.h[2])};
   const double wd = a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0;
-  const T w = (T)(UNI ? wd / (a.g.h[0] * a.g.h[0]) : wd);
+  const T w = (T)((UNI ? wd / (a.g.h[0] * a.g.h[0]) : wd) * (MODE == 0 && a.negate ? -1.0 : 1.0));
   const T msc = (T)(UNI ? a.g.h[0] : 1.0);
   const bool has_extra = tid < NEXTRA;
   const int ex = tid < BY ? BX - 1 : tid - BY - 1;
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   const int nx = a.g.nx, ny = a.g.ny;
   const long long n = a.g.n;
   const T ih[2] = {(T)(1.0 / a.g.h[0]), (T)(1.0 / a.g.h[1])};
-  const T w = (T)(a.g.h[0] * a.g.h[1] / 2.0);
+  const T w = (T)(a.g.h[0] * a.g.h[1] / 2.0 * (MODE == 0 && a.negate ? -1.0 : 1.0));
   const T* u = a.u ? a.u + l * a.lstride : nullptr;
   TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
   const double* eb = a.eps[l % a.lpc];

@@ -1,0 +1,112 @@
+"""Parity of the kernels the 256^3 workloads run, at their own FFT lengths
+and tile shapes, against the oracle.
+
+* Preconditioner: every FFT variant a schedule can select (x-pass rows and
+  radix order, y-pass columns, last-pass columns x threads and radix order)
+  on grids whose axes reach the long codelets: the x pass transforms
+  N_x / 2 complex points (64, 96, 128 here), the y and z passes N_y and N_z
+  points (128, 192, 256), 2D the last pass along y (128, 256).  Reference:
+  the oracle's Fourier preconditioner, whose symbol is the DFT of the
+  assembled homogeneous operator's impulse response (the circulant
+  structure of constant stencil functions, Sec. 3.2, eq. KeyIdentity), with
+  numpy's real FFT.
+* Operator: the uniform-h stencil kernels (equal edge lengths, where 1/h^2
+  is folded into the material weights) at every compiled tile and z extent
+  on a 64^3 unit cell, and the bench configuration's tile (32 x 8 nodes,
+  z extent 64) on a 256 x 256 x 16 grid with h = 1/256 and the two-phase
+  1:1000 material recipe, against the oracle's matrix-free K u (the linear
+  law of Sec. 2.2, eq. LinearElastEnergy).
+
+Tolerances (relative, max-norm) as in the single-step parity tests: operator
+FP64 1e-12, FP32 2e-5; preconditioner FP64 1e-10, FP32 1e-4.
+"""
+import numpy as np
+import pytest
+
+from oracle import fem, matfree
+from paper_2004_05197_amd import microstructures as ms
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def rand_material(shape, seed, Emin=1.0, Emax=10.0):
+    rng = np.random.default_rng(seed)
+    nshape = tuple(reversed(shape))
+    return rng.uniform(Emin, Emax, nshape), rng.uniform(0.05, 0.45, nshape)
+
+
+FFT_VARIANTS = [(x, y, z, rp) for x in (0, 1, 2, 3) for y in (0, 1, 2, 3) for z in (0, 1, 2, 3) for rp in (0, 1)]
+# 2D: the y pass is absent and the last pass has two variants (z & 1)
+FFT_VARIANTS_2D = [(x, 0, z, rp) for x in (0, 1, 2, 3) for z in (0, 1) for rp in (0, 1)]
+
+# (grid, lengths): x pass 128 / 4 / 96 / 64 complex points, y 8 / 256 / 192 /
+# 16, z 256 / 128 / 8 / 192; 2D last pass 256 / 128
+FFT_GRIDS = [((256, 8, 256), None), ((8, 256, 128), None), ((192, 192, 8), (1.0, 1.0, 0.25)),
+             ((128, 16, 192), None), ((256, 256), None), ((192, 128), (1.0, 0.8))]
+
+
+@pytest.mark.parametrize("shape,lengths", FFT_GRIDS)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-4)])
+def test_preconditioner_long_codelets_every_variant(lib, shape, lengths, prec, tol):
+    E, nu = rand_material(shape, 3, 1.0, 50.0)
+    grid = fem.Grid(shape, lengths=lengths)
+    r = np.random.default_rng(4).standard_normal((grid.d,) + grid.nshape)
+    r -= r.reshape(grid.d, -1).mean(axis=1).reshape((grid.d,) + (1,) * grid.d)
+    variants = FFT_VARIANTS if grid.d == 3 else FFT_VARIANTS_2D
+    with lib.Cell(shape, precision=prec, lengths=grid.L) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        zref = matfree.FourierPreconditioner(grid, *c.reference_medium())(r).ravel()
+        errs = {}
+        for x, y, z, rp in variants:
+            c.schedule = (0, 32, x, y, z, rp)
+            zz = c.apply_preconditioner(r.ravel(), precision=prec)
+            errs[(x, y, z, rp)] = relerr(zz, zref)
+    worst = max(errs, key=errs.get)
+    assert errs[worst] < tol, (worst, errs[worst])
+
+
+@pytest.fixture(scope="module")
+def unit64():
+    shape = (64, 64, 64)
+    E, nu = rand_material(shape, 1)
+    grid = fem.Grid(shape)
+    lam, mu = fem.lame(E, nu)
+    u = np.random.default_rng(2).standard_normal((3,) + grid.nshape)
+    return shape, E, nu, u, matfree.apply_K(grid, lam, mu, u).ravel()
+
+
+@pytest.mark.parametrize("tile", range(5))
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+def test_uniform_h_operator_every_tile(lib, unit64, tile, prec, tol):
+    shape, E, nu, u, ref = unit64
+    with lib.Cell(shape, precision=prec) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        for tz in (8, 16, 32, 64):
+            c.schedule = (tile, tz, 0, 0, 0, 0)
+            assert c.schedule == (tile, tz, 0, 0, 0, 0)
+            q = c.apply_operator(u.ravel(), precision=prec)
+            assert relerr(q, ref) < tol, tz
+
+
+@pytest.mark.parametrize("prec,tol,tile", [(0, 1e-12, 0), (1, 2e-5, 1)])
+def test_uniform_h_operator_bench_tile(lib, prec, tol, tile):
+    """FP32 tile 1 and FP64 tile 0 are both 32 x 8 nodes; the z extent 64
+    is larger than nz = 16, so one ragged z tile covers the grid."""
+    shape = (256, 256, 16)
+    g = ms.gaussian_random_field(shape, 8.0, 3)
+    E = np.where(g >= 0.0, 1000.0, 1.0)
+    nu = np.where(g >= 0.0, 0.35, 0.25)
+    grid = fem.Grid(shape, lengths=(1.0, 1.0, 1.0 / 16.0))
+    assert grid.h[0] == grid.h[1] == grid.h[2]
+    lam, mu = fem.lame(E, nu)
+    u = np.random.default_rng(5).standard_normal((3,) + grid.nshape)
+    ref = matfree.apply_K(grid, lam, mu, u).ravel()
+    with lib.Cell(shape, precision=prec, lengths=grid.L) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        c.schedule = (tile, 64, 0, 0, 0, 0)
+        q = c.apply_operator(u.ravel(), precision=prec)
+    assert relerr(q, ref) < tol

@@ -216,3 +216,29 @@ def test_surrogate_errors(lib):
         with pytest.raises(lib.CellError) as e:
             c.surrogate_stencil()
         assert e.value.status == lib.CELL_E_STATE
+
+
+def test_surrogate_off_drops_its_results(lib):
+    """Switching the surrogate operator off (M = 0) after a surrogate solve
+    leaves no result that could pass for the exact operator's: the adjoint,
+    the displacement, residual and energy-matrix getters report CELL_E_STATE
+    until the next exact solve, whose adjoint then works."""
+    rng = np.random.default_rng(12)
+    E = np.exp(0.3 * rng.standard_normal(512))
+    nu = np.full(512, 0.3)
+    with lib.Cell((8, 8, 8), precision=lib.FP64, tol=1e-10) as c:
+        c.set_material(E, nu)
+        c.set_surrogate(2, 3)
+        c.effective_stiffness()
+        c.set_surrogate(0)
+        for call in (lambda: c.adjoint(np.eye(6)), lambda: c.displacement(0), lambda: c.residual(0),
+                     lambda: c.energy_matrix(6)):
+            with pytest.raises(lib.CellError) as e:
+                call()
+            assert e.value.status == lib.CELL_E_STATE
+        C, _ = c.effective_stiffness()
+        g = c.adjoint(np.eye(6))
+    grid = fem.Grid((8, 8, 8))
+    Cref, _, _ = fem.effective_stiffness(grid, E.reshape(8, 8, 8), nu.reshape(8, 8, 8))
+    assert relerr(C, Cref) < 1e-10
+    assert np.all(np.isfinite(g))

@@ -84,6 +84,36 @@ def test_material_law_closed_forms():
             assert abs(fd[0] - P[a, b]) < 1e-7
 
 
+def test_energy_density_closed_values():
+    """W itself at deformations with a closed value (Sec. 2.2, eq.
+    NeoHookeanEnergy): zero at F = I; pure dilation F = s I with J = s^d,
+    W = lam/2 (d ln s)^2 - mu d ln s + mu/2 d (s^2 - 1); simple shear
+    F = I + g e_1 (x) e_2 with J = 1, W = mu g^2 / 2 (only the trace term);
+    uniaxial stretch F = diag(s, 1, ..) with J = s, W = lam/2 ln^2 s - mu ln s
+    + mu/2 (s^2 - 1); no admissible value for det F <= 0.  Dropping or
+    changing any of the three terms, or the tr I constant, fails one of them."""
+    lam, mu = np.array([1.7]), np.array([0.6])
+    for d in (2, 3):
+        I = np.eye(d)[None]
+        assert hyper.energy_density(I, lam, mu)[0] == 0.0
+        for s in (0.8, 1.25, 2.0):
+            W = hyper.energy_density(s * I, lam, mu)[0]
+            Wc = 0.5 * lam[0] * (d * np.log(s)) ** 2 - mu[0] * d * np.log(s) + 0.5 * mu[0] * d * (s * s - 1.0)
+            assert abs(W - Wc) < 1e-14 * max(1.0, abs(Wc))
+            F = np.eye(d)
+            F[0, 0] = s
+            W = hyper.energy_density(F[None], lam, mu)[0]
+            Wc = 0.5 * lam[0] * np.log(s) ** 2 - mu[0] * np.log(s) + 0.5 * mu[0] * (s * s - 1.0)
+            assert abs(W - Wc) < 1e-14 * max(1.0, abs(Wc))
+        for g in (0.1, -0.7):
+            F = np.eye(d)
+            F[0, 1] = g
+            assert abs(hyper.energy_density(F[None], lam, mu)[0] - 0.5 * mu[0] * g * g) < 1e-15
+        F = np.eye(d)
+        F[0, 0] = -1.0
+        assert np.isnan(hyper.energy_density(F[None], lam, mu)[0])
+
+
 @pytest.mark.parametrize("shape", [(4, 4, 4), (6, 6)])
 def test_homogeneous_cell(shape):
     grid = fem.Grid(shape)
