@@ -136,6 +136,24 @@ const char* cell_last_error(void);
  * CELL_MIXED = FP32 arithmetic); u, q host [d][n]. */
 cell_status cell_apply_operator(cell_t c, int precision, const double* u, double* q_out);
 
+/* q = K u like cell_apply_operator in FP64, for callers that cannot
+ * allocate device memory: code recorded under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc.  u and q are device arrays of d n
+ * doubles ([d][n]) on the handle's device; uKu_out (device, one double, may
+ * be NULL) receives u . K u.  The call allocates nothing, neither through
+ * the handle nor otherwise: the reduction's per-block partials and its
+ * scalar block use a library-owned static device array of 1 MiB (held by
+ * each device the library runs on until the process ends); a stencil launch
+ * with more blocks than it holds (131040) would return CELL_E_ARG, which no
+ * supported grid reaches (256^3 in FP64 with z extent 8: 8192 blocks).
+ * Asynchronous on the handle's stream (no synchronisation, no memset);
+ * results are ready once that stream has reached them.  Every handle on one
+ * device shares the array: calls that may overlap on one device (several
+ * streams, several threads) race, calls ordered on one stream do not.
+ * CELL_E_UNSUPPORTED while a surrogate stencil operator is set, CELL_E_STATE
+ * without a material, CELL_E_ARG for null u or q. */
+cell_status cell_apply_operator_noalloc(cell_t c, const double* u, double* q_out, double* uKu_out);
+
 /* z = K_ref^{-1} r through the FFT passes of the given precision (the
  * zero-frequency component of z is 0); r, z host [d][n]; r should have zero
  * mean per component. */

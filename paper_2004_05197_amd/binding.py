@@ -108,6 +108,7 @@ _SIGS = {
     "cell_hyper_residual": (ct.c_int, [_P, _P, _P, _P, _P]),
     "cell_get_schedule": (ct.c_int, [_P, _P]),
     "cell_set_schedule": (ct.c_int, [_P, _P]),
+    "cell_apply_operator_noalloc": (ct.c_int, [_P, _P, _P, _P]),
 }
 
 KERNEL_KINDS = ["k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv", "residual", "merge", "homog"]
@@ -304,6 +305,20 @@ class Cell:
         p = self.precision if precision is None else precision
         _check(_lib.cell_apply_operator(self._h, int(p), u.ctypes.data_as(ct.c_void_p),
                                         q.ctypes.data_as(ct.c_void_p)))
+        return q
+
+    def apply_operator_noalloc(self, u, q, uKu=None):
+        """q = K u (FP64) on device tensors without any allocation by the
+        library (float64 CUDA tensors of d n values; uKu: optional float64
+        CUDA tensor of one value).  Asynchronous on the handle's stream."""
+        import torch
+        for t in (u, q) + (() if uKu is None else (uKu,)):
+            if not (_is_torch(t) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("expected contiguous float64 CUDA tensors")
+        if u.numel() != self.dim * self.n or q.numel() != self.dim * self.n or (uKu is not None and uKu.numel() != 1):
+            raise ValueError("u and q need d n values, uKu one")
+        _check(_lib.cell_apply_operator_noalloc(self._h, ct.c_void_p(u.data_ptr()), ct.c_void_p(q.data_ptr()),
+                                                None if uKu is None else ct.c_void_p(uKu.data_ptr())))
         return q
 
     def apply_preconditioner(self, r, precision=None):
