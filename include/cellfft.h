@@ -112,6 +112,25 @@ cell_status cell_effective_stiffness(cell_t c, double* C_out, cell_info* info);
  * [nv][nv]; dJ_dE_out has n values.  CELL_E_STATE before any solve. */
 cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int on_device);
 
+/* Initial guess of load case `load` (0 <= load < max_loads) for the
+ * linear solves that follow (cell_solve, cell_effective_stiffness): u0
+ * [d][n], host or device (on_device); NULL clears it.  The values are
+ * copied before the call returns (the handle's stream is synchronised).
+ * The guess stays set across cell_set_material calls, so that a solve on a
+ * perturbed material starts from an earlier solution, until it is cleared
+ * or the handle destroyed.  The solve then starts from x = u0 with
+ * r = f - K u0 recomputed in FP64 and stops on the same test as a cold
+ * start (||f - K u|| <= tol ||f||); a guess that already passes it ends
+ * that load with 0 iterations.  The per-component mean of u0 does not
+ * matter (displacements are returned mean-free; C* and the gradient depend
+ * on strains only).  Not used by cell_solve_hyper nor while a surrogate
+ * stencil operator is set.  Errors: CELL_E_ARG for a load out of range or
+ * non-finite host values (device values are checked through their residual:
+ * the next solve returns CELL_E_ARG); CELL_E_NOMEM if the guess storage
+ * ([max_loads][d][n] doubles, allocated at the first guess) cannot be
+ * allocated. */
+cell_status cell_set_initial_guess(cell_t c, int load, const double* u0, int on_device);
+
 /* Displacement fluctuation of load `load` of the last solve, [d][n], each
  * component with zero nodal mean. */
 cell_status cell_get_displacement(cell_t c, int load, double* u_out, int on_device);

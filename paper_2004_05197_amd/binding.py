@@ -109,6 +109,7 @@ _SIGS = {
     "cell_get_schedule": (ct.c_int, [_P, _P]),
     "cell_set_schedule": (ct.c_int, [_P, _P]),
     "cell_apply_operator_noalloc": (ct.c_int, [_P, _P, _P, _P]),
+    "cell_set_initial_guess": (ct.c_int, [_P, ct.c_int, _P, ct.c_int]),
 }
 
 KERNEL_KINDS = ["k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv", "residual", "merge", "homog"]
@@ -283,6 +284,16 @@ class Cell:
         _check(_lib.cell_hyper_residual(self._h, Fb.ctypes.data_as(ct.c_void_p), u.ctypes.data_as(ct.c_void_p),
                                         f.ctypes.data_as(ct.c_void_p), sums.ctypes.data_as(ct.c_void_p)))
         return f, sums
+
+    def set_initial_guess(self, load, u0=None):
+        """Initial guess [d][n] (numpy, or a float64 torch tensor on the host
+        or the device) of load case `load` for later linear solves; None
+        clears it."""
+        if u0 is None:
+            _check(_lib.cell_set_initial_guess(self._h, int(load), None, 0))
+            return
+        p, dev, keep = _in_ptr(u0, self.dim * self.n)
+        _check(_lib.cell_set_initial_guess(self._h, int(load), p, dev))
 
     def displacement(self, load=0):
         u = np.zeros((self.dim, self.n))

@@ -257,6 +257,12 @@ cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int o
   return CELL_OK;
 }
 
+cell_status cell_set_initial_guess(cell_t c, int load, const double* u0, int on_device) {
+  if (!c) return fail(CELL_E_ARG, "null argument");
+  DevGuard dg(c->dev);
+  return instance_set_guess(c, load, u0, on_device);
+}
+
 cell_status cell_get_displacement(cell_t c, int load, double* u_out, int on_device) {
   if (!c || !u_out) return fail(CELL_E_ARG, "null argument");
   return slot_displacement(c, 0, load, u_out, on_device);

@@ -61,6 +61,8 @@ struct cell_s {
   cellfft::Fields<float> f32;
   cellfft::Fields<double> f64;
   double* x64 = nullptr;  // mixed precision FP64 solution [nslot][d n]
+  double* x0 = nullptr;   // initial guesses of the linear solve [lpc][d n] (single cell; on first use)
+  std::vector<char> x0_set;  // per load slot: a guess is set
   // scalars, reductions
   cellfft::LoadState* st = nullptr;
   cellfft::LoadState* st_h = nullptr;
@@ -162,6 +164,9 @@ cell_status instance_hyper_solve(cell_s* c, int nload, const double* Fbar, doubl
                                  double* P_out, cell_hyper_info* infos);
 void instance_get_schedule(cell_s* c, int* out);            // SCHED_NFIELD ints
 cell_status instance_set_schedule(cell_s* c, const int* in);
+// initial guess of load slot `load` for later linear solves with the exact
+// operator (u0 [d][n], host or device; nullptr clears it)
+cell_status instance_set_guess(cell_s* c, int load, const double* u0, int on_device);
 
 // An in-flight solve of one instance.  Phases: solve_begin, then
 // { solve_launch; synchronise the instance's stream; solve_poll } until

@@ -581,6 +581,44 @@ cell_status begin_t(SolveRun& R) {
       R.done = false;
     }
   }
+  // initial guesses (linear solves with the exact operator): x = x0 and
+  // r = f - K x0 in FP64 for the active slots that have one; a slot whose
+  // guess already passes the test is final with 0 iterations
+  if (c->op == 0 && c->x0 && !R.done) {
+    bool any = false;
+    for (int l = 0; l < ns; ++l) {
+      c->mask_h[l] = 0;
+      const int j = l % c->lpc;
+      if (R.fin[l] || !c->x0_set[j]) continue;
+      double* dst = (sizeof(T) == 4 ? c->x64 : reinterpret_cast<double*>(F.x)) + (long long)l * c->lstride;
+      HIPCHK(hipMemcpyAsync(dst, c->x0 + (long long)j * c->lstride, sizeof(double) * c->lstride,
+                            hipMemcpyDeviceToDevice, s));
+      c->mask_h[l] = 1;
+      any = true;
+    }
+    if (any) {
+      HIPCHK(hipMemcpyAsync(c->mask, c->mask_h, sizeof(int) * ns, hipMemcpyHostToDevice, s));
+      const double* u64 = sizeof(T) == 4 ? c->x64 : reinterpret_cast<const double*>(F.x);
+      STCHK(residual<T>(c, u64, c->mask));
+      R.done = true;
+      for (int l = 0; l < ns; ++l) {
+        LoadState& S = c->st_h[l];
+        if (c->mask_h[l]) {
+          const double rt = c->res2_h[l];
+          if (!(rt == rt) || rt > 1e300) return fail(CELL_E_ARG, "non-finite residual of the initial guess of load " +
+                                                                     std::to_string(l % c->lpc));
+          S.rr = rt;
+          R.rr_ru[l] = rt;
+          R.nref[l] = 1;
+          if (rt <= S.thr) {
+            S.state = ST_DONE;
+            R.fin[l] = 1;
+          }
+        }
+        if (!R.fin[l]) R.done = false;
+      }
+    }
+  }
   HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * ns, hipMemcpyHostToDevice, s));
   STCHK(iteration<T>(c, false));
   return CELL_OK;
@@ -786,6 +824,7 @@ void instance_destroy(cell_s* c) {
   free_fields(c->f32);
   free_fields(c->f64);
   fr(c->x64);
+  fr(c->x0);
   fr(c->st);
   fr(c->parts);
   fr(c->res2);
@@ -884,6 +923,7 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
   const char* nq = std::getenv("CELLFFT_DEBUG_NEGATE_Q");
   c->dbg_negate_q = (nq && nq[0] == '1') ? 1 : 0;
   c->have_mat.assign(ncell, 0);
+  c->x0_set.assign(c->lpc, 0);
   c->lam0.assign(ncell, 0.0);
   c->mu0.assign(ncell, 0.0);
   c->maxmod.assign(ncell, 0.0);
@@ -2031,6 +2071,27 @@ cell_status instance_set_schedule(cell_s* c, const int* in) {
   Sched sc;
   if (!sched_from_ints(in, &sc)) return fail(CELL_E_ARG, "invalid schedule");
   c->sched = sc;
+  return CELL_OK;
+}
+
+cell_status instance_set_guess(cell_s* c, int load, const double* u0, int on_device) {
+  if (load < 0 || load >= c->lpc) return fail(CELL_E_ARG, "load index out of range");
+  if (!u0) {
+    c->x0_set[load] = 0;
+    return CELL_OK;
+  }
+  const long long m = c->lstride;
+  if (!on_device)
+    for (long long i = 0; i < m; ++i)
+      if (!std::isfinite(u0[i])) return fail(CELL_E_ARG, "non-finite initial guess");
+  if (!c->x0 && hipMalloc((void**)&c->x0, sizeof(double) * m * c->lpc) != hipSuccess) {
+    c->x0 = nullptr;
+    return fail(CELL_E_NOMEM, "device allocation of the initial guesses failed");
+  }
+  HIPCHK(hipMemcpyAsync(c->x0 + (long long)load * m, u0, sizeof(double) * m,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->x0_set[load] = 1;
   return CELL_OK;
 }
 
