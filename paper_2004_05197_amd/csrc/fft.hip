@@ -78,6 +78,15 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
   const int row0 = rb * RPB;
   const T2* in2 = reinterpret_cast<const T2*>((MODE == 0 ? a.q : a.r) + l * a.lstride);
   cpx<T>* R = a.R + l * (a.lstride / 2);
+  // row-wave operator: q's rows y = 0 mod edge_rows still lack the edge rows
+  const T2* edge2 = (MODE == 0 && a.edge) ? reinterpret_cast<const T2*>(a.edge + l * a.edge_stride) : nullptr;
+  const int erows = a.edge_rows > 0 ? a.edge_rows : 1;  // a power of two
+  const int eshift = __builtin_ctz(erows);
+  const int nyt = a.ny >> eshift;
+  // blocks inside one (component, z) plane (the usual case): y and the plane
+  // index without a division per element
+  const bool inplane = (a.ny % RPB) == 0;
+  const int yb = row0 % a.ny, pb = row0 / a.ny;
   cpx<T> rv[QX];  // mode 0: this thread's R values, loaded with q
   {
     // every load first, then the LDS stores (a loop that stores each value
@@ -94,6 +103,16 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
         const T2 w = in2[off];
         v[q] = {w.x, w.y};
         if (MODE == 0) rv[q] = R[off];
+        if (MODE == 0 && edge2) {
+          // row = (c nz + z) ny + y
+          const int y = inplane ? yb + rr : row % a.ny;
+          if ((y & (erows - 1)) == 0) {
+            const int pl = inplane ? pb : row / a.ny;
+            const T2 ed = edge2[((long long)pl * nyt + (y >> eshift)) * M + m];
+            v[q].re += ed.x;
+            v[q].im += ed.y;
+          }
+        }
       }
     }
 #pragma unroll

@@ -28,8 +28,8 @@ struct RedBuf {
 // block, and the tests check each against the oracle.
 struct Sched {
   int st_tile = 0;  // 3D stencil tile (BX x BY threads): fp32 {64x4, 32x8, 16x16,
-                    // 64x8, 32x16}, fp64 {32x8, 16x16, 64x4, 32x16, 16x32}; a tile
-                    // that does not divide the grid falls back to the first that
+                    // 64x8, 32x16, row-wave}, fp64 {32x8, 16x16, 64x4, 32x16, 16x32};
+                    // a tile that does not fit the grid falls back to the first that
                     // does, else to the runtime-tile kernel
   int st_tz = 32;   // z extent of a stencil tile (8, 16, 32 or 64)
   int x_var = 0;    // x passes: rows per block = 2048 / (nx/2) (0, 2) or 1024 / (nx/2)
@@ -43,7 +43,8 @@ struct Sched {
   int z_radix = 0;  // last pass radix order: radix 8 first (0) or radix 16 first (1)
 };
 constexpr int SCHED_NFIELD = 6;
-constexpr int ST_NTILE = 5;
+constexpr int ST_NTILE = 6;   // tile 5: the FP32 row-wave operator (falls back in FP64)
+constexpr int ST_RW = 5;
 constexpr int ST_TZ_MIN = 8;
 
 struct Geom {
@@ -76,6 +77,10 @@ template <typename T> struct XArgs {
   const double* qmean;  // xfwd mode 0, nullptr or [slot][3]: per-component mean of q,
                         // removed from its transform (the projected operator P K P)
   int comp_rows;        // rows per component (ny nz) for qmean
+  const T* edge;        // xfwd mode 0, nullptr or the row-wave operator's edge rows
+                        // (added to q's rows y = 0 mod edge_rows), [load][3][nz][ny / edge_rows][nx]
+  long long edge_stride;
+  int edge_rows;
 };
 
 // ---------------------------------------------------------------- y pass (3D)
@@ -139,6 +144,14 @@ template <typename T> struct KArgs {
                         // 00,11,22,12,02,01); nullptr = not accumulated
   double* sbar;         // mode 1 (optional): [load][6] finalised stress sums
   int negate;           // mode 0, debugging only: 1 writes -K u (forces a CG breakdown)
+  // row-wave FP32 operator (mode 0): contributions of each tile's last voxel
+  // row to the first node row of the next tile, [load][3][nz][ny / rows][nx]
+  // with rows = rw_rows(nx)
+  // floats; edge_fused = 1: the x forward pass adds them to q (else the
+  // launch adds them itself); nullptr: the row-wave kernel is not used
+  float* edge;
+  long long edge_stride;  // floats per load
+  int edge_fused;
   RedBuf red;
 };
 
@@ -280,6 +293,14 @@ int max_reduction_blocks(const Geom& g);
 // stencil tile variant t of a precision: (BX, BY), and whether it fits the grid
 void stencil_tile_dims(bool fp64, int t, int* bx, int* by);
 bool stencil_tile_fits(const Geom& g, bool fp64, int t);
+// the row-wave operator: voxel rows (waves) per block for a row length
+// (4 at nx = 256, else 8), its grid condition (3D, nx in {64, 128, 256},
+// ny a multiple of the rows per block) and its edge-row floats per load
+int rw_rows(int nx);
+bool rw_fits(const Geom& g);
+// the tile a schedule's stencil launches run (-1: runtime tile)
+int stencil_effective_tile(const Geom& g, bool fp64, int t);
+long long rw_edge_floats(const Geom& g);
 int homog_blocks(const Geom& g);
 bool fft_size_ok(int n);      // y/z length (and x length)
 

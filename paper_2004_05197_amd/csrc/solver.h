@@ -26,6 +26,7 @@ template <typename T> struct Fields {
   T* trig[3] = {nullptr, nullptr, nullptr};
   T* symtab = nullptr;   // 3D: [ncell][ny][nz][nx/2][6]
   T* symtabB = nullptr;  // 3D: [ncell][2][nz][6]
+  float* edge = nullptr; // FP32 row-wave operator: edge rows [nslot][rw_edge_floats]
   T* med = nullptr;      // 2D: per-cell (lambda0, mu0) [ncell][2]
   std::vector<T> med_h;  // host copy of med (source of its upload)
   std::vector<double> sym_lam0, sym_mu0;  // reference medium of each cell's table

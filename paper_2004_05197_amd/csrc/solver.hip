@@ -133,6 +133,11 @@ cell_status ensure_fields(cell_s* c) {
   if (hipMalloc((void**)&F.S, sbytes) != hipSuccess || hipMalloc((void**)&F.R, bytes) != hipSuccess)
     return fail(CELL_E_NOMEM, "device allocation of the spectrum failed");
   HIPCHK(hipMemset(F.S, 0, sbytes));
+  if (sizeof(T) == 4 && rw_fits(c->g)) {
+    const size_t eb = sizeof(float) * (size_t)rw_edge_floats(c->g) * c->nslot;
+    if (hipMalloc((void**)&F.edge, eb) != hipSuccess) return fail(CELL_E_NOMEM, "device allocation of the edge rows failed");
+    HIPCHK(hipMemset(F.edge, 0, eb));
+  }
   const int N[3] = {c->g.nx, c->g.ny, c->g.nz};
   for (int a = 0; a < c->d; ++a) {
     std::vector<cpx<T>> tw(N[a]);
@@ -183,6 +188,7 @@ template <typename T> void free_fields(Fields<T>& F) {
   fr(F.q);
   fr(F.S);
   fr(F.R);
+  fr(F.edge);
   fr(F.symtab);
   fr(F.symtabB);
   fr(F.med);
@@ -229,6 +235,13 @@ KArgs<T> kargs(cell_s* c, int mode, const T* u, void* out, const T* mat) {
   a.sparts = nullptr;
   a.sbar = nullptr;
   a.negate = c->dbg_negate_q;
+  if constexpr (sizeof(T) == 4) {
+    // the FP32 row-wave operator (when the schedule selects it) fixes up its
+    // edge rows itself unless the caller's x forward pass adds them
+    a.edge = c->f32.edge;
+    a.edge_stride = rw_edge_floats(c->g);
+    a.edge_fused = 0;
+  }
   a.red = red_of(c);
   return a;
 }
@@ -335,6 +348,13 @@ XArgs<T> xargs(cell_s* c) {
   xa.red = red_of(c);
   xa.qmean = c->op == 2 ? c->sr_mean : nullptr;
   xa.comp_rows = c->g.ny * (c->d == 3 ? c->g.nz : 1);
+  if constexpr (sizeof(T) == 4) {
+    if (c->f32.edge && c->op == 0 && stencil_effective_tile(c->g, false, c->sched.st_tile) == ST_RW) {
+      xa.edge = c->f32.edge;
+      xa.edge_stride = rw_edge_floats(c->g);
+      xa.edge_rows = rw_rows(c->g.nx);
+    }
+  }
   return xa;
 }
 
@@ -407,6 +427,7 @@ cell_status iteration(cell_s* c, bool kapply) {
       HIPCHK(launch_sr_apply<T>(sa, s));
     } else {
       KArgs<T> ka = kargs<T>(c, 0, F.p, F.q, mat_of<T>(c));
+      ka.edge_fused = 1;  // the x forward pass below adds the edge rows
       HIPCHK(launch_stencil<T>(ka, c->sched, s));
     }
   }

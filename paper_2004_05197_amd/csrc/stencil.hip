@@ -699,6 +699,262 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   }
 }
 
+// =============================================== 3D row-wave stencil (FP32)
+// q = K p for grids with nx = 64 V (V = 1, 2, 4), one wavefront per periodic
+// x row: lane i holds nodes and voxels x = V i .. V i + V - 1 of its row, so
+// the x neighbours are the next and previous lanes and the wave rotation
+// that reaches them wraps exactly like the periodic grid (no x halo).  A
+// block has NW waves for the voxel rows y0 .. y0 + NW - 1 and marches
+// tz node planes along z (one halo layer below, as the tiled kernel).  Wave
+// w owns node row y0 + w: it adds its voxel row's lower-side corner forces,
+// the upper-side forces of wave w - 1 (through LDS, double buffered by step
+// parity) and the upper-z forces of the previous layer (carried in a
+// per-lane LDS area, which keeps the registers of two waves per SIMD, or
+// of one at four voxels per lane).  The upper-side forces of the last wave belong to node row
+// y0 + NW of the next tile: they go to the edge rows, which the x
+// forward pass (or the fix-up launch) adds to q.  p.q is summed from every
+// contribution with the p of its node, so it needs no fix-up.
+template <int V> __device__ __forceinline__ void rw_load(const float* p, float* o) {
+  if constexpr (V == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+  } else if constexpr (V == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    o[0] = t.x;
+    o[1] = t.y;
+  } else {
+    o[0] = *p;
+  }
+}
+template <int V> __device__ __forceinline__ void rw_store(float* p, const float* o) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(o[0], o[1]);
+  } else {
+    *p = o[0];
+  }
+}
+// lane i <- lane i + 1 (ROL) or lane i - 1 (ROR), wrapping around the wave
+__device__ __forceinline__ float rw_rol(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float rw_ror(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x13C, 0xF, 0xF, false));
+}
+
+template <int V, int NW, bool UNI>
+__global__ __launch_bounds__(NW* WAVE) __attribute__((amdgpu_waves_per_eu(V == 4 ? 1 : 2))) void k_stencil_rw(
+    KArgs<float> a, int tz, int nyt, int nzt) {
+  constexpr int NTH = NW * WAVE;
+  // xch: upper-row forces to the next wave, [parity][wave][comp][lane][V];
+  // car: this lane's plane-(k+1) parts carried to the next layer,
+  // [wave][own / upper row][comp][x node][lane] (lane fastest: no bank
+  // conflicts for the one-value accesses)
+  __shared__ float xch[2 * NW * 3 * WAVE * V];
+  __shared__ float car[NW * 2 * 3 * V * WAVE];
+  __shared__ double sh[NTH / WAVE];
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+  const int n = (int)a.g.n;
+  const int nxy = nx * ny;
+  const int ntiles = nyt * nzt;
+  const int item = xcd_order(blockIdx.x, ntiles * a.nload);
+  if (item < 0) return;
+  const int l = item % a.nload;
+  const int blk = item / a.nload;
+  if (a.st[l].state != ST_ACTIVE) return;
+  const int byi = blk % nyt, bzi = blk / nyt;
+  const int y0 = byi * NW, z0 = bzi * tz;
+  const int yv = y0 + w;                       // voxel row, between node rows yv and yv1
+  const int yv1 = yv + 1 == ny ? 0 : yv + 1;
+  const int xb = lane * V;
+  const float ih[3] = {(float)(1.0 / a.g.h[0]), (float)(1.0 / a.g.h[1]), (float)(1.0 / a.g.h[2])};
+  const double wd = a.g.h[0] * a.g.h[1] * a.g.h[2] / 6.0;
+  const float wgt = (float)((UNI ? wd / (a.g.h[0] * a.g.h[0]) : wd) * (a.negate ? -1.0 : 1.0));
+  const float* u = a.u + l * a.lstride;
+  float* out = reinterpret_cast<float*>(a.out) + l * a.lstride;
+  const float* matl = a.mat + (long long)(l / a.lpc) * a.mat_stride;
+  float* edge = a.edge + l * a.edge_stride;
+  const int ety = byi + 1 == nyt ? 0 : byi + 1;  // tile of node row y0 + NW
+  const int roff[2] = {yv * nx + xb, yv1 * nx + xb};
+  float* carw = car + w * (2 * 3 * V * WAVE) + lane;
+  auto cidx = [](int r, int c, int j) { return ((r * 3 + c) * V + j) * WAVE; };
+  // node planes in registers: u at node rows yv / yv1, x nodes xb .. xb + V
+  // (the last one from the next lane); three plane sets and three material
+  // sets rotate (bottom, top, prefetch) so that no step copies registers
+  using Plane = float[2][3][V + 1];
+  using Mat = float[2 * V];
+  Plane P0, P1, P2;
+  Mat M0, M1, M2;
+  auto load_plane = [&](int zp, Plane& dst) {
+    const int zoff = (zp < 0 ? zp + nz : (zp >= nz ? zp - nz : zp)) * nxy;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rw_load<V>(u + c * n + zoff + roff[r], dst[r][c]);
+  };
+  auto load_mat = [&](int zl, Mat& dst) {
+    const int zoff = (zl < 0 ? zl + nz : (zl >= nz ? zl - nz : zl)) * nxy;
+    const float* m = matl + 2 * (zoff + roff[0]);
+#pragma unroll
+    for (int i = 0; i < 2 * V; i += (V == 1 ? 2 : 4)) {
+      if constexpr (V == 1) {
+        const float2 t = *reinterpret_cast<const float2*>(m);
+        dst[0] = t.x;
+        dst[1] = t.y;
+      } else {
+        const float4 t = *reinterpret_cast<const float4*>(m + i);
+        dst[i] = t.x;
+        dst[i + 1] = t.y;
+        dst[i + 2] = t.z;
+        dst[i + 3] = t.w;
+      }
+    }
+  };
+  auto complete = [&](Plane& pl) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pl[r][c][V] = rw_rol(pl[r][c][0]);
+  };
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < V; ++j) carw[cidx(r, c, j)] = 0.0f;
+  double acc = 0.0;
+  // one layer: k between node planes k and k + 1, bottom plane ub, top
+  // plane ut (loaded one step earlier, completed here), material mc;
+  // prefetches plane k + 2 into un and the material of layer k + 1 into mn
+  auto step = [&](int L, Plane& ub, Plane& ut, Plane& un, Mat& mc, Mat& mn) {
+    const int k = z0 - 1 + L;
+    complete(ut);
+    if (L < tz) {
+      load_plane(k + 2, un);
+      load_mat(k + 1, mn);
+    }
+    const bool store = L >= 1 && k < nz;
+    const int slot = L & 1;
+    // node x column j of this lane gets corners (0, ., .) of voxel j and
+    // (1, ., .) of voxel j - 1 (for j = 0: the previous lane's last voxel);
+    // per column: own row plane k (P), upper row plane k (U, to the next
+    // wave), and the plane-(k+1) parts (to the carries)
+    float P[3][V], U[3][V];
+    float h00[3], h10[3], h01[3], h11[3];  // corners (1, ., .) of the last voxel
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      float uu[8][3], f[8][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        uu[0][c] = ub[0][c][i];
+        uu[1][c] = ub[0][c][i + 1];
+        uu[2][c] = ub[1][c][i];
+        uu[3][c] = ub[1][c][i + 1];
+        uu[4][c] = ut[0][c][i];
+        uu[5][c] = ut[0][c][i + 1];
+        uu[6][c] = ut[1][c][i];
+        uu[7][c] = ut[1][c][i + 1];
+      }
+      voxel3<float, false, UNI>(uu, mc[2 * i] * wgt, mc[2 * i + 1] * wgt, ih, nullptr, f, nullptr);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float c0 = carw[cidx(0, c, i)], c1 = carw[cidx(1, c, i)];
+        if (i > 0) {  // column i is complete
+          P[c][i] = f[0][c] + h00[c] + c0;
+          U[c][i] = f[2][c] + h10[c] + c1;
+          carw[cidx(0, c, i)] = f[4][c] + h01[c];
+          carw[cidx(1, c, i)] = f[6][c] + h11[c];
+        } else {  // column 0 still lacks the previous lane's last voxel
+          P[c][0] = f[0][c] + c0;
+          U[c][0] = f[2][c] + c1;
+          carw[cidx(0, c, 0)] = f[4][c];
+          carw[cidx(1, c, 0)] = f[6][c];
+        }
+        // corners (1, ., .) of voxel i: column i + 1, or the next lane
+        h00[c] = f[1][c];
+        h10[c] = f[3][c];
+        h01[c] = f[5][c];
+        h11[c] = f[7][c];
+      }
+    }
+    // column 0 of this lane: corners (1, ., .) of the previous lane's last voxel
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      P[c][0] += rw_ror(h00[c]);
+      U[c][0] += rw_ror(h10[c]);
+      carw[cidx(0, c, 0)] += rw_ror(h01[c]);
+      carw[cidx(1, c, 0)] += rw_ror(h11[c]);
+    }
+    // p.q of every contribution made here, each with the p of its node
+    // (own row: ub[0]; upper row: ub[1]); FP32 within the step
+    float pq = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < V; ++i) pq += ub[0][c][i] * P[c][i] + ub[1][c][i] * U[c][i];
+    if (store) acc += (double)pq;
+    // upper node row, plane k: to the next wave, or (last wave) to the edge rows
+    if (w < NW - 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rw_store<V>(xch + (((slot * NW + w) * 3 + c) * WAVE + lane) * V, U[c]);
+    } else if (store) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rw_store<V>(edge + ((long long)(c * nz + k) * nyt + ety) * nx + xb, U[c]);
+    }
+    __syncthreads();
+    if (store) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float lo[V];
+        if (w > 0) {
+          rw_load<V>(xch + (((slot * NW + w - 1) * 3 + c) * WAVE + lane) * V, lo);
+        } else {
+#pragma unroll
+          for (int i = 0; i < V; ++i) lo[i] = 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) lo[i] += P[c][i];
+        rw_store<V>(out + c * n + k * nxy + roff[0], lo);
+      }
+    }
+  };
+  load_plane(z0 - 1, P0);
+  load_plane(z0, P1);
+  load_mat(z0 - 1, M0);
+  complete(P0);
+  for (int L = 0; L <= tz; L += 3) {
+    step(L, P0, P1, P2, M0, M1);
+    if (L + 1 <= tz) step(L + 1, P1, P2, P0, M1, M2);
+    if (L + 2 <= tz) step(L + 2, P2, P0, P1, M2, M0);
+  }
+  const double bs = block_sum<NTH>(acc, sh);
+  if (tid == 0) a.red.slot_parts(RED_PQ, l)[blk] = bs;
+}
+
+// q[rows y = 0 mod rows] += edge rows, for the active slots (the row-wave
+// operator's fix-up when no x forward pass follows)
+__global__ __launch_bounds__(NT) void k_rw_edge_fix(float* q, const float* edge, long long lstride,
+                                                    long long estride, int nx, int ny, int nz, int nyt, int rows,
+                                                    const LoadState* st) {
+  const int l = blockIdx.y;
+  if (st[l].state != ST_ACTIVE) return;
+  const long long total = 3LL * nz * nyt * nx;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < total; e += (long long)gridDim.x * NT) {
+    const int x = (int)(e % nx);
+    const long long r = e / nx;  // (c nz + z) nyt + t
+    const int t = (int)(r % nyt);
+    const long long cz = r / nyt;
+    q[l * lstride + (cz * ny + (long long)t * rows) * nx + x] += edge[l * estride + e];
+  }
+}
+
 // fixed-order sums of the per-block stress partials: sbar[l][i]
 __global__ __launch_bounds__(NT) void k_stress_finalize(const double* sparts, int maxblk, int nparts,
                                                         int only_load, const int* mask, double* sbar) {
@@ -911,14 +1167,24 @@ static Tile3 pick_tile3(const Geom& g, bool fp64, int tz) {
 // (BX + BY + 1 halo voxels are computed twice, once here and once by the
 // neighbouring tile: the 512-thread tiles halve that share)
 void stencil_tile_dims(bool fp64, int t, int* bx, int* by) {
-  static const int f32[ST_NTILE][2] = {{64, 4}, {32, 8}, {16, 16}, {64, 8}, {32, 16}};
-  static const int f64[ST_NTILE][2] = {{32, 8}, {16, 16}, {64, 4}, {32, 16}, {16, 32}};
+  static const int f32[ST_NTILE][2] = {{64, 4}, {32, 8}, {16, 16}, {64, 8}, {32, 16}, {64, 8}};
+  static const int f64[ST_NTILE][2] = {{32, 8}, {16, 16}, {64, 4}, {32, 16}, {16, 32}, {32, 8}};
   if (t < 0 || t >= ST_NTILE) t = 0;
   *bx = (fp64 ? f64 : f32)[t][0];
   *by = (fp64 ? f64 : f32)[t][1];
 }
 
+int rw_rows(int nx) { return nx == 256 ? 4 : 8; }
+
+bool rw_fits(const Geom& g) {
+  return g.dim == 3 && (g.nx == 64 || g.nx == 128 || g.nx == 256) && g.ny % rw_rows(g.nx) == 0 &&
+         g.n < (1LL << 29);
+}
+
+long long rw_edge_floats(const Geom& g) { return 3LL * g.nz * (g.ny / rw_rows(g.nx)) * g.nx; }
+
 bool stencil_tile_fits(const Geom& g, bool fp64, int t) {
+  if (t == ST_RW) return !fp64 && rw_fits(g);
   int bx, by;
   stencil_tile_dims(fp64, t, &bx, &by);
   return g.dim == 3 && g.nx % bx == 0 && g.ny % by == 0 && g.n < (1LL << 29);
@@ -932,6 +1198,8 @@ static int effective_tile(const Geom& g, bool fp64, int t) {
     if (stencil_tile_fits(g, fp64, u)) return u;
   return -1;
 }
+
+int stencil_effective_tile(const Geom& g, bool fp64, int t) { return effective_tile(g, fp64, t); }
 
 static int sched_tz(const Geom& g, const Sched& sc) {
   const int tz = sc.st_tz < ST_TZ_MIN ? ST_TZ_MIN : sc.st_tz;
@@ -948,6 +1216,7 @@ int stencil_blocks(const Geom& g, const Sched& sc, bool fp64) {
   const int tz = sched_tz(g, sc);
   const int nzt = (g.nz + tz - 1) / tz;
   const int t = effective_tile(g, fp64, sc.st_tile);
+  if (t == ST_RW) return (g.ny / rw_rows(g.nx)) * nzt;
   if (t >= 0) {
     int bx, by;
     stencil_tile_dims(fp64, t, &bx, &by);
@@ -992,12 +1261,52 @@ static void launch_tile3(const KArgs<T>& a, int tz, int& nparts, hipStream_t s) 
     hipLaunchKernelGGL((k_stencil3t<T, TO, MODE, false, BX, BY>), grid, dim3(BX * BY), 0, s, a, tz, nxt, nyt, nzt);
 }
 
+template <int V>
+static void launch_rw_v(const KArgs<float>& a, int tz, int& nparts, hipStream_t s) {
+  constexpr int NW = V == 4 ? 4 : 8;  // rw_rows(64 V)
+  const Geom& g = a.g;
+  const int nyt = g.ny / NW, nzt = (g.nz + tz - 1) / tz;
+  nparts = nyt * nzt;
+  dim3 grid(xcd_grid(nparts * a.nload));
+  const bool uni = g.h[0] == g.h[1] && g.h[1] == g.h[2];
+  if (uni) hipLaunchKernelGGL((k_stencil_rw<V, NW, true>), grid, dim3(NW * WAVE), 0, s, a, tz, nyt, nzt);
+  else hipLaunchKernelGGL((k_stencil_rw<V, NW, false>), grid, dim3(NW * WAVE), 0, s, a, tz, nyt, nzt);
+}
+
 template <typename T, typename TO, int MODE>
 static hipError_t launch_stencil_impl(const KArgs<T>& a, const Sched& sc, hipStream_t s) {
   const Geom& g = a.g;
   constexpr bool fp64 = sizeof(T) == 8;
   int nparts = 0;
-  const int tile = g.dim == 3 ? effective_tile(g, fp64, sc.st_tile) : -1;
+  int tile = g.dim == 3 ? effective_tile(g, fp64, sc.st_tile) : -1;
+  if (tile == ST_RW) {
+    if constexpr (!fp64 && sizeof(TO) == 4 && MODE == 0) {
+      if (a.edge) {
+        const int tz = sched_tz(g, sc);
+        if (g.nx == 256) launch_rw_v<4>(a, tz, nparts, s);
+        else if (g.nx == 128) launch_rw_v<2>(a, tz, nparts, s);
+        else launch_rw_v<1>(a, tz, nparts, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (nparts > a.red.maxblk) return hipErrorInvalidValue;
+        if (!a.edge_fused) {
+          hipLaunchKernelGGL(k_rw_edge_fix, dim3(256, a.nload), dim3(NT), 0, s, reinterpret_cast<float*>(a.out),
+                             (const float*)a.edge, a.lstride, a.edge_stride, g.nx, g.ny, g.nz, g.ny / rw_rows(g.nx),
+                             rw_rows(g.nx), (const LoadState*)a.st);
+          e = hipGetLastError();
+          if (e != hipSuccess) return e;
+        }
+        return launch_finalize(a.red, a.st, a.res2, RED_PQ, nparts, a.nload, a.only_load, nullptr, s);
+      }
+    }
+    // the row-wave kernel needs FP32, mode 0 and the edge rows: a compiled tile instead
+    tile = -1;
+    for (int u = 0; u < ST_RW; ++u)
+      if (stencil_tile_fits(g, fp64, u)) {
+        tile = u;
+        break;
+      }
+  }
   if (tile >= 0) {
     const int tz = sched_tz(g, sc);
     // tile order as in stencil_tile_dims

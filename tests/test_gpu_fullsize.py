@@ -12,10 +12,14 @@ and tile shapes, against the oracle.
   numpy's real FFT.
 * Operator: the uniform-h stencil kernels (equal edge lengths, where 1/h^2
   is folded into the material weights) at every compiled tile and z extent
-  on a 64^3 unit cell, and the bench configuration's tile (32 x 8 nodes,
-  z extent 64) on a 256 x 256 x 16 grid with h = 1/256 and the two-phase
-  1:1000 material recipe, against the oracle's matrix-free K u (the linear
-  law of Sec. 2.2, eq. LinearElastEnergy).
+  on a 64^3 unit cell (tile 5: the FP32 row-wave kernel, one voxel per
+  lane), the row-wave kernel with two and four voxels per lane, and the
+  32 x 8 tile with z extent 64 on a 256 x 256 x 16 grid with h = 1/256 and
+  the two-phase 1:1000 material recipe, against the oracle's matrix-free
+  K u (the linear law of Sec. 2.2, eq. LinearElastEnergy).
+* Solves with the row-wave operator inside the PCG iteration (the x forward
+  pass adds its edge rows): six loads, C* against FP64 and the iteration
+  counts of the tiled operator.
 
 Tolerances (relative, max-norm) as in the single-step parity tests: operator
 FP64 1e-12, FP32 2e-5; preconditioner FP64 1e-10, FP32 1e-4.
@@ -79,7 +83,7 @@ def unit64():
     return shape, E, nu, u, matfree.apply_K(grid, lam, mu, u).ravel()
 
 
-@pytest.mark.parametrize("tile", range(5))
+@pytest.mark.parametrize("tile", range(6))
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
 def test_uniform_h_operator_every_tile(lib, unit64, tile, prec, tol):
     shape, E, nu, u, ref = unit64
@@ -110,3 +114,45 @@ def test_uniform_h_operator_bench_tile(lib, prec, tol, tile):
         c.schedule = (tile, 64, 0, 0, 0, 0)
         q = c.apply_operator(u.ravel(), precision=prec)
     assert relerr(q, ref) < tol
+
+
+# the FP32 row-wave operator at nx = 128 and 256 (two and four voxels per
+# lane): uniform and stretched spacings, z extents that leave a ragged last
+# z tile (the launch adds the edge rows itself here)
+RW_CASES = [((256, 16, 24), None, 16), ((256, 8, 12), (1.0, 0.05, 0.06), 8), ((128, 24, 24), None, 16),
+            ((128, 8, 8), (1.0, 0.1, 0.07), 64), ((64, 16, 12), (1.0, 0.3, 0.2), 32)]
+
+
+@pytest.mark.parametrize("shape,lengths,tz", RW_CASES)
+def test_row_wave_operator(lib, shape, lengths, tz):
+    E, nu = rand_material(shape, 7)
+    grid = fem.Grid(shape, lengths=lengths)
+    lam, mu = fem.lame(E, nu)
+    u = np.random.default_rng(8).standard_normal((3,) + grid.nshape)
+    ref = matfree.apply_K(grid, lam, mu, u).ravel()
+    with lib.Cell(shape, precision=lib.MIXED, lengths=grid.L) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        c.schedule = (5, tz, 0, 0, 0, 0)
+        assert c.schedule == (5, tz, 0, 0, 0, 0)
+        q = c.apply_operator(u.ravel(), precision=lib.MIXED)
+    assert relerr(q, ref) < 2e-5
+
+
+def test_row_wave_solve(lib):
+    shape = (128, 32, 24)
+    g = ms.gaussian_random_field(shape, 4.0, 9)
+    E = np.where(g >= 0.0, 100.0, 1.0)
+    nu = np.where(g >= 0.0, 0.35, 0.25)
+    with lib.Cell(shape, precision=lib.FP64, tol=1e-10) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        Cref, _ = c.effective_stiffness()
+    its = {}
+    for tile in (1, 5):
+        with lib.Cell(shape, precision=lib.MIXED, tol=1e-7) as c:
+            c.set_material(E.ravel(), nu.ravel())
+            c.schedule = (tile, 8, 0, 0, 0, 0)
+            C, info = c.effective_stiffness()
+        assert info["status"] == "CELL_OK"
+        assert relerr(C, Cref) < 1e-6, tile
+        its[tile] = info["iters"]
+    assert all(abs(a - b) <= 1 for a, b in zip(its[1], its[5])), its
