@@ -437,8 +437,8 @@ __device__ __forceinline__ void sym_solve3(const PArgs<T>& P, int kx, int ky, in
 }
 
 // tabulated inverse (6 consecutive values)
-template <typename T>
-__device__ __forceinline__ void sym_load(const T* tab, long long idx, T* m) {
+template <typename T, typename I>
+__device__ __forceinline__ void sym_load(const T* tab, I idx, T* m) {
   using T2 = typename V2<T>::type;
   const T2* t2 = reinterpret_cast<const T2*>(tab + 6 * idx);
   const T2 a = t2[0], b = t2[1], c = t2[2];
@@ -526,14 +526,15 @@ __device__ __forceinline__ void zpass_tile(const PArgs<T>& a, int l, int y, int 
   constexpr int QS = (N * TX + NTH - 1) / NTH;
   if (a.tab) {
     // all of a thread's table entries are loaded before the first use
-    const T* tab = a.tab + (long long)(l / a.lpc) * a.tab_stride;
+    // this row's entries: the row base once, 32-bit offsets per element
+    const T* tab = a.tab + (long long)(l / a.lpc) * a.tab_stride + (long long)y * a.nz * M * 6;
     T m[QS][6];
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
       const int e = tid + q * NTH;
       const int kz = e / TX, s = e - kz * TX;
       const int slot = s0 + s;
-      if (e < N * TX && slot < M) sym_load(tab, ((long long)y * a.nz + kz) * M + slot, m[q]);
+      if (e < N * TX && slot < M) sym_load(tab, (unsigned)kz * (unsigned)M + (unsigned)slot, m[q]);
     }
 #pragma unroll
     for (int q = 0; q < QS; ++q) {
@@ -641,35 +642,41 @@ __global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NTH) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
-  const long long cstride = (long long)a.nz * a.zsS;      // component
-  const long long zstride = a.zsS;                        // z plane (padded)
+  // global <-> LDS copies: thread t keeps one column (t mod NC: component
+  // and slot) and walks z in steps of ZS = NTH / NC, so each element costs
+  // one address add (32-bit offsets from the block's base: a load's
+  // spectrum holds fewer than 2^31 complex values) and its LDS index is a
+  // constant offset; the NTH mod NC threads left over idle
+  constexpr int ZS = NTH / NC;
+  constexpr int QZ = (N + ZS - 1) / ZS;
+  const int col = tid % NC, zi = tid / NC;
+  const bool act = zi < ZS && s0 + col % TX < M;
+  const unsigned zstride = (unsigned)a.zsS;                  // z plane (padded)
+  const unsigned off0 = (unsigned)(col / TX) * ((unsigned)a.nz * zstride) + (unsigned)zi * zstride + (unsigned)(col % TX);
+  const unsigned ostep = (unsigned)ZS * zstride;
   // all of a thread's loads are issued before the first LDS store (a
   // strided loop that stores each value as it arrives waits out one memory
   // latency per element)
-  constexpr int PER = (N * NC + NTH - 1) / NTH;
   {
-    cpx<T> v[PER];
+    cpx<T> v[QZ];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * NTH;
-      const int z = e / NC, rem = e - z * NC;
-      const int c = rem / TX, s = rem - c * TX;
-      v[q] = (e < N * NC && s0 + s < M) ? base[c * cstride + z * zstride + s] : cpx<T>{T(0), T(0)};
+    for (int q = 0; q < QZ; ++q) {
+      const int z = zi + q * ZS;
+      v[q] = (act && (N % ZS == 0 || z < N)) ? base[off0 + (unsigned)q * ostep] : cpx<T>{T(0), T(0)};
     }
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * NTH;
-      if (e < N * NC) buf[e] = v[q];
+    for (int q = 0; q < QZ; ++q) {
+      const int z = zi + q * ZS;
+      if (zi < ZS && (N % ZS == 0 || z < N)) buf[(zi + q * ZS) * NC + col] = v[q];
     }
   }
   __syncthreads();
   double acc = 0.0;
   zpass_tile<T, N, TX, RP, NTH>(a, l, y, s0, buf, tws, acc);
-  // (a plain loop: unrolled, its addresses would stay live through the FFT)
-  for (int e = tid; e < N * NC; e += NTH) {
-    const int z = e / NC, rem = e - z * NC;
-    const int c = rem / TX, s = rem - c * TX;
-    if (s0 + s < M) base[c * cstride + z * zstride + s] = buf[e];
+  if (act) {
+    // (a plain loop: unrolled, its addresses would stay live through the FFT)
+    unsigned off = off0;
+    for (int z = zi; z < N; z += ZS, off += ostep) base[off] = buf[z * NC + col];
   }
   const double bs = block_sum<NTH>(acc, sh);
   if (tid == 0) a.red.slot_parts(RED_RZ, l)[pb] = bs;
