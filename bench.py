@@ -8,20 +8,34 @@ solved together, mixed precision (FP32 stencil/FFT/vector updates, FP64
 reductions and reliable-update residuals), tol 1e-6 on ||r||/||f||.
 
 One step = one cell_effective_stiffness call (load vectors, PCG for the 6
-loads, FP64 residual refreshes, homogenisation).  value = sum over steps and
-loads of 3 n iterations / wall time.  The inputs are resident on the GPU
-before timing starts.
+loads, FP64 residual refreshes, homogenisation), run as in production: the
+kernel schedule pinned (HEADLINE_SCHEDULE; --tune runs the autotuner), the
+PCG chunks replayed from captured HIP graphs, no per-kernel events.  value
+= 3 n x (iterations of the six loads) / median wall time of the timed steps
+(steps are deterministic: every step runs the same iterations).  The inputs
+are resident on the GPU before timing starts.
 
 Besides the headline line it reports (same JSON object):
   * roofline: the kernel with the largest share of GPU time, its algorithmic
     bytes per launch (the byte model of the design notes) divided by its
-    average launch time (HIP events on the library's stream, timed region);
-  * fp64: the same solve in FP64 to tol 1e-6 (time to solution, speed-up of
-    mixed over FP64) and the normwise C* error of both against an FP64
-    solve at tol 1e-10;
+    average launch time, from HIP events around every launch of one more
+    step run with eager launches after the timed ones; traffic from the
+    committed counter summary of the same kernels and schedule;
+  * iteration: the bytes of a whole step over its median wall time, as a
+    fraction of 8 TB/s (this schedule's bytes and the 72 B per
+    DOF-iteration of the textbook fused schedule);
+  * fp64: the same solve in FP64 to tol 1e-6 (median time to solution under
+    the same protocol, speed-up of mixed over FP64) and the normwise C*
+    error of both against an FP64 solve at tol 1e-10;
   * cpu_baseline: the CPU oracle (numpy/scipy FP64) timed on this host on a
     bounded sample: 6 PCG iterations on one load of a 128^3 periodic
-    sub-block of the same field.
+    sub-block of the same field; with --cpu-full also 3 iterations at the
+    full size and the time to solution extrapolated from them.
+
+`--workload` selects the other measured workloads (uneven batch, neo-Hookean,
+surrogate operator, adjoint gradient, the 64^3 sphere cell);
+`summarize-stats` / `summarize-traffic` write the profiles/ summaries from
+rocprofv3 CSV output of this script.
 """
 import argparse
 import json
@@ -65,10 +79,10 @@ def source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kind, workload):
+def measured_traffic(kind, workload, sched=None):
     """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) recorded in
-    profiles/traffic_<workload>.json, or None if absent or taken on other
-    kernel sources."""
+    profiles/traffic_<workload>.json, or None if absent, taken on other
+    kernel sources or under another kernel schedule."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -76,8 +90,65 @@ def measured_traffic(kind, workload):
         t = json.load(fh)
     if t.get("source_sha256") != source_sha256() or kind not in t.get("kernels", {}):
         return None
+    if sched is not None and t.get("schedule") is not None and list(t["schedule"]) != list(sched):
+        return None
     k = t["kernels"][kind]
     return round(k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"])
+
+
+def kernel_variant(kind, sched, n1=256, fp64=False):
+    """Compiled kernel that a schedule selects for one kernel kind (3D grid
+    n1^3, uniform spacing), named as rocprofv3 lists it."""
+    T = "double" if fp64 else "float"
+    tile, tz, xv, yv, zv, zr = sched
+    if kind == "k_apply":
+        tiles = ([(32, 8), (16, 16), (64, 4), (32, 16), (16, 32)] if fp64 else
+                 [(64, 4), (32, 8), (16, 16), (64, 8), (32, 16)])
+        bx, by = tiles[tile]
+        return f"k_stencil3t<{T}, {T}, 0, true, {bx}, {by}>"
+    if kind in ("x_fwd", "x_inv"):
+        v, rp = xv & 1, xv >> 1
+        return (f"k_xfwd<{T}, {n1 // 2}, {v}, {rp}, 0>" if kind == "x_fwd" else f"k_xinv<{T}, {n1 // 2}, {v}, {rp}>")
+    if kind in ("y_fwd", "y_inv"):
+        return f"k_ypass<{T}, {n1}, {'true' if kind == 'y_inv' else 'false'}, {yv & 1}, {yv >> 1}>"
+    B = 4 if fp64 else 8
+    tx, nth = [(B, 512), (B // 2, 512), (B, 768), (2 * B, 1024)][zv]
+    return f"k_zpass<{T}, {n1}, {tx}, {zr}, {nth}>"
+
+
+def cpu_full_size(E, nu, gpu_iters, iters=3):
+    """The CPU oracle's matrix-free PCG (numpy K-apply, scipy.fft
+    preconditioner, FP64) on one load of the full grid: time per iteration,
+    and the time to solve every load, extrapolated from it with the GPU's
+    FP64 iteration counts."""
+    from oracle import fem, matfree
+    g = fem.Grid(E.shape[::-1])
+    t0 = time.perf_counter()
+    pre = matfree.FourierPreconditioner(g, *matfree.reference_medium(E, nu, 3))
+    t_setup = time.perf_counter() - t0
+    its = []
+    t0 = time.perf_counter()
+    matfree.pcg(g, E, nu, np.eye(6)[0], tol=1e-30, maxit=iters, precond=pre,
+                callback=lambda it, rel: its.append(time.perf_counter()))
+    dt = time.perf_counter() - t0
+    s_it = dt / iters
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "s_per_iteration": round(s_it, 3),
+        "value": 3 * g.n / s_it,
+        "unit": "DOF-CG-iterations/s",
+        "cores": cores,
+        "kind": "oracle",
+        "iterations_timed": iters,
+        "timed_s": round(dt, 2),
+        "preconditioner_setup_s": round(t_setup, 2),
+        "time_to_solution_s_extrapolated": round(s_it * sum(gpu_iters) + t_setup, 1),
+        "extrapolation": f"s/iteration x the GPU FP64 iteration counts {list(gpu_iters)} summed over the loads, "
+                         "plus the preconditioner setup; not a measured solve",
+        "sample": f"{iters} PCG iterations on load eps_11 of the full {g.shape[0]}^3 cell (FP64 numpy matrix-free "
+                  f"K-apply, single thread; scipy.fft on {cores} workers), the initial residual and "
+                  "preconditioning included",
+    }
 
 
 def cpu_baseline(E, nu, sub=128, iters=6):
@@ -474,6 +545,64 @@ def bench_adjoint(args, B, ms, progress):
     }
 
 
+def bench_spheres64(args, B, ms, progress):
+    """The 64^3 sphere cell: RSA spheres r 4-8 voxels, vf 0.3, seed 2,
+    E 1:100, nu 0.3, all six unit loads; FP64 to tol 1e-10 and mixed to
+    tol 1e-7 (C* error of the mixed solve against the FP64 one).  The CPU
+    baseline is the oracle's whole FP64 PCG solve of load eps_11 at the same
+    size and tolerance, timed end to end."""
+    import torch
+    n1 = 64
+    n = n1 ** 3
+    E, nu, vf = ms.spheres_cell(n1, 0.3, seed=2, contrast=100.0)
+    Ed = torch.from_numpy(E.ravel()).cuda()
+    nud = torch.from_numpy(nu.ravel()).cuda()
+    res = {}
+    for key, prec, tol in (("fp64", B.FP64, 1e-10), ("mixed", B.MIXED, 1e-7)):
+        with B.Cell((n1,) * 3, precision=prec, tol=tol) as c:
+            c.set_material(Ed, nud)
+            if not args.no_tune:
+                c.autotune()
+            for _ in range(args.warmup):
+                c.effective_stiffness()
+            C, times, infos = timed_steps(c, args.steps, torch)
+        med = float(np.median(times))
+        res[key] = dict(C=C, med=med, iters=infos[-1]["iters"], relres=infos[-1]["relres"])
+        progress(f"{key}: median {med * 1e3:.2f} ms, iters {infos[-1]['iters']}")
+    err = float(np.abs(res["mixed"]["C"] - res["fp64"]["C"]).max() / np.abs(res["fp64"]["C"]).max())
+    value = 3 * n * sum(res["mixed"]["iters"]) / res["mixed"]["med"]
+    cpu = None
+    if not args.no_cpu:
+        from oracle import fem, matfree
+        progress("cpu oracle: full FP64 PCG of load eps_11 ...")
+        g = fem.Grid((n1,) * 3)
+        t0 = time.perf_counter()
+        pre = matfree.FourierPreconditioner(g, *matfree.reference_medium(E, nu, 3))
+        u, it, rel = matfree.pcg(g, E, nu, np.eye(6)[0], tol=1e-10, precond=pre)
+        dt = time.perf_counter() - t0
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": 3 * n * it / dt, "unit": "DOF-CG-iterations/s", "cores": cores, "kind": "oracle",
+               "time_to_solution_s": round(dt, 2), "iters": it, "relres": rel,
+               "gpu_fp64_time_to_solution_s_one_load": round(res["fp64"]["med"] / 6, 5),
+               "sample": f"the whole solve of load eps_11 at {n1}^3 (FP64 numpy matrix-free K-apply, single thread; "
+                         f"scipy.fft preconditioner on {cores} workers; symbol setup included), tol 1e-10, "
+                         f"{it} iterations, {dt:.1f} s"}
+    return {
+        "metric": "DOF-CG-iterations/sec, 64^3 sphere cell (mixed, tol 1e-7)",
+        "value": value, "unit": "DOF-CG-iterations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res["mixed"]["med"] * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"spheres3d_64: 64^3 RSA spheres (r 4-8, vf target 0.3, achieved {vf:.3f}, seed 2), "
+                               "E 1:100, nu 0.3, six unit loads",
+                   "voxels": n, "iters_mixed": res["mixed"]["iters"], "iters_fp64": res["fp64"]["iters"]},
+        "fp64": {"time_to_solution_s": round(res["fp64"]["med"], 5),
+                 "dof_cg_iter_per_s": 3 * n * sum(res["fp64"]["iters"]) / res["fp64"]["med"],
+                 "speedup_mixed_over_fp64": round(res["fp64"]["med"] / res["mixed"]["med"], 3),
+                 "C_err_mixed_tol1e-7_vs_fp64_tol1e-10": err},
+        "cpu_baseline": cpu,
+    }
+
+
 def copy_bandwidth(torch, mib=1024, reps=5):
     """Device-to-device copy rate (GB/s of read + write traffic) of a plain
     torch copy of `mib` MiB, best of `reps`: the practically reachable HBM
@@ -492,6 +621,180 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2 * mib * (1 << 20) / (best * 1e-3) / 1e9
 
 
+# ------------------------------------------------- rocprofv3 summaries
+# `python bench.py summarize-stats ...` / `summarize-traffic ...` turn the
+# CSV output of rocprofv3 runs of this script into the text summaries kept
+# under profiles/ (and the JSON that roofline.traffic reads).
+
+KIND_PATTERNS = [("k_apply", "k_stencil"), ("x_fwd", "k_xfwd<"), ("y_fwd", "k_ypass<"), ("last", "k_zpass<"),
+                 ("y_inv", "k_ypass<"), ("x_inv", "k_xinv<")]
+
+
+def kernel_kind(name):
+    """Iteration kernel kind of a rocprofv3 kernel name (FP32 iteration
+    variants only), or None."""
+    if "k_stencil3t<float, float, 0" in name or "k_stencil_rw<" in name:
+        return "k_apply"
+    if "<float" not in name:
+        return None
+    if "k_xfwd<" in name:
+        return "x_fwd" if name.split(">")[0].rstrip().endswith(" 0") else None
+    if "k_ypass<" in name:
+        return "y_inv" if ", true," in name else "y_fwd"
+    if "k_zpass<" in name:
+        return "last"
+    if "k_xinv<" in name:
+        return "x_inv"
+    return None
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _bench_line(path):
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{") and '"metric"' in line:
+                return json.loads(line)
+    raise SystemExit(f"no bench JSON line in {path}")
+
+
+def summarize_stats(argv):
+    ap = argparse.ArgumentParser(prog="bench.py summarize-stats")
+    ap.add_argument("stats_dir")
+    ap.add_argument("bench_out", help="the bench.py output of the profiled run (its JSON line)")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--command", required=True)
+    a = ap.parse_args(argv)
+    rows = _csv_rows(a.stats_dir, "kernel_stats.csv")
+    line = _bench_line(a.bench_out)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    n = line["config"]["voxels"]
+    f = 3 * n * 4
+    out = [f"# {a.title}", "",
+           f"Workload: {line['config']['workload']}.", "",
+           "Command (run from the repository root on one MI355X):", "", "```", a.command, "```", "",
+           f"Bench line of the same run: value = {line['value']:.4g} {line['unit']}, "
+           f"ms_per_step = {line['ms_per_step']}, schedule = {line['config'].get('schedule')}, "
+           f"iterations per load = {line['config']['iters_per_step']}.", "",
+           "| kernel | calls | total ms | avg us | % GPU time |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    iters = line["config"]["iters_per_step"]
+    out += ["", "Algorithmic bandwidth of the iteration kernels from their average launch time above "
+            "(byte model of bench.py per active load; launches counted over the solves of the run, "
+            "whose loads converge at different iterations):", "",
+            "| kind | kernel | B per voxel and load | avg active loads | avg ms | algorithmic GB/s | % of 8 TB/s |",
+            "|---|---|---:|---:|---:|---:|---:|"]
+    for kind in ("k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv"):
+        cand = [r for r in rows if kernel_kind(r["Name"]) == kind]
+        if not cand:
+            continue
+        r = max(cand, key=lambda r: int(r["Calls"]))
+        calls = int(r["Calls"])
+        nsolve = max(1, round(calls / (max(iters) + (0 if kind == "k_apply" else 1))))
+        load_launches = nsolve * (sum(iters) + (0 if kind == "k_apply" else len(iters)))
+        avg_loads = load_launches / calls
+        bpl = byte_model(kind, n, 4) * avg_loads + (8 * n if kind == "k_apply" else 0)
+        ms = float(r["AverageNs"]) / 1e6
+        gbs = bpl / (ms * 1e-3) / 1e9
+        out.append(f"| {kind} | `{r['Name'].split('(')[0]}` | {byte_model(kind, n, 4) / n:.0f} | {avg_loads:.3f} | "
+                   f"{ms:.4f} | {gbs:.0f} | {100 * gbs / HBM_PEAK_GBS:.1f} |")
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print(a.out)
+
+
+def summarize_traffic(argv):
+    ap = argparse.ArgumentParser(prog="bench.py summarize-traffic")
+    ap.add_argument("fetch_dir")
+    ap.add_argument("write_dir")
+    ap.add_argument("bench_out", help="the bench.py output of one of the counter runs (its JSON line)")
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--commands", nargs=2, required=True)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    a = ap.parse_args(argv)
+    line = _bench_line(a.bench_out)
+    n = line["config"]["voxels"]
+    iters = line["config"]["iters_per_step"]
+    per = {}
+    cal = {}
+    for counter, d in (("FETCH_SIZE", a.fetch_dir), ("WRITE_SIZE", a.write_dir)):
+        vals = {}
+        best_copy = 0.0
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r.get("Counter_Name") != counter:
+                continue
+            name, v = r["Kernel_Name"], float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                best_copy = max(best_copy, v)
+                continue
+            vals.setdefault(name, []).append(v)
+        copy_kib = a.copy_mib * 1024.0
+        if best_copy <= 0:
+            raise SystemExit(f"no copy dispatch for {counter}")
+        cal[counter] = {"KiB": best_copy, "factor": copy_kib / best_copy}
+        for name, v in vals.items():
+            kind = kernel_kind(name)
+            if kind is None:
+                continue
+            per.setdefault(kind, {})[name] = per.get(kind, {}).get(name, {})
+            per[kind][name][counter] = (len(v), sum(v) / len(v) * 1024.0 * cal[counter]["factor"])
+    kernels = {}
+    for kind, names in per.items():
+        name = max(names, key=lambda nm: names[nm].get("FETCH_SIZE", (0, 0))[0])
+        launches, fetch = names[name].get("FETCH_SIZE", (0, 0.0))
+        _, write = names[name].get("WRITE_SIZE", (0, 0.0))
+        nsolve = max(1, round(launches / (max(iters) + (0 if kind == "k_apply" else 1))))
+        load_launches = nsolve * (sum(iters) + (0 if kind == "k_apply" else len(iters)))
+        model = byte_model(kind, n, 4) * load_launches / launches + (8 * n if kind == "k_apply" else 0)
+        kernels[kind] = {"name": name, "launches": launches, "fetch_bytes_per_launch": fetch,
+                         "write_bytes_per_launch": write, "model_bytes_per_launch": model}
+    t = {"workload": a.workload, "source_sha256": source_sha256(), "schedule": line["config"].get("schedule"),
+         "calibration": {"copy_bytes": a.copy_mib << 20, "FETCH_SIZE_KiB": cal["FETCH_SIZE"]["KiB"],
+                         "WRITE_SIZE_KiB": cal["WRITE_SIZE"]["KiB"],
+                         "fetch_factor": cal["FETCH_SIZE"]["factor"], "write_factor": cal["WRITE_SIZE"]["factor"]},
+         "commands": a.commands, "kernels": kernels}
+    base = os.path.join(ROOT, "profiles", f"traffic_{a.workload}")
+    with open(base + ".json", "w") as fh:
+        json.dump(t, fh, indent=1)
+    out = [f"# HBM traffic per launch: PCG iteration kernels, {a.workload} workload", "",
+           "Counters: rocprofv3 `--pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (separate runs, KiB per dispatch), "
+           f"each scaled by the factor that makes the same counter read {a.copy_mib} MiB for a plain device copy "
+           f"of that size (`bench.py --copy-probe {a.copy_mib}`):", "",
+           f"* FETCH_SIZE of the copy: {cal['FETCH_SIZE']['KiB']:.0f} KiB -> factor {cal['FETCH_SIZE']['factor']:.3f}",
+           f"* WRITE_SIZE of the copy: {cal['WRITE_SIZE']['KiB']:.0f} KiB -> factor {cal['WRITE_SIZE']['factor']:.3f}",
+           "", f"Kernel schedule: {t['schedule']}.", "", "Commands:", "", "```"] + a.commands + ["```", "",
+           "| kind | kernel | launches | fetch MiB/launch | write MiB/launch | model MiB/launch | traffic / model |",
+           "|---|---|---:|---:|---:|---:|---:|"]
+    for kind in ("k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv"):
+        if kind not in kernels:
+            continue
+        k = kernels[kind]
+        tot = k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+        out.append(f"| {kind} | `{k['name'].split('(')[0]}` | {k['launches']} | {k['fetch_bytes_per_launch'] / 2**20:.1f} | "
+                   f"{k['write_bytes_per_launch'] / 2**20:.1f} | {k['model_bytes_per_launch'] / 2**20:.1f} | "
+                   f"{tot / k['model_bytes_per_launch']:.3f} |")
+    out += ["", f"Kernel sources (csrc/*.hip, *.h) sha256 at measurement: `{t['source_sha256']}`. bench.py reports "
+            "these bytes as `roofline.traffic` only while the sources hash to this value and the schedule matches."]
+    with open(base + ".md", "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print(base + ".json", base + ".md")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,18 +803,27 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default kernel schedule (other workloads)")
+    ap.add_argument("--tune", action="store_true",
+                    help="grf3d: autotune the kernel schedules instead of the pinned headline schedules")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="grf3d: also time the CPU oracle at the full grid size (3 PCG iterations)")
     ap.add_argument("--schedule", default=None,
                     help="six comma-separated ints: use this kernel schedule instead of tuning")
-    ap.add_argument("--workload", default="grf3d", choices=["grf3d", "uneven", "hyper", "surrogate", "adjoint"],
+    ap.add_argument("--workload", default="grf3d",
+                    choices=["grf3d", "uneven", "hyper", "surrogate", "adjoint", "spheres64"],
                     help="grf3d: the 256^3 headline workload; uneven: the batch of sphere cells; "
-                         "hyper: the neo-Hookean Newton-PCG on the grf3d geometry")
+                         "hyper: the neo-Hookean Newton-PCG on the grf3d geometry; spheres64: the 64^3 "
+                         "sphere cell with the whole CPU oracle solve")
     ap.add_argument("--cells", type=int, default=512, help="cells of the uneven batch")
     ap.add_argument("--contrast", type=float, default=10.0, help="phase contrast of the hyper workload")
     ap.add_argument("--M", type=int, default=4, help="sampling step of the surrogate workload")
     ap.add_argument("--ell", type=float, default=32.0, help="correlation length of the surrogate workload")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    if len(sys.argv) > 1 and sys.argv[1] in ("summarize-stats", "summarize-traffic"):
+        (summarize_stats if sys.argv[1] == "summarize-stats" else summarize_traffic)(sys.argv[2:])
+        return
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -547,6 +859,35 @@ def main():
     if args.workload == "adjoint":
         print(json.dumps(bench_adjoint(args, B, ms, progress)), flush=True)
         return
+    if args.workload == "spheres64":
+        print(json.dumps(bench_spheres64(args, B, ms, progress)), flush=True)
+        return
+    print(json.dumps(bench_grf3d(args, B, ms, progress, torch)), flush=True)
+
+
+# Kernel schedules the headline workload runs (stencil tile, z extent, x, y
+# and last-pass variants; see the autotuner): pinned so that the timed run,
+# the rocprofv3 kernel-time summary and the traffic counters all measure the
+# same compiled variants.  `--tune` runs the autotuner instead.
+HEADLINE_SCHEDULE = {"mixed": (1, 64, 3, 0, 0, 0), "fp64": (0, 64, 1, 2, 0, 1)}
+
+
+def timed_steps(cell, steps, torch):
+    """Wall time of each effective-stiffness call (graphs on, no events),
+    with a synchronisation on both sides of every step."""
+    times, infos = [], []
+    C = None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C, info = cell.effective_stiffness()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        infos.append(info)
+    return C, times, infos
+
+
+def bench_grf3d(args, B, ms, progress, torch):
     n1 = args.n
     n = n1 ** 3
     E, nu = ms.two_phase_grf(n1, seed=3)
@@ -554,47 +895,52 @@ def main():
     nud = torch.from_numpy(nu.ravel()).cuda()
     torch.cuda.synchronize()
 
+    def setup(precision, tol, key):
+        cell = B.Cell((n1, n1, n1), precision=precision, tol=tol)
+        cell.set_material(Ed, nud)
+        if args.schedule:
+            cell.schedule = tuple(int(v) for v in args.schedule.split(","))
+        elif args.tune:
+            t_tune = time.perf_counter()
+            cell.autotune()
+            progress(f"autotune ({key}): schedule {cell.schedule} in {time.perf_counter() - t_tune:.2f} s")
+        elif n1 == 256:
+            cell.schedule = HEADLINE_SCHEDULE[key]
+        return cell
 
     # ---------------------------------------------------------------- mixed
-    cell = B.Cell((n1, n1, n1), precision=B.MIXED, tol=1e-6)
-    cell.set_material(Ed, nud)
-    if args.schedule:
-        cell.schedule = tuple(int(v) for v in args.schedule.split(","))
+    cell = setup(B.MIXED, 1e-6, "mixed")
     sched = cell.schedule
-    if not args.no_tune and not args.schedule:
-        t_tune = time.perf_counter()
-        sched = cell.autotune()
-        progress(f"autotune: schedule {sched} in {time.perf_counter() - t_tune:.2f} s")
     for i in range(args.warmup):
         C_mixed, info = cell.effective_stiffness()
         progress(f"warmup {i}: iters {info['iters']} {info['seconds']:.2f} s")
-    cell.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters_total = 0
-    per_step = []
-    for i in range(args.steps):
-        C_mixed, info = cell.effective_stiffness()
-        iters_total += sum(info["iters"])
-        per_step.append(info)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    C_mixed, times, per_step = timed_steps(cell, args.steps, torch)
+    dt = time.perf_counter() - t0
+    med = float(np.median(times))
+    iters_step = sum(per_step[-1]["iters"])
+    progress(f"timed {args.steps} steps in {dt:.3f} s (median {med * 1e3:.1f} ms, min {min(times) * 1e3:.1f}, "
+             f"max {max(times) * 1e3:.1f}), iters {per_step[-1]['iters']}, "
+             f"refinements {per_step[-1]['refinements']}")
+    assert all(sum(i["iters"]) == iters_step for i in per_step)
+    value = 3 * n * iters_step / med
+    # per-kernel times: one more step with eager launches and HIP events
+    # around every kernel on the library's stream (graph replays carry no
+    # per-kernel timestamps); the same kernels as the timed steps
+    cell.profile(True)
+    _, info_p = cell.effective_stiffness()
     prof = cell.profile_read()
     cell.profile(False)
-    dt = t1 - t0
-    progress(f"timed {args.steps} steps in {dt:.3f} s, iters {per_step[-1]['iters']}, "
-             f"refinements {per_step[-1]['refinements']}")
-    dof_iter = 3 * n * iters_total
-    value = dof_iter / dt
-    mixed_tts = dt / args.steps
+    prof_step_s = info_p["seconds"]
     cell.close()
     del cell
 
-    # roofline of the dominant kernel (largest GPU time in the timed region)
+    # roofline of the dominant kernel (largest GPU time in the profiled step)
     kinds = ["k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv"]
     dom = max(kinds, key=lambda k: prof[k][0])
     ms_tot, launches = prof[dom]
-    load_launches = iters_total + (0 if dom == "k_apply" else 6 * args.steps)
+    load_launches = iters_step + (0 if dom == "k_apply" else 6)
     alg_bytes = load_launches * byte_model(dom, n, 4)
     if dom == "k_apply":
         alg_bytes += launches * 8 * n
@@ -604,53 +950,72 @@ def main():
     roofline = {
         "bound": "hbm",
         "kernel": dom,
+        "variant": kernel_variant(dom, sched),
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(dom, f"grf3d_{n1}"),
+        "traffic": measured_traffic(dom, f"grf3d_{n1}", sched),
         "avg_launch_ms": round(ms_tot / launches, 4),
         "launches": launches,
         "bytes_per_launch": round(alg_bytes / launches),
+        "timing": "HIP events around every launch of one profiled step (eager launches), after the timed steps",
         "copy_gbs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
     }
-    # whole-iteration byte model: all six kernels
-    all_bytes = sum((iters_total + (0 if k == "k_apply" else 6 * args.steps)) * byte_model(k, n, 4)
-                    for k in kinds) + prof["k_apply"][1] * 8 * n
+    # whole-iteration fractions on the wall time of a timed step: the bytes
+    # of this schedule (64 B per DOF-iteration, FP32) and of the textbook
+    # fused schedule (72 B per DOF-iteration)
+    step_bytes = sum((iters_step + (0 if k == "k_apply" else 6)) * byte_model(k, n, 4) for k in kinds) \
+        + prof["k_apply"][1] * 8 * n
     loop_ms = sum(prof[k][0] for k in kinds)
-    kernel_ms = {k: round(v[0], 2) for k, v in prof.items()}
+    iteration = {
+        "bytes_per_dof_iter": round(step_bytes / (3 * n * iters_step), 2),
+        "frac_wall": round(step_bytes / med / 1e9 / HBM_PEAK_GBS, 4),
+        "frac_wall_72B_model": round(72.0 * value / 1e9 / HBM_PEAK_GBS, 4),
+        "frac_of_copy_wall": round(step_bytes / med / 1e9 / copy_gbs, 4),
+        "frac_kernel_time": round(step_bytes / (loop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
 
     # ---------------------------------------------------------------- fp64
     fp64 = None
     if not args.no_fp64:
         with B.Cell((n1, n1, n1), precision=B.FP64, tol=1e-10) as c64:
             c64.set_material(Ed, nud)
+            if n1 == 256 and not args.tune:
+                c64.schedule = HEADLINE_SCHEDULE["fp64"]
             C_ref, info_ref = c64.effective_stiffness()
             progress(f"fp64 tol 1e-10: iters {info_ref['iters']} {info_ref['seconds']:.2f} s")
-        with B.Cell((n1, n1, n1), precision=B.FP64, tol=1e-6) as c64:
-            c64.set_material(Ed, nud)
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            C_64, info_64 = c64.effective_stiffness()
-            torch.cuda.synchronize()
-            fp64_tts = time.perf_counter() - t2
-            progress(f"fp64 tol 1e-6: iters {info_64['iters']} {fp64_tts:.2f} s")
+        c64 = setup(B.FP64, 1e-6, "fp64")
+        for i in range(max(1, args.warmup)):
+            c64.effective_stiffness()
+        C_64, t64, inf64 = timed_steps(c64, max(2, min(args.steps, 5)), torch)
+        sched64 = c64.schedule
+        c64.close()
+        fp64_tts = float(np.median(t64))
+        progress(f"fp64 tol 1e-6: iters {inf64[-1]['iters']} median {fp64_tts:.3f} s over {len(t64)} steps")
         err = lambda C: float(np.abs(C - C_ref).max() / np.abs(C_ref).max())
         fp64 = {
             "time_to_solution_s": round(fp64_tts, 4),
-            "iters": info_64["iters"],
-            "dof_cg_iter_per_s": 3 * n * sum(info_64["iters"]) / fp64_tts,
-            "mixed_time_to_solution_s": round(mixed_tts, 4),
-            "speedup_mixed_over_fp64": round(fp64_tts / mixed_tts, 3),
+            "iters": inf64[-1]["iters"],
+            "schedule": list(sched64),
+            "dof_cg_iter_per_s": 3 * n * sum(inf64[-1]["iters"]) / fp64_tts,
+            "mixed_time_to_solution_s": round(med, 4),
+            "speedup_mixed_over_fp64": round(fp64_tts / med, 3),
             "C_err_mixed_vs_fp64_tol1e-10": err(C_mixed),
             "C_err_fp64_tol1e-6_vs_fp64_tol1e-10": err(C_64),
+            "timing": "median of timed steps, same protocol as the mixed line (warm, graphs on)",
         }
 
     cpu = None
     if not args.no_cpu:
         progress("cpu oracle baseline ...")
         cpu = cpu_baseline(E, nu)
+    cpu_full = None
+    if args.cpu_full:
+        progress("cpu oracle at the full size ...")
+        iters64 = fp64["iters"] if fp64 else per_step[-1]["iters"]
+        cpu_full = cpu_full_size(E, nu, iters64)
 
     out = {
         "metric": "DOF-CG-iterations/sec at 256^3 (mixed vs FP64, rel err <=1e-6); % HBM roofline",
@@ -659,7 +1024,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "ms_per_step": round(med * 1e3, 3),
+        "mean_ms_per_step": round(dt / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -674,16 +1040,18 @@ def main():
             "iters_per_step": per_step[-1]["iters"],
             "refinements_per_step": per_step[-1]["refinements"],
             "schedule": list(sched),
+            "timing": "median wall time of the timed effective-stiffness calls (captured graphs, no events)",
         },
         "roofline": roofline,
-        "iteration_byte_model_frac": round(all_bytes / (loop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "iteration_byte_model_frac_of_copy": round(all_bytes / (loop_ms * 1e-3) / 1e9 / copy_gbs, 4),
-        "kernel_ms": kernel_ms,
-        "gpu_busy_frac": round(gpu_ms * 1e-3 / dt, 4),
+        "iteration": iteration,
+        "kernel_ms_profiled_step": {k: round(v[0], 2) for k, v in prof.items()},
+        "profiled_step_s": round(prof_step_s, 4),
+        "gpu_busy_frac": round(gpu_ms * 1e-3 / prof_step_s, 4),
         "fp64": fp64,
         "cpu_baseline": cpu,
+        "cpu_full_size": cpu_full,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":
