@@ -112,6 +112,23 @@ cell_status cell_effective_stiffness(cell_t c, double* C_out, cell_info* info);
  * [nv][nv]; dJ_dE_out has n values.  CELL_E_STATE before any solve. */
 cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int on_device);
 
+/* Strain-based Fourier projection variant of the solve (3D, FP64, a
+ * cross-check of the iteration; not built for speed): conjugate gradients
+ * on compatible strain fields e = B u (one Voigt strain per simplex) with
+ * the operator B M^-1 B^T D (M the Fourier-inverted reference operator of
+ * the preconditioner) in the inner product sum_s |s| a_s . D0 b_s of the
+ * reference medium.  Its iterates are the strains of the displacement PCG's
+ * iterates: the same step lengths and, stopped on the same residual
+ * ||f - K u|| <= tol ||f|| (the handle's tol and max_iter), the same
+ * iteration counts.  nload (1..6) macro strains [nload][6] (host, Voigt,
+ * engineering shear); writes the mean stresses [nload][6] (host, may be
+ * NULL) and per-load iterations and relative residuals into info.  Allocates
+ * its strain fields (about 1.2 KB per voxel) for the call; leaves no
+ * solution for the getters.  CELL_E_UNSUPPORTED in 2D or for a batch;
+ * CELL_E_STATE without a material or while a surrogate operator is set. */
+cell_status cell_solve_projection(cell_t c, int nload, const double* macro_strain, double* mean_stress_out,
+                                  cell_info* info);
+
 /* Initial guess of load case `load` (0 <= load < max_loads) for the
  * linear solves that follow (cell_solve, cell_effective_stiffness): u0
  * [d][n], host or device (on_device); NULL clears it.  The values are

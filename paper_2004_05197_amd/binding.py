@@ -110,6 +110,7 @@ _SIGS = {
     "cell_set_schedule": (ct.c_int, [_P, _P]),
     "cell_apply_operator_noalloc": (ct.c_int, [_P, _P, _P, _P]),
     "cell_set_initial_guess": (ct.c_int, [_P, ct.c_int, _P, ct.c_int]),
+    "cell_solve_projection": (ct.c_int, [_P, ct.c_int, _P, _P, ct.POINTER(CellInfo)]),
 }
 
 KERNEL_KINDS = ["k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv", "residual", "merge", "homog"]
@@ -223,6 +224,17 @@ class Cell:
         st = _check(_lib.cell_solve(self._h, nl, eb.ctypes.data_as(ct.c_void_p),
                                     out.ctypes.data_as(ct.c_void_p), ct.byref(info)))
         self.solves += 1
+        return out, dict(info.as_dict(), status=STATUS_NAMES[st])
+
+    def solve_projection(self, macro_strains):
+        """The strain-based projection variant (3D, FP64): mean stresses
+        (nload, 6) and info (iterations, relative residuals)."""
+        eb = np.ascontiguousarray(np.atleast_2d(np.asarray(macro_strains, dtype=np.float64)))
+        nl = eb.shape[0]
+        out = np.zeros((nl, self.nv))
+        info = CellInfo()
+        st = _check(_lib.cell_solve_projection(self._h, nl, eb.ctypes.data_as(ct.c_void_p),
+                                               out.ctypes.data_as(ct.c_void_p), ct.byref(info)))
         return out, dict(info.as_dict(), status=STATUS_NAMES[st])
 
     def effective_stiffness(self):

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcellfft.so")
-SOURCES = ["fft.hip", "stencil.hip", "hyper.hip", "surrogate.hip", "solver.hip", "capi.hip", "noalloc.hip"]
+SOURCES = ["fft.hip", "stencil.hip", "hyper.hip", "surrogate.hip", "solver.hip", "capi.hip", "noalloc.hip", "strainproj.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -257,6 +257,18 @@ cell_status cell_adjoint(cell_t c, const double* dJ_dC, double* dJ_dE_out, int o
   return CELL_OK;
 }
 
+cell_status cell_solve_projection(cell_t c, int nload, const double* macro_strain, double* mean_stress_out,
+                                  cell_info* info) {
+  const double t0 = now_s();
+  if (!c || !macro_strain) return fail(CELL_E_ARG, "null argument");
+  if (nload < 1 || nload > 6) return fail(CELL_E_ARG, "nload must be in [1, 6]");
+  STCHK(check_strains(nload, c->nv, macro_strain));
+  DevGuard dg(c->dev);
+  const cell_status st = instance_solve_projection(c, nload, macro_strain, mean_stress_out, info);
+  if (info && st >= 0) info->seconds = now_s() - t0;
+  return st;
+}
+
 cell_status cell_set_initial_guess(cell_t c, int load, const double* u0, int on_device) {
   if (!c) return fail(CELL_E_ARG, "null argument");
   DevGuard dg(c->dev);

@@ -165,6 +165,13 @@ cell_status instance_hyper_solve(cell_s* c, int nload, const double* Fbar, doubl
                                  double* P_out, cell_hyper_info* infos);
 void instance_get_schedule(cell_s* c, int* out);            // SCHED_NFIELD ints
 cell_status instance_set_schedule(cell_s* c, const int* in);
+// FFT preconditioner on device vectors of slot 0 (FP64): prepare once, then
+// z = K_ref^{-1} r ([d][n], device, the handle's stream)
+cell_status instance_precond_prepare(cell_s* c);
+cell_status instance_precond_device(cell_s* c, const double* r, double* z);
+// strain-based projection CG (3D, FP64) for nload macro strains (host
+// [nload][6]); mean stresses [nload][6] (host); iterations in info
+cell_status instance_solve_projection(cell_s* c, int nload, const double* eps, double* stress_out, cell_info* info);
 // initial guess of load slot `load` for later linear solves with the exact
 // operator (u0 [d][n], host or device; nullptr clears it)
 cell_status instance_set_guess(cell_s* c, int load, const double* u0, int on_device);

@@ -1693,6 +1693,23 @@ cell_status apply_precond_t(cell_s* c, const double* r, double* z) {
 
 }  // namespace
 
+cell_status instance_precond_prepare(cell_s* c) { return ensure_fields<double>(c); }
+
+cell_status instance_precond_device(cell_s* c, const double* r, double* z) {
+  Fields<double>& F = c->f64;
+  hipStream_t s = c->stream;
+  const size_t bytes = sizeof(double) * c->lstride;
+  HIPCHK(hipMemcpyAsync(F.r, r, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemsetAsync(F.p, 0, bytes, s));
+  HIPCHK(hipMemsetAsync(F.q, 0, bytes, s));
+  // the slot states are the same on every call (slot 0 active, alpha = beta = 0)
+  diag_state(c);
+  HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * c->nslot, hipMemcpyHostToDevice, s));
+  STCHK(iteration<double>(c, false));
+  HIPCHK(hipMemcpyAsync(z, F.p, bytes, hipMemcpyDeviceToDevice, s));
+  return CELL_OK;
+}
+
 // neo-Hookean single steps on slot 0: q = K_T(u) p in the given precision,
 // or (p == nullptr) f = -grad Pi(u) in FP64 with the 10 sums |s| W, |s| P
 template <typename T>
