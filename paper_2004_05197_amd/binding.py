@@ -17,7 +17,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcellfft.so")
+# CELLFFT_LIBRARY selects another build of the same library (the host-
+# sanitized one of the ABI tests); the default is the in-tree build
+LIB_PATH = os.environ.get("CELLFFT_LIBRARY") or os.path.join(_HERE, "libcellfft.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2004_05197_amd.build`")

@@ -49,5 +49,46 @@ def build(verbose=False):
     return LIB
 
 
+# Host-sanitized variant for the CPU tests of the C ABI: the host code (argument
+# checks, handle bookkeeping, schedule cache, error paths) built with
+# AddressSanitizer and UndefinedBehaviorSanitizer; the device code is
+# unchanged.  The library loads into a Python started with the clang ASan
+# runtime preloaded (see tests/test_abi_sanitized.py).
+SAN_OBJ = os.path.join(HERE, "_build_asan")
+SAN_LIB = os.path.join(SAN_OBJ, "libcellfft_asan.so")
+CLANGXX = os.environ.get("CLANGXX", "/opt/rocm/lib/llvm/bin/clang++")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def sanitizer_runtime():
+    r = _run([CLANGXX, "-print-file-name=libclang_rt.asan-x86_64.so"])
+    return r.stdout.strip()
+
+
+def build_sanitized(verbose=False):
+    os.makedirs(SAN_OBJ, exist_ok=True)
+    objs, cmds = [], []
+    for src in SOURCES:
+        obj = os.path.join(SAN_OBJ, src.replace(".hip", ".o"))
+        objs.append(obj)
+        cmds.append([HIPCC] + FLAGS + SAN_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        for r in ex.map(_run, cmds):
+            if verbose and (r.stdout or r.stderr):
+                print(r.stdout + r.stderr)
+    # the objects carry their device code; the link is a host link against
+    # the HIP runtime and the shared sanitizer runtime
+    tmp = SAN_LIB + ".tmp"
+    san = ",".join(["address", "undefined"])
+    _run([CLANGXX, "-shared", "-fPIC", "-shared-libsan", "-fsanitize=" + san, "-o", tmp] + objs +
+         ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -9,7 +9,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LIB = os.path.join(ROOT, "paper_2004_05197_amd", "libcellfft.so")
+LIB = os.environ.get("CELLFFT_LIBRARY") or os.path.join(ROOT, "paper_2004_05197_amd", "libcellfft.so")
 
 
 @pytest.fixture(scope="module")
