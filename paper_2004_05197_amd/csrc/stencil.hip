@@ -19,6 +19,7 @@
 //              they give the energy-form effective stiffness (k_homog_combine)
 // k_grad       per-voxel derivative of sum_IJ a_IJ C*_IJ w.r.t. E
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -237,8 +238,8 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
     };
     auto mat_of = [&](int vx, int vy, int k, T& lw, T& mw) {
       const long long vid = ((long long)wrapi(k, nz) * ny + wrapi(y0 + vy, ny)) * nx + wrapi(x0 + vx, nx);
-      lw = matl[2 * vid] * w;
-      mw = matl[2 * vid + 1] * w;
+      lw = matl[2 * vid];  // raw: scaled by w where used (no wait at the load)
+      mw = matl[2 * vid + 1];
     };
     // computes voxel (vx, vy) of layer k from planes in slots s0 (k), s1 (k+1)
     auto voxel = [&](int vx, int vy, int s0, int s1, T lw, T mw, T (&own)[2][3], T* sv) {
@@ -307,8 +308,8 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
         if (!doit) continue;
         T o[2][3];
         T sv[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        voxel(pass == 0 ? tx - 1 : ex, pass == 0 ? ty - 1 : ey, s0, s1, pass == 0 ? lw0 : lwe,
-              pass == 0 ? mw0 : mwe, o, sv);
+        voxel(pass == 0 ? tx - 1 : ex, pass == 0 ? ty - 1 : ey, s0, s1, (pass == 0 ? lw0 : lwe) * w,
+              (pass == 0 ? mw0 : mwe) * w, o, sv);
         if (pass == 0) {
 #pragma unroll
           for (int z = 0; z < 2; ++z)
@@ -382,6 +383,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
   constexpr int NEXTRA = BX + BY + 1;
   __shared__ T pl[2 * 3 * PP];
   __shared__ T cb[18 * VV];
+  __shared__ T mt[2 * VV];  // (lambda, mu) of the layer's voxels, by their cb index
   __shared__ double sh[NTH / WAVE];
   const int tid = threadIdx.x;
   const int tx = tid % BX, ty = tid / BX;
@@ -445,6 +447,24 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
       for (int q = 0; q < PF; ++q)
         if (poff[q] >= 0) pf[q] = u ? u[poff[q] + zoff] : T(0);
     };
+    // the material goes through LDS like the node planes: loaded one layer
+    // ahead, stored after the layer's last use, so no wait for a load falls
+    // inside the voxel computations
+    using T2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+    T2 mo, me;
+    auto fetch_mat = [&](int zl) {
+      const int zo = wrapi(zl, nz) * nxy;
+      mo = *reinterpret_cast<const T2*>(matl + 2 * (zo + vown));
+      if (has_extra) me = *reinterpret_cast<const T2*>(matl + 2 * (zo + vext));
+    };
+    auto store_mat = [&]() {
+      mt[2 * cown] = mo.x;
+      mt[2 * cown + 1] = mo.y;
+      if (has_extra) {
+        mt[2 * cext] = me.x;
+        mt[2 * cext + 1] = me.y;
+      }
+    };
     auto store_plane = [&](int slot) {
 #pragma unroll
       for (int q = 0; q < PF; ++q)
@@ -492,27 +512,15 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
     store_plane(0);
     fetch_plane(z0);
     store_plane(1);
-    int zm = wrapi(z0 - 1, nz) * nxy;
-    T lw0 = matl[2 * (zm + vown)] * w, mw0 = matl[2 * (zm + vown) + 1] * w;
-    T lwe = T(0), mwe = T(0);
-    if (has_extra) {
-      lwe = matl[2 * (zm + vext)] * w;
-      mwe = matl[2 * (zm + vext) + 1] * w;
-    }
+    fetch_mat(z0 - 1);
+    store_mat();
     __syncthreads();
     for (int L = 0; L <= tz; ++L) {
       const int k = z0 - 1 + L;
       const int s0 = L & 1, s1 = (L + 1) & 1;
-      if (L < tz) fetch_plane(k + 2);
-      T lw1 = T(0), mw1 = T(0), lwe1 = T(0), mwe1 = T(0);
       if (L < tz) {
-        const int zn = wrapi(k + 1, nz) * nxy;
-        lw1 = matl[2 * (zn + vown)] * w;
-        mw1 = matl[2 * (zn + vown) + 1] * w;
-        if (has_extra) {
-          lwe1 = matl[2 * (zn + vext)] * w;
-          mwe1 = matl[2 * (zn + vext) + 1] * w;
-        }
+        fetch_plane(k + 2);
+        fetch_mat(k + 1);
       }
       T pk[3] = {T(0), T(0), T(0)};
       if (MODE == 0) {
@@ -525,8 +533,8 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
         if (pass == 1 && !has_extra) break;
         T o[2][3];
         T sv[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        voxel(pass == 0 ? bown : bext, pass == 0 ? cown : cext, s0, s1, pass == 0 ? lw0 : lwe,
-              pass == 0 ? mw0 : mwe, o, sv);
+        const int ci = pass == 0 ? cown : cext;
+        voxel(pass == 0 ? bown : bext, ci, s0, s1, mt[2 * ci] * w, mt[2 * ci + 1] * w, o, sv);
         if (pass == 0) {
 #pragma unroll
           for (int z = 0; z < 2; ++z)
@@ -566,11 +574,10 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
 #pragma unroll
         for (int c = 0; c < 3; ++c) carry[c] = nc[c];
       }
-      if (L < tz) store_plane(s0);
-      lw0 = lw1;
-      mw0 = mw1;
-      lwe = lwe1;
-      mwe = mwe1;
+      if (L < tz) {
+        store_plane(s0);
+        store_mat();
+      }
       __syncthreads();
     }
     const double bs = block_sum<NTH>(acc, sh);
