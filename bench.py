@@ -808,6 +808,86 @@ def summarize_traffic(argv):
     print(base + ".json", base + ".md")
 
 
+# gfx950: 256 CUs x 4 SIMDs; a 64-lane FP32/FP64 VALU instruction (not
+# packed) occupies its SIMD for 4 cycles
+SIMDS = 1024
+VALU_CYCLES = 4
+CLOCK_HZ = 2.4e9
+
+
+def summarize_counters(argv):
+    ap = argparse.ArgumentParser(prog="bench.py summarize-counters")
+    ap.add_argument("pmc_dirs", nargs="+", help="rocprofv3 --pmc output directories (one per pass)")
+    ap.add_argument("--bench-out", required=True, help="the bench.py output of one of the runs (its JSON line)")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--commands", nargs="+", required=True)
+    a = ap.parse_args(argv)
+    line = _bench_line(a.bench_out)
+    n = line["config"]["voxels"]
+    iters = line["config"]["iters_per_step"]
+    per = {}  # kind -> name -> counter -> [values]
+    dur = {}  # kind -> name -> [ns]
+    for d in a.pmc_dirs:
+        seen = set()
+        for r in _csv_rows(d, "counter_collection.csv"):
+            kind = kernel_kind(r["Kernel_Name"])
+            if kind is None:
+                continue
+            name = r["Kernel_Name"].split("(")[0]
+            per.setdefault(kind, {}).setdefault(name, {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+            key = (r["Dispatch_Id"], name)
+            if key not in seen:
+                seen.add(key)
+                dur.setdefault(kind, {}).setdefault(name, []).append(
+                    float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+    out = [f"# {a.title}", "", f"Workload: {line['config']['workload']}.", "",
+           f"Kernel schedule: {line['config'].get('schedule')}. Counter passes (one rocprofv3 run each):", "",
+           "```"] + a.commands + ["```", "",
+           "Per launch, averaged over the launches of the run (counters summed over the whole device). "
+           "A unit is one voxel of one active load case. VALU-busy = SQ_INSTS_VALU x 4 cycles / "
+           f"({SIMDS} SIMDs x launch duration x {CLOCK_HZ / 1e9:.1f} GHz); the durations are those of the "
+           "counter runs (dispatches serialised by the collection).", ""]
+    rows = []
+    for kind in ("k_apply", "x_fwd", "y_fwd", "last", "y_inv", "x_inv"):
+        if kind not in per:
+            continue
+        name = max(per[kind], key=lambda nm: max(len(v) for v in per[kind][nm].values()))
+        c = {k: sum(v) / len(v) for k, v in per[kind][name].items()}
+        launches = max(len(v) for v in per[kind][name].values())
+        nsolve = max(1, round(launches / (max(iters) + (0 if kind == "k_apply" else 1))))
+        load_launches = nsolve * (sum(iters) + (0 if kind == "k_apply" else len(iters)))
+        units = n * load_launches / launches
+        ns = sum(dur[kind][name]) / len(dur[kind][name])
+        rows.append((kind, name, launches, units, ns, c))
+    names = sorted({k for r in rows for k in r[5]})
+    out += ["| kind | kernel | launches | units / launch | avg us | " + " | ".join(f"`{k}`" for k in names) + " |",
+            "|---|---|---:|---:|---:|" + "---:|" * len(names)]
+    for kind, name, launches, units, ns, c in rows:
+        out.append(f"| {kind} | `{name}` | {launches} | {units:.4g} | {ns / 1e3:.1f} | " +
+                   " | ".join(f"{c[k]:.4g}" if k in c else "-" for k in names) + " |")
+    out += ["", "Derived:", "", "| kind | VALU instr / wave | VALU instr / unit (per lane) | LDS instr / unit | "
+            "VMEM instr / unit | VALU-busy | L2 hit rate |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for kind, name, launches, units, ns, c in rows:
+        def g(k):
+            return c.get(k)
+        waves = g("SQ_WAVES")
+        valu = g("SQ_INSTS_VALU")
+        vw = f"{valu / waves:.0f}" if valu and waves else "-"
+        vu = f"{valu * 64 / units:.0f}" if valu else "-"
+        lu = f"{g('SQ_INSTS_LDS') * 64 / units:.1f}" if g("SQ_INSTS_LDS") else "-"
+        vm = (g("SQ_INSTS_VMEM_RD") or 0) + (g("SQ_INSTS_VMEM_WR") or 0)
+        mu = f"{vm * 64 / units:.2f}" if vm else "-"
+        busy = f"{valu * VALU_CYCLES / (SIMDS * ns * 1e-9 * CLOCK_HZ):.2f}" if valu else "-"
+        hit = (f"{g('TCC_HIT_sum') / (g('TCC_HIT_sum') + g('TCC_MISS_sum')):.2f}"
+               if g("TCC_HIT_sum") is not None and g("TCC_MISS_sum") else "-")
+        out.append(f"| {kind} | {vw} | {vu} | {lu} | {mu} | {busy} | {hit} |")
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print(a.out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -834,8 +914,9 @@ def main():
     ap.add_argument("--ell", type=float, default=32.0, help="correlation length of the surrogate workload")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
-    if len(sys.argv) > 1 and sys.argv[1] in ("summarize-stats", "summarize-traffic"):
-        (summarize_stats if sys.argv[1] == "summarize-stats" else summarize_traffic)(sys.argv[2:])
+    if len(sys.argv) > 1 and sys.argv[1] in ("summarize-stats", "summarize-traffic", "summarize-counters"):
+        {"summarize-stats": summarize_stats, "summarize-traffic": summarize_traffic,
+         "summarize-counters": summarize_counters}[sys.argv[1]](sys.argv[2:])
         return
     args = ap.parse_args()
 

@@ -299,9 +299,10 @@ cell_status cell_get_surrogate_stencil(cell_t c, double* blocks_out);
  * A schedule picks the compiled variant of each iteration kernel; all
  * variants compute the same operator (sums inside a block may be ordered
  * differently).  Six ints: stencil tile (0..4: fp32 64x4, 32x8, 16x16,
- * 64x8, 32x16; fp64 32x8, 16x16, 64x4, 32x16, 16x32 threads; a tile that
- * does not divide the grid falls back to the first one that does, or to the
- * runtime tile), stencil z
+ * 64x8, 32x16; fp64 32x8, 16x16, 64x4, 32x16, 16x32 threads; 5: the fp32
+ * row-wave operator, one wave per x-row of N_x = 64, 128 or 256 nodes; a
+ * tile that does not fit the grid falls back to the first one that does,
+ * or to the runtime tile), stencil z
  * extent (8, 16, 32, 64), x-pass rows per block (0: 2048/(N_x/2) complex
  * values, 1: half; fp64 half of these; 2, 3: the same with radix 16 first),
  * y-pass columns per block (0: 16, 1: 8; fp64 8, 4; 2, 3: the same with
