@@ -902,7 +902,7 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
   if (dev < 0) HIPCHK(hipGetDevice(&dev));
   if (dev >= ndev) return fail(CELL_E_ARG, "device ordinal out of range");
   const char* zp = std::getenv("CELLFFT_ZPAD");
-  const long long zpad = zp ? std::atoll(zp) : 64;  // complex values
+  const long long zpad = zp ? std::atoll(zp) : 32;  // complex values
   if (zpad < 0 || zpad > (1 << 20)) return fail(CELL_E_ARG, "CELLFFT_ZPAD out of range");
   DevGuard dg(dev);
   cell_s* c = new cell_s();
