@@ -258,7 +258,9 @@ cell_status instance_solve_projection(cell_s* c, int nload, const double* eps, d
   for (int J = 0; J < nload; ++J) {
     double eb[6];
     for (int q = 0; q < 6; ++q) eb[q] = eps[J * 6 + q];
-    if (hipMemcpy(ebar_d, eb, sizeof(eb), hipMemcpyHostToDevice) != hipSuccess)
+    // eb stays alive until the copy has run: the reductions below synchronise
+    // the stream before the next load overwrites it
+    if (hipMemcpyAsync(ebar_d, eb, sizeof(eb), hipMemcpyHostToDevice, s) != hipSuccess)
       return fail(CELL_E_DEVICE, "strain projection upload failed");
     // f = -B^T D ebar, e = 0
     if (hipMemsetAsync(e, 0, sizeof(double) * ms, s) != hipSuccess)
