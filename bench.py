@@ -173,6 +173,34 @@ def cpu_baseline(E, nu, sub=128, iters=6):
     }
 
 
+def cpu_baseline_uneven(cells, budget_s=20.0, max_n=48):
+    """The oracle's whole FP64 PCG solve (matrix-free numpy K-apply, scipy.fft
+    preconditioner, tol 1e-6) of load eps_11 for the first cells of the
+    batch of at most max_n^3 voxels (one larger cell alone would exceed the
+    budget), until about budget_s of host time is spent."""
+    from oracle import fem, matfree
+    done, dofit, t_all = [], 0.0, 0.0
+    for c in cells:
+        n1 = c["n"]
+        if n1 > max_n:
+            continue
+        g = fem.Grid((n1,) * 3)
+        t0 = time.perf_counter()
+        pre = matfree.FourierPreconditioner(g, *matfree.reference_medium(c["E"], c["nu"], 3))
+        _, it, _ = matfree.pcg(g, c["E"], c["nu"], np.eye(6)[0], tol=1e-6, precond=pre)
+        t_all += time.perf_counter() - t0
+        dofit += 3 * g.n * it
+        done.append(f"{n1}^3 {it} it")
+        if t_all >= budget_s:
+            break
+    cores = len(os.sched_getaffinity(0))
+    return {"value": dofit / t_all, "unit": "DOF-CG-iterations/s", "cores": cores, "kind": "oracle",
+            "sample": f"whole FP64 PCG solves of load eps_11 to tol 1e-6 (numpy matrix-free K-apply, single "
+                      f"thread; scipy.fft preconditioner on {cores} workers; setup included) of the first "
+                      f"{len(done)} cells of the batch with at most {max_n}^3 voxels ({', '.join(done)}), "
+                      f"{t_all:.1f} s"}
+
+
 def bench_uneven(args, B, ms, progress):
     """The uneven batch: args.cells sphere cells (seeds 1000..), sizes from
     {32,48,64,96}, 6 unit loads each, one batched mixed-precision solve."""
@@ -254,7 +282,7 @@ def bench_uneven(args, B, ms, progress):
         "profiled_step_s": round(prof_s, 4),
         "gpu_busy_frac_profiled_step": round(gpu_ms * 1e-3 / prof_s, 4),
         "kernel_time_over_timed_step": round(gpu_ms * 1e-3 / dt, 4),
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_uneven(cells),
     }
 
 
