@@ -718,23 +718,36 @@ def summarize_stats(argv):
     ap.add_argument("--out", required=True)
     ap.add_argument("--title", required=True)
     ap.add_argument("--command", required=True)
+    ap.add_argument("--note", default=None, help="a closing sentence")
     a = ap.parse_args(argv)
     rows = _csv_rows(a.stats_dir, "kernel_stats.csv")
     line = _bench_line(a.bench_out)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     n = line["config"]["voxels"]
-    f = 3 * n * 4
+    iters = line["config"].get("iters_per_step")
+    desc = f"ms_per_step = {line['ms_per_step']}"
+    if iters is not None:
+        desc += f", schedule = {line['config'].get('schedule')}, iterations per load = {iters}"
+    else:
+        rl = line.get("roofline") or {}
+        desc += (f"; dominant kernel {rl.get('kernel')} at {rl.get('achieved')} GB/s algorithmic "
+                 f"({100 * rl.get('frac', 0):.1f} % of 8 TB/s, average launch {rl.get('avg_launch_ms')} ms "
+                 f"over {rl.get('launches')} launches)")
     out = [f"# {a.title}", "",
            f"Workload: {line['config']['workload']}.", "",
            "Command (run from the repository root on one MI355X):", "", "```", a.command, "```", "",
-           f"Bench line of the same run: value = {line['value']:.4g} {line['unit']}, "
-           f"ms_per_step = {line['ms_per_step']}, schedule = {line['config'].get('schedule')}, "
-           f"iterations per load = {line['config']['iters_per_step']}.", "",
+           f"Bench line of the same run: value = {line['value']:.4g} {line['unit']}, {desc}.", "",
            "| kernel | calls | total ms | avg us | % GPU time |", "|---|---:|---:|---:|---:|"]
     for r in rows:
         out.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                    f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
-    iters = line["config"]["iters_per_step"]
+    if iters is None:
+        if a.note:
+            out += ["", a.note]
+        with open(a.out, "w") as fh:
+            fh.write("\n".join(out) + "\n")
+        print(a.out)
+        return
     out += ["", "Algorithmic bandwidth of the iteration kernels from their average launch time above "
             "(byte model of bench.py per active load; launches counted over the solves of the run, "
             "whose loads converge at different iterations):", "",
@@ -754,6 +767,8 @@ def summarize_stats(argv):
         gbs = bpl / (ms * 1e-3) / 1e9
         out.append(f"| {kind} | `{r['Name'].split('(')[0]}` | {byte_model(kind, n, 4) / n:.0f} | {avg_loads:.3f} | "
                    f"{ms:.4f} | {gbs:.0f} | {100 * gbs / HBM_PEAK_GBS:.1f} |")
+    if a.note:
+        out += ["", a.note]
     with open(a.out, "w") as fh:
         fh.write("\n".join(out) + "\n")
     print(a.out)

@@ -467,8 +467,22 @@ cell_status cell_batch_set_material(cell_batch_t b, int cell, const double* E, c
   return instance_set_material(b->cls[b->cls_of[cell]], b->idx_of[cell], E, nu, on_device);
 }
 
+namespace {
+struct GraphExec {
+  hipGraphExec_t g = nullptr;
+  void reset() {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  ~GraphExec() { reset(); }
+};
+}  // namespace
+
 // every instance's PCG advances in lockstep: one chunk of iterations per
-// unfinished instance, one stream synchronisation, then the polls
+// unfinished instance, one stream synchronisation, then the polls.  With
+// graphs the chunks of all unfinished instances are one captured graph (in
+// instance order, as the eager launches would queue them), captured again
+// when an instance finishes
 static cell_status batch_run(cell_batch_t b, int nload, const double* eps, std::vector<std::vector<cell_info>>& inf) {
   const int ng = (int)b->cls.size();
   std::vector<SolveRun> runs(ng);
@@ -477,17 +491,46 @@ static cell_status batch_run(cell_batch_t b, int nload, const double* eps, std::
     inf[k].assign(b->cls[k]->ncell, cell_info{});
     STCHK(solve_begin(runs[k], b->cls[k], nload, eps, inf[k].data()));
   }
+  GraphExec ge;
+  std::vector<int> in_graph;  // the instances the current graph launches
   for (;;) {
-    bool any = false;
+    std::vector<int> act;
+    bool graphs = true;
     for (int k = 0; k < ng; ++k)
       if (!runs[k].done) {
-        STCHK(solve_launch(runs[k]));
-        any = true;
+        act.push_back(k);
+        graphs = graphs && solve_graphs(runs[k]);
       }
-    if (!any) break;
+    if (act.empty()) break;
+    if (!graphs) {
+      ge.reset();
+      for (int k : act) STCHK(solve_launch(runs[k]));
+    } else {
+      if (!ge.g || act != in_graph) {
+        ge.reset();
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        cell_status st = CELL_OK;
+        for (size_t i = 0; i < act.size() && st >= 0; ++i) st = solve_enqueue_chunk(runs[act[i]]);
+        hipError_t e = hipStreamEndCapture(b->stream, &graph);
+        if (st < 0) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return st;
+        }
+        if (e != hipSuccess) return fail(CELL_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&ge.g, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+          ge.g = nullptr;
+          return fail(CELL_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        in_graph = act;
+      }
+      HIPCHK(hipGraphLaunch(ge.g, b->stream));
+      for (int k : act) STCHK(solve_copy_states(runs[k]));
+    }
     HIPCHK(hipStreamSynchronize(b->stream));
-    for (int k = 0; k < ng; ++k)
-      if (!runs[k].done) STCHK(solve_poll(runs[k]));
+    for (int k : act) STCHK(solve_poll(runs[k]));
   }
   cell_status worst = CELL_OK;
   for (int k = 0; k < ng; ++k) {

@@ -198,6 +198,13 @@ struct SolveRun {
 };
 cell_status solve_begin(SolveRun& R, cell_s* c, int nload, const double* eps, cell_info* infos);
 cell_status solve_launch(SolveRun& R);
+// the pieces of solve_launch, for callers that capture several instances'
+// chunks into one graph: whether the instance launches from graphs (not
+// while profiling), its CHUNK iterations (eager, or into an open capture on
+// its stream), the copy of its slot states to the host
+bool solve_graphs(const SolveRun& R);
+cell_status solve_enqueue_chunk(SolveRun& R);
+cell_status solve_copy_states(SolveRun& R);
 cell_status solve_poll(SolveRun& R);
 cell_status solve_end(SolveRun& R);
 

@@ -645,6 +645,14 @@ cell_status begin_t(SolveRun& R) {
   return CELL_OK;
 }
 
+// the CHUNK iterations of one launch on the instance's stream (eager, or
+// into a capture the caller has opened on that stream)
+template <typename T>
+cell_status chunk_t(SolveRun& R) {
+  for (int i = 0; i < CHUNK; ++i) STCHK(iteration<T>(R.c, true));
+  return CELL_OK;
+}
+
 // queues CHUNK iterations and the copy of the slot states to the host
 template <typename T>
 cell_status launch_t(SolveRun& R) {
@@ -652,14 +660,13 @@ cell_status launch_t(SolveRun& R) {
   hipStream_t s = c->stream;
   // per-launch event timing needs eager launches (events recorded inside a
   // captured graph carry no timestamps)
-  if (!c->use_graphs || c->prof) {
-    for (int i = 0; i < CHUNK; ++i) STCHK(iteration<T>(c, true));
+  if (!solve_graphs(R)) {
+    STCHK(chunk_t<T>(R));
   } else {
     if (!R.gexec) {  // capture once per solve: the launch arguments are fixed for its duration
       hipGraph_t graph = nullptr;
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      cell_status st = CELL_OK;
-      for (int i = 0; i < CHUNK && st >= 0; ++i) st = iteration<T>(c, true);
+      cell_status st = chunk_t<T>(R);
       hipError_t e = hipStreamEndCapture(s, &graph);
       if (st < 0) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -675,8 +682,7 @@ cell_status launch_t(SolveRun& R) {
     }
     HIPCHK(hipGraphLaunch(R.gexec, s));
   }
-  HIPCHK(hipMemcpyAsync(c->st_h, c->st, sizeof(LoadState) * c->nslot, hipMemcpyDeviceToHost, s));
-  return CELL_OK;
+  return solve_copy_states(R);
 }
 
 // after the stream has drained: reliable updates (FP64 residual, plus the
@@ -1068,6 +1074,18 @@ cell_status solve_begin(SolveRun& R, cell_s* c, int nload, const double* eps, ce
 
 cell_status solve_launch(SolveRun& R) {
   return R.c->precision == CELL_MIXED ? launch_t<float>(R) : launch_t<double>(R);
+}
+
+bool solve_graphs(const SolveRun& R) { return R.c->use_graphs && !R.c->prof; }
+
+cell_status solve_enqueue_chunk(SolveRun& R) {
+  return R.c->precision == CELL_MIXED ? chunk_t<float>(R) : chunk_t<double>(R);
+}
+
+cell_status solve_copy_states(SolveRun& R) {
+  cell_s* c = R.c;
+  HIPCHK(hipMemcpyAsync(c->st_h, c->st, sizeof(LoadState) * c->nslot, hipMemcpyDeviceToHost, c->stream));
+  return CELL_OK;
 }
 
 cell_status solve_poll(SolveRun& R) {

@@ -4,7 +4,9 @@
   reference medium) returns, cell by cell, the bits of the single-cell solve:
   the same kernels run on the same data, one slot per (cell, load).
 - Replaying the captured HIP graph of a chunk of iterations returns the bits
-  of launching the same kernels one by one, solve after solve.
+  of launching the same kernels one by one, solve after solve; for a batch
+  the graph holds the chunks of all unfinished groups and is captured again
+  when a group finishes.
 - The uneven workload (sphere cells of sizes 32..96, contrast 10-100):
   mixed precision within 1e-6 of FP64, bounds, symmetry, and the oracle's
   PCG on a 32^3 cell.
@@ -110,6 +112,36 @@ def test_graph_replay_equals_eager(lib, monkeypatch):
             assert np.array_equal(graph[k][0], eager[0][0]), (prec, k)
             assert graph[k][1] == eager[0][1]
             assert np.array_equal(graph[k][2], eager[k][2])
+
+
+def test_batch_graph_equals_eager(lib, monkeypatch):
+    """One captured graph per chunk for the whole batch (every unfinished
+    group's iterations, captured again whenever a group finishes: the groups
+    here converge after different numbers of chunks) gives the bits of eager
+    launches, twice in a row, with eager work between the solves."""
+    cells = small_cells()
+    m, _, _ = ms.rsa_spheres(12, 0.2, seed=6, rmin=1.5, rmax=2.5)
+    cells.append(((12, 12, 12), np.where(m, 1000.0, 1.0), np.full(m.shape, 0.3)))
+    res = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("CELLFFT_GRAPHS", mode)
+        for prec in (lib.FP64, lib.MIXED):
+            with lib.Batch([c[0] for c in cells], precision=prec, tol=1e-9 if prec == lib.FP64 else 1e-6) as b:
+                assert b.groups == 3
+                for i, (_, E, nu) in enumerate(cells):
+                    b.set_material(i, E.ravel(), nu.ravel())
+                runs = []
+                for _ in range(2):
+                    C, infos = b.effective_stiffness()
+                    runs.append((C, [inf["iters"] for inf in infos]))
+                res[(mode, prec)] = runs
+    for prec in (lib.FP64, lib.MIXED):
+        eager, graph = res[("0", prec)], res[("1", prec)]
+        chunks = {max(it) // 8 for it in eager[0][1]}
+        assert len(chunks) > 1, eager[0][1]  # the groups finish in different chunks
+        for k in range(2):
+            assert np.array_equal(graph[k][0], eager[0][0]), (prec, k)
+            assert graph[k][1] == eager[0][1]
 
 
 def test_batch_rejects_mismatched_configs(lib):
