@@ -330,9 +330,11 @@ cell_status cell_set_schedule(cell_t c, const int* sched /* [6] */);
  * (n and len) share one set of kernel launches: with lpc = max_loads slots
  * per cell, a launch covers ncell_g * lpc independent load cases, each with
  * its own material, reference medium and CG scalars.  Groups of different
- * grids advance in lockstep on one stream, each group replaying a captured
- * HIP graph of a chunk of iterations.  Results equal those of one
- * single-cell handle per cell (the same kernels on the same data). */
+ * grids advance in lockstep on one stream: one captured HIP graph holds a
+ * chunk of iterations of every unfinished group (captured again when a
+ * group finishes), with one host synchronisation per chunk for all groups.
+ * Results equal those of one single-cell handle per cell (the same kernels
+ * on the same data). */
 
 /* cfgs[ncell]: per-cell configurations; dim, precision, tol, max_iter,
  * max_loads, stream and device must agree (else CELL_E_ARG). */
