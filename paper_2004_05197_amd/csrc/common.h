@@ -3,12 +3,11 @@
 //  * cpx<T>            minimal complex type (T = float | double)
 //  * block reductions  wave64 shuffle trees + fixed-order cross-wave sum, so
 //                      every FP64 reduction is deterministic (no float atomics)
-//  * last-block        per-launch "last block done" finalisation: every block
-//                      writes one partial, the block that arrives last sums the
-//                      partials in index order and updates per-load scalars
+//  * XCD order         mapping of block ids so that the blocks of one XCD
+//                      take a contiguous range of the logical work list
 //  * LDS FFT engine    in-place Stockham autosort FFT over a tile of columns
 //                      held in LDS, compile-time length N = 2^a 3^b, radix
-//                      8/4/3/2 codelets in registers, twiddles from a table.
+//                      16/8/4/3/2 codelets in registers, twiddles from a table.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
