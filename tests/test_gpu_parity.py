@@ -206,3 +206,33 @@ def test_error_paths(lib):
         c.set_material(E.ravel(), nu.ravel())
         C, info = c.effective_stiffness()
     assert info["status"] == "CELL_NOT_CONVERGED"
+
+
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + ".json")) as fh:
+        return json.load(fh)
+
+
+def test_golden_values(lib):
+    """The stored oracle values (tests/golden/, written by the oracle alone):
+    the 32^2 circle cell's C* and the mean stress of eps_xx = 1e-2, and the
+    12 x 8 x 6 random cell with stretched edges, FP64 at tol 1e-11."""
+    g = _golden("circle2d_32")
+    E, nu = ms.circle2d(32)
+    with lib.Cell((32, 32), precision=lib.FP64, tol=1e-11) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+        s, _ = c.solve(np.array([g["eps_bar"]]))
+    assert relerr(C, g["C_energy"]) < 1e-10
+    assert relerr(s[0], g["mean_stress"]) < 1e-9
+    g = _golden("random3d_12x8x6")
+    rng = np.random.default_rng(g["seed"])
+    nshape = tuple(reversed(g["shape"]))
+    E = rng.uniform(*g["E_range"], nshape)
+    nu = rng.uniform(*g["nu_range"], nshape)
+    with lib.Cell(tuple(g["shape"]), precision=lib.FP64, tol=1e-11, lengths=g["lengths"]) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+    assert relerr(C, g["C_energy"]) < 1e-10
