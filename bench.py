@@ -728,11 +728,13 @@ def summarize_stats(argv):
     desc = f"ms_per_step = {line['ms_per_step']}"
     if iters is not None:
         desc += f", schedule = {line['config'].get('schedule')}, iterations per load = {iters}"
-    else:
-        rl = line.get("roofline") or {}
+    elif line.get("roofline"):
+        rl = line["roofline"]
         desc += (f"; dominant kernel {rl.get('kernel')} at {rl.get('achieved')} GB/s algorithmic "
                  f"({100 * rl.get('frac', 0):.1f} % of 8 TB/s, average launch {rl.get('avg_launch_ms')} ms "
                  f"over {rl.get('launches')} launches)")
+    elif line["config"].get("iters") is not None:
+        desc += f", iterations per load = {line['config']['iters']}"
     out = [f"# {a.title}", "",
            f"Workload: {line['config']['workload']}.", "",
            "Command (run from the repository root on one MI355X):", "", "```", a.command, "```", "",
