@@ -153,6 +153,19 @@ __device__ __forceinline__ void voxel3(const T (&u)[8][3], T lw, T mw, const T* 
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// element at a 32-bit byte offset from a block-uniform base pointer: the
+// access takes the scalar-base + 32-bit vector-offset form (one add per
+// access instead of a 64-bit address computation); offsets stay below 4 GiB
+// for every supported grid (3 x 256^3 FP64 values per load: 402 MB)
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, unsigned boff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T* base, unsigned boff, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
 // macro stress D eps_bar (tensor storage) scaled by sc, with lw/mw already
 // holding the |s| (and 1/h^2) factors of the caller
 template <typename T>
@@ -411,15 +424,18 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
   const bool has_extra = tid < NEXTRA;
   const int ex = tid < BY ? BX - 1 : tid - BY - 1;
   const int ey = tid < BY ? tid - 1 : BY - 1;
-  int poff[PF];
+  // byte offsets (in-plane part) of the node values this thread stages
+  unsigned poff[PF];
+  bool pon[PF];
 #pragma unroll
   for (int q = 0; q < PF; ++q) {
     const int e = tid + q * NTH;
-    poff[q] = -1;
-    if (e < 3 * PP) {
+    pon[q] = e < 3 * PP;
+    poff[q] = 0;
+    if (pon[q]) {
       const int c = e / PP, rem = e - c * PP;
       const int py = rem / PW, px = rem - py * PW;
-      poff[q] = c * n + wrapi(y0 - 1 + py, ny) * nx + wrapi(x0 - 1 + px, nx);
+      poff[q] = (unsigned)(c * n + wrapi(y0 - 1 + py, ny) * nx + wrapi(x0 - 1 + px, nx)) * (unsigned)sizeof(T);
     }
   }
   // in-plane voxel offsets (material) and LDS corner bases of the two voxels
@@ -442,20 +458,21 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
     }
     T pf[PF];
     auto fetch_plane = [&](int zp) {
-      const int zoff = wrapi(zp, nz) * nxy;
+      const unsigned zb = (unsigned)(wrapi(zp, nz) * nxy) * (unsigned)sizeof(T);
 #pragma unroll
       for (int q = 0; q < PF; ++q)
-        if (poff[q] >= 0) pf[q] = u ? u[poff[q] + zoff] : T(0);
+        if (pon[q]) pf[q] = u ? ld_off(u, poff[q] + zb) : T(0);
     };
     // the material goes through LDS like the node planes: loaded one layer
     // ahead, stored after the layer's last use, so no wait for a load falls
     // inside the voxel computations
     using T2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
     T2 mo, me;
+    const T2* mat2 = reinterpret_cast<const T2*>(matl);
     auto fetch_mat = [&](int zl) {
       const int zo = wrapi(zl, nz) * nxy;
-      mo = *reinterpret_cast<const T2*>(matl + 2 * (zo + vown));
-      if (has_extra) me = *reinterpret_cast<const T2*>(matl + 2 * (zo + vext));
+      mo = ld_off(mat2, (unsigned)(zo + vown) * (unsigned)sizeof(T2));
+      if (has_extra) me = ld_off(mat2, (unsigned)(zo + vext) * (unsigned)sizeof(T2));
     };
     auto store_mat = [&]() {
       mt[2 * cown] = mo.x;
@@ -468,7 +485,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
     auto store_plane = [&](int slot) {
 #pragma unroll
       for (int q = 0; q < PF; ++q)
-        if (poff[q] >= 0) pl[slot * 3 * PP + tid + q * NTH] = pf[q];
+        if (pon[q]) pl[slot * 3 * PP + tid + q * NTH] = pf[q];
     };
     auto voxel = [&](int base, int ci, int s0, int s1, T lw, T mw, T (&own)[2][3], T* sv) {
       T uu[8][3];
@@ -559,14 +576,15 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
           nc[c] = own[1][c] + cb[(3 + c) * VV + i00] + cb[(9 + c) * VV + i10] + cb[(15 + c) * VV + i01];
         }
         if (L >= 1 && k < nz && out_ok) {
-          const int node = k * nxy + (y0 + ty) * nx + (x0 + tx);
+          const unsigned nb = (unsigned)(k * nxy + (y0 + ty) * nx + (x0 + tx)) * (unsigned)sizeof(TO);
+          const unsigned cs = (unsigned)n * (unsigned)sizeof(TO);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             if (MODE == 0) {
-              out[c * n + node] = (TO)val[c];
+              st_off(out, nb + c * cs, (TO)val[c]);
               acc += (double)pk[c] * (double)val[c];
             } else {
-              out[c * n + node] = (TO)(-val[c]);
+              st_off(out, nb + c * cs, (TO)(-val[c]));
               acc += (double)val[c] * (double)val[c];
             }
           }
