@@ -719,6 +719,7 @@ def summarize_stats(argv):
     ap.add_argument("--title", required=True)
     ap.add_argument("--command", required=True)
     ap.add_argument("--note", default=None, help="a closing sentence")
+    ap.add_argument("--top", type=int, default=0, help="list only the N kernels with the most time")
     a = ap.parse_args(argv)
     rows = _csv_rows(a.stats_dir, "kernel_stats.csv")
     line = _bench_line(a.bench_out)
@@ -740,9 +741,15 @@ def summarize_stats(argv):
            "Command (run from the repository root on one MI355X):", "", "```", a.command, "```", "",
            f"Bench line of the same run: value = {line['value']:.4g} {line['unit']}, {desc}.", "",
            "| kernel | calls | total ms | avg us | % GPU time |", "|---|---:|---:|---:|---:|"]
-    for r in rows:
+    shown = rows[:a.top] if a.top > 0 else rows
+    for r in shown:
         out.append(f"| `{r['Name'][:110]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                    f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if len(shown) < len(rows):
+        rest = rows[len(shown):]
+        out.append(f"| ({len(rest)} more kernels) | {sum(int(r['Calls']) for r in rest)} | "
+                   f"{sum(float(r['TotalDurationNs']) for r in rest) / 1e6:.2f} | | "
+                   f"{sum(float(r['Percentage']) for r in rest):.2f} |")
     if iters is None:
         if a.note:
             out += ["", a.note]
