@@ -162,6 +162,19 @@ cell_status cell_energy_matrix(cell_t c, double* C_out);
  * device).  CELL_E_STATE before any solve. */
 cell_status cell_get_residual(cell_t c, int load, double* r_out, int on_device);
 
+/* Residual history of load `load` in the last linear solve (the PCG of
+ * Sec. 2.1's static problem; for cell_solve_hyper, its last inner PCG):
+ * hist_out[k] = ||r_k||_2 / ||f||_2 after k iterations, k = 0 the initial
+ * residual, as the iteration tracks it (mixed precision: the FP32 iterated
+ * residual between FP64 refreshes; the stopping test itself uses the FP64
+ * recomputation).  *count_out receives the number of entries, min(iterations
+ * + 1, min(max_iter + 1, 4096)) (a longer solve keeps its last entry in the
+ * final slot); min(count, capacity) values are written to hist_out (host;
+ * may be NULL when capacity is 0).  CELL_E_STATE before any solve of that
+ * load, CELL_E_ARG for a load outside [0, max_loads) or a negative
+ * capacity. */
+cell_status cell_get_residual_history(cell_t c, int load, double* hist_out, int capacity, int* count_out);
+
 void cell_destroy(cell_t c);
 
 const char* cell_last_error(void);

@@ -89,6 +89,7 @@ _SIGS = {
     "cell_reference_medium": (ct.c_int, [_P, _D, _D]),
     "cell_energy_matrix": (ct.c_int, [_P, _P]),
     "cell_get_residual": (ct.c_int, [_P, ct.c_int, _P, ct.c_int]),
+    "cell_get_residual_history": (ct.c_int, [_P, ct.c_int, _P, ct.c_int, ct.POINTER(ct.c_int)]),
     "cell_profile": (ct.c_int, [_P, ct.c_int]),
     "cell_profile_read": (ct.c_int, [_P, _P, _P]),
     "cell_batch_create": (ct.c_int, [ct.POINTER(CellConfig), ct.c_int, ct.POINTER(_P)]),
@@ -323,6 +324,16 @@ class Cell:
         r = np.zeros((self.dim, self.n))
         _check(_lib.cell_get_residual(self._h, int(load), r.ctypes.data_as(ct.c_void_p), 0))
         return r
+
+    def residual_history(self, load=0):
+        """||r_k|| / ||f|| after k = 0, 1, ... iterations of the last linear
+        solve of load `load`."""
+        cnt = ct.c_int(0)
+        _check(_lib.cell_get_residual_history(self._h, int(load), None, 0, ct.byref(cnt)))
+        h = np.zeros(cnt.value)
+        _check(_lib.cell_get_residual_history(self._h, int(load), h.ctypes.data_as(ct.c_void_p), cnt.value,
+                                               ct.byref(cnt)))
+        return h
 
     def apply_operator(self, u, precision=None):
         u = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).ravel()

@@ -293,6 +293,25 @@ cell_status cell_get_residual(cell_t c, int load, double* r_out, int on_device) 
   return slot_residual(c, 0, load, r_out, on_device);
 }
 
+cell_status cell_get_residual_history(cell_t c, int load, double* hist_out, int capacity, int* count_out) {
+  if (!c || !count_out || (!hist_out && capacity > 0)) return fail(CELL_E_ARG, "null argument");
+  if (capacity < 0) return fail(CELL_E_ARG, "negative capacity");
+  if (load < 0 || load >= c->lpc) return fail(CELL_E_ARG, "load index out of range");
+  const int n = c->hist_n.empty() ? 0 : c->hist_n[load];
+  if (n == 0) return fail(CELL_E_STATE, "no solve of this load yet");
+  *count_out = n;
+  const int m = std::min(n, capacity);
+  if (m == 0) return CELL_OK;
+  DevGuard dg(c->dev);
+  std::vector<double> h(m);
+  HIPCHK(hipMemcpyAsync(h.data(), c->hist + (long long)load * c->hist_cap, sizeof(double) * m,
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double fn2 = c->hist_fn2[load];
+  for (int k = 0; k < m; ++k) hist_out[k] = fn2 > 0.0 ? std::sqrt(h[k] / fn2) : 0.0;
+  return CELL_OK;
+}
+
 cell_status cell_reference_medium(cell_t c, double* lam0, double* mu0) {
   if (!c || !lam0 || !mu0) return fail(CELL_E_ARG, "null argument");
   if (!c->have_mat[0]) return fail(CELL_E_STATE, "cell_set_material has not been called");

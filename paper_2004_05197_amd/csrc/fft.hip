@@ -808,6 +808,7 @@ __global__ __launch_bounds__(NTF) void k_finalize(RedBuf red, LoadState* st, dou
       break;
     case RED_RR:
       S->rr = s;
+      if (red.hist) red.hist[(long long)l * red.hist_cap + min(S->iters, red.hist_cap - 1)] = s;
       if (!(s == s) || s > 1e300) S->state = ST_BREAKDOWN;
       else if (s <= S->thr) S->state = ST_CONVERGED;
       else if (S->iters >= S->maxit) {

@@ -17,6 +17,8 @@ struct RedBuf {
   double* parts;
   int maxblk;
   int maxload;
+  double* hist = nullptr;  // per load: ||r_k||^2 after k iterations, hist_cap entries
+  int hist_cap = 0;
   __host__ __device__ double* slot_parts(int slot, int load) const {
     return parts + ((long long)slot * maxload + load) * maxblk;
   }

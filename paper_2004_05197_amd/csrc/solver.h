@@ -78,6 +78,13 @@ struct cell_s {
   double* hparts = nullptr;
   double* hres = nullptr;
   double* grad = nullptr;
+  // residual history of the last linear solve: ||r_k||^2 per slot (the
+  // iterated residual, k = 0 the initial one), hist_n[l] entries of
+  // hist_cap kept, relative to hist_fn2[l] = ||f||^2
+  double* hist = nullptr;
+  int hist_cap = 0;
+  std::vector<int> hist_n;
+  std::vector<double> hist_fn2;
   double* scratch = nullptr;
   int hblk = 0;
   // neo-Hookean Newton path

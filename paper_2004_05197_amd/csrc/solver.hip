@@ -47,6 +47,12 @@ constexpr int CHUNK = 8;         // iterations between host polls
 constexpr double DELTA = 0.05;   // reliable-update trigger (residual reduction)
 constexpr int PROF_PAIRS = 256;  // event pairs before a forced collection
 
+// first entry of every slot's residual history: the initial ||r||^2
+__global__ void k_hist_init(double* hist, int cap, const LoadState* st, int ns) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < ns) hist[(long long)l * cap] = st[l].rr;
+}
+
 // x64[slot] += x32[slot], x32[slot] = 0 for the masked slots
 __global__ void k_merge(double* x64, float* x32, long long len, const int* mask) {
   const int l = blockIdx.y;
@@ -75,7 +81,7 @@ double now_s() {
 
 namespace {
 
-RedBuf red_of(cell_s* c) { return RedBuf{c->parts, c->maxblk, c->nslot}; }
+RedBuf red_of(cell_s* c) { return RedBuf{c->parts, c->maxblk, c->nslot, c->hist, c->hist_cap}; }
 
 template <typename T> Fields<T>& fields(cell_s* c);
 template <> Fields<float>& fields<float>(cell_s* c) { return c->f32; }
@@ -641,6 +647,14 @@ cell_status begin_t(SolveRun& R) {
     }
   }
   HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * ns, hipMemcpyHostToDevice, s));
+  // residual history: entry 0 is the initial ||r||^2 of every slot
+  hipLaunchKernelGGL(k_hist_init, dim3((ns + NT - 1) / NT), dim3(NT), 0, s, c->hist, c->hist_cap,
+                     (const LoadState*)c->st, ns);
+  HIPCHK(hipGetLastError());
+  for (int l = 0; l < ns; ++l) {
+    c->hist_n[l] = 0;
+    c->hist_fn2[l] = R.fn2[l];
+  }
   STCHK(iteration<T>(c, false));
   return CELL_OK;
 }
@@ -781,6 +795,7 @@ cell_status end_t(SolveRun& R) {
   }
   bool all_conv = true;
   for (int l = 0; l < c->nslot; ++l) {
+    c->hist_n[l] = R.active[l] ? std::min(c->st_h[l].iters + 1, c->hist_cap) : 0;
     if (!R.active[l]) continue;
     const double rel = (R.fn2[l] > 0 && R.nref[l] > 0) ? std::sqrt(R.rr_ru[l] / R.fn2[l]) : 0.0;
     if (R.infos) {
@@ -861,6 +876,7 @@ void instance_destroy(cell_s* c) {
   fr(c->hparts);
   fr(c->hres);
   fr(c->grad);
+  fr(c->hist);
   fr(c->scratch);
   fr(c->hy_u);
   fr(c->hy_u32);
@@ -981,6 +997,11 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
       !dmalloc((void**)&c->E64, sizeof(double) * c->n * ncell) || !dmalloc((void**)&c->grad, sizeof(double) * c->n) ||
       !dmalloc((void**)&c->scratch, sizeof(double) * 64 * 1024))
     return bail(fail(CELL_E_NOMEM, "device allocation failed"));
+  c->hist_cap = std::min(c->max_iter + 1, 4096);
+  if (!dmalloc((void**)&c->hist, sizeof(double) * (size_t)c->hist_cap * ns))
+    return bail(fail(CELL_E_NOMEM, "device allocation failed"));
+  c->hist_n.assign(ns, 0);
+  c->hist_fn2.assign(ns, 0.0);
   c->hblk = homog_blocks(c->g);
   const int nvalmax = c->lpc * c->lpc + c->lpc * nv;
   if (!dmalloc((void**)&c->hparts, sizeof(double) * (size_t)c->lpc * c->lpc * c->hblk * ncell) ||

@@ -236,3 +236,55 @@ def test_golden_values(lib):
         c.set_material(E.ravel(), nu.ravel())
         C, info = c.effective_stiffness()
     assert relerr(C, g["C_energy"]) < 1e-10
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 32)])
+def test_residual_history_matches_oracle_pcg(lib, shape):
+    """The per-iteration residuals of the FP64 PCG (cell_get_residual_history)
+    against the oracle's textbook PCG with the same reference medium: the two
+    run the same recurrence, so the histories agree to rounding (1e-6 over
+    the first 40 iterations; CG amplifies rounding slowly) and the
+    iteration counts within one."""
+    if len(shape) == 3:
+        mask, _, _ = ms.rsa_spheres(16, 0.25, seed=3, rmin=1.5, rmax=3.0)
+        E = np.where(mask, 20.0, 1.0)
+    else:
+        E, _ = ms.circle2d(32)
+    nu = np.full(E.shape, 0.3)
+    grid = fem.Grid(shape)
+    eb = np.eye(grid.nv)[0]
+    with lib.Cell(shape, precision=lib.FP64, tol=1e-10) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        with pytest.raises(lib.CellError) as e:
+            c.residual_history(0)
+        assert e.value.status == lib.CELL_E_STATE
+        S, info = c.solve(eb[None, :])
+        h = c.residual_history(0)
+        pre = matfree.FourierPreconditioner(grid, *c.reference_medium())
+        with pytest.raises(lib.CellError) as e:
+            c.residual_history(7)
+        assert e.value.status == lib.CELL_E_ARG
+    ref = [1.0]
+    matfree.pcg(grid, E, nu, eb, tol=1e-10, precond=pre, callback=lambda it, rel: ref.append(rel))
+    ref = np.array(ref)
+    assert len(h) == info["iters"][0] + 1
+    assert abs(len(h) - len(ref)) <= 1, (len(h), len(ref))
+    assert h[0] == 1.0 and h[-1] <= 1e-10 * 1.0000001
+    k = min(40, len(h), len(ref))
+    assert np.abs(h[:k] / ref[:k] - 1).max() < 1e-6, np.abs(h[:k] / ref[:k] - 1).max()
+
+
+def test_residual_history_mixed(lib):
+    """Mixed precision: the history starts at 1, ends at or below tol (the
+    stopping test uses the FP64 recomputation, the history the iterated FP32
+    residual) and has iterations + 1 entries for every load."""
+    mask, _, _ = ms.rsa_spheres(24, 0.25, seed=4, rmin=2.0, rmax=4.0)
+    E = np.where(mask, 50.0, 1.0)
+    nu = np.full(E.shape, 0.3)
+    with lib.Cell((24, 24, 24), precision=lib.MIXED, tol=1e-7) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+        for l in range(6):
+            h = c.residual_history(l)
+            assert len(h) == info["iters"][l] + 1
+            assert h[0] == 1.0 and h[-1] <= 2e-7, (l, h[-1])
