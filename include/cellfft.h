@@ -31,6 +31,12 @@
  *     was written.  CELL_NOT_CONVERGED: the best iterate and its results
  *     were written and cell_info holds the residuals.  cell_last_error()
  *     returns a thread-local message for the last failure.
+ *   - A linear solve ends CELL_NOT_CONVERGED when a load reaches max_iter
+ *     or stagnates: CELLFFT_STAG_WINDOW iterations (environment, read at
+ *     create; default 256, 0 = never) without halving the smallest
+ *     ||r||^2 seen so far.  The first stagnation refreshes the residual in
+ *     FP64 and restarts CG there (beta = 0 at the next direction update);
+ *     the second ends that load, and cell_last_error() names it.
  *   - Grid sizes: N_a in {4,6,8,12,16,24,32,48,64,96,128,192,256} (even,
  *     radix 2/3 FFTs); others return CELL_E_UNSUPPORTED.
  */

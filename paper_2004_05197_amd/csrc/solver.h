@@ -51,6 +51,8 @@ struct cell_s {
   int nslot = 6;  // ncell * lpc
   bool use_graphs = true;
   int dbg_negate_q = 0;     // CELLFFT_DEBUG_NEGATE_Q=1: the linear K-apply writes -K p
+  int stag_window = 256;    // CELLFFT_STAG_WINDOW: CG iterations without progress that count as
+                            // stagnation (0: never)
   cellfft::Sched sched{};  // kernel variants (autotuner)
   bool tuned = false;
   // material, per cell
@@ -193,6 +195,11 @@ struct SolveRun {
   cell_info* infos = nullptr;  // ncell entries or nullptr
   std::vector<double> fn2, rr_ru;
   std::vector<int> fin, nref, active;
+  // stagnation: smallest ||r||^2 seen at the polls and the iteration that
+  // last halved it; restarts taken; slots marked for the stagnation refresh;
+  // slots that ended on stagnation
+  std::vector<double> best;
+  std::vector<int> best_it, restarts, stag_pending, stagnated;
   hipGraphExec_t gexec = nullptr;  // CHUNK iterations, captured at the first launch
   cell_status result = CELL_OK;
   bool done = false;

@@ -646,6 +646,12 @@ cell_status begin_t(SolveRun& R) {
       }
     }
   }
+  R.best.assign(ns, 0.0);
+  R.best_it.assign(ns, 0);
+  R.restarts.assign(ns, 0);
+  R.stag_pending.assign(ns, 0);
+  R.stagnated.assign(ns, 0);
+  for (int l = 0; l < ns; ++l) R.best[l] = c->st_h[l].rr;
   HIPCHK(hipMemcpyAsync(c->st, c->st_h, sizeof(LoadState) * ns, hipMemcpyHostToDevice, s));
   // residual history: entry 0 is the initial ||r||^2 of every slot
   hipLaunchKernelGGL(k_hist_init, dim3((ns + NT - 1) / NT), dim3(NT), 0, s, c->hist, c->hist_cap,
@@ -724,7 +730,18 @@ cell_status poll_t(SolveRun& R) {
     // finalisation, which marks DONE, has not run yet); NEGCURV: stopped on
     // p.Kp <= 0 with the previous iterate
     const bool finished = S.state == ST_DONE || S.state == ST_CONVERGED || S.state == ST_NEGCURV;
-    if (finished || (mixed && S.state == ST_ACTIVE && S.rr < DELTA * DELTA * R.rr_ru[l])) {
+    // stagnation: stag_window iterations without halving the smallest
+    // ||r||^2 seen so far; the slot gets an FP64 residual refresh, then a
+    // restart (the first time) or the end of its iteration (the second)
+    if (!finished && S.state == ST_ACTIVE && c->stag_window > 0) {
+      if (S.rr < 0.5 * R.best[l]) {
+        R.best[l] = S.rr;
+        R.best_it[l] = S.iters;
+      } else if (S.iters - R.best_it[l] >= c->stag_window) {
+        R.stag_pending[l] = 1;
+      }
+    }
+    if (finished || R.stag_pending[l] || (mixed && S.state == ST_ACTIVE && S.rr < DELTA * DELTA * R.rr_ru[l])) {
       c->mask_h[l] = 1;
       any = true;
     }
@@ -769,11 +786,26 @@ cell_status poll_t(SolveRun& R) {
         R.result = fail(CELL_E_BREAKDOWN, "non-finite residual in slot " + std::to_string(l));
         continue;
       }
+      const bool stag = R.stag_pending[l] != 0;
+      R.stag_pending[l] = 0;
       if (rt <= S.thr || (finished && S.maxit_hit) || S.iters >= c->max_iter) {
         R.fin[l] = 1;
         S.state = ST_DONE;
+      } else if (stag && R.restarts[l] > 0) {
+        // stagnated again after a restart: the iterate stays as it is
+        R.fin[l] = 1;
+        S.state = ST_DONE;
+        R.stagnated[l] = 1;
       } else {
         S.state = ST_ACTIVE;
+        if (stag) {
+          // restart: the next direction update takes beta = 0 (p = z of
+          // the refreshed residual); progress is measured from here
+          R.restarts[l] += 1;
+          S.first = 1;
+          R.best[l] = rt;
+          R.best_it[l] = S.iters;
+        }
       }
       S.rr = rt;
     }
@@ -809,7 +841,16 @@ cell_status end_t(SolveRun& R) {
     if (rel > c->tol) all_conv = false;
   }
   if (R.result < 0) return R.result;
-  return all_conv ? CELL_OK : CELL_NOT_CONVERGED;
+  if (all_conv) return CELL_OK;
+  std::string msg;
+  for (int l = 0; l < c->nslot; ++l)
+    if (R.active[l] && R.stagnated[l])
+      msg += (msg.empty() ? "CG stagnated (no halving of ||r||^2 in " + std::to_string(c->stag_window) +
+                                " iterations, also after a restart) in slot "
+                          : ", ") +
+             std::to_string(l);
+  if (!msg.empty()) return fail(CELL_NOT_CONVERGED, msg);
+  return CELL_NOT_CONVERGED;
 }
 
 // C* (energy form) and mean stresses of every cell from the final
@@ -965,6 +1006,8 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
   // the first p.Kp is negative and every solve ends in CELL_E_BREAKDOWN
   const char* nq = std::getenv("CELLFFT_DEBUG_NEGATE_Q");
   c->dbg_negate_q = (nq && nq[0] == '1') ? 1 : 0;
+  const char* sw = std::getenv("CELLFFT_STAG_WINDOW");
+  if (sw && sw[0]) c->stag_window = std::max(0, std::atoi(sw));
   c->have_mat.assign(ncell, 0);
   c->x0_set.assign(c->lpc, 0);
   c->lam0.assign(ncell, 0.0);

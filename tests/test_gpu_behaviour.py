@@ -9,6 +9,12 @@ breakdown in the finalize kernel and later launches skip the slot); the
 solve must report CELL_E_BREAKDOWN and a handle created afterwards must
 solve normally.
 
+Stagnation: a tolerance below what the arithmetic can reach (1e-20) leaves
+the true residual on a plateau; with CELLFFT_STAG_WINDOW=40 the solve
+refreshes and restarts once, then ends the loads with CELL_NOT_CONVERGED
+long before max_iter, keeping the best iterate (C* still equal to the
+direct solve).  With the window off, the same solve runs to max_iter.
+
 Iteration counts: the Fourier preconditioner is spectrally equivalent to
 the operator with bounds set by the local ratios of the material to the
 reference medium (K/K_0 and mu/mu_0 per voxel), not by the voxel size, so
@@ -53,6 +59,32 @@ def test_breakdown_status_forced_from_host(lib, monkeypatch, prec):
         C, info = c.effective_stiffness()
     assert info["status"] == "CELL_OK"
     assert np.abs(C - Cref).max() < 1e-10 * np.abs(Cref).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stagnation_ends_unreachable_tolerance(lib, monkeypatch, prec):
+    mask, _, _ = ms.rsa_spheres(16, 0.3, seed=2, rmin=1.0, rmax=2.0)
+    E = np.where(mask, 20.0, 1.0)
+    nu = np.full(E.shape, 0.3)
+    Cref, _, _ = fem.effective_stiffness(fem.Grid((16, 16, 16)), E, nu)
+    monkeypatch.setenv("CELLFFT_STAG_WINDOW", "40")
+    with lib.Cell((16, 16, 16), precision=prec, tol=1e-20, max_iter=3000) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+        msg = lib.last_error()
+    print("stagnation:", prec, info["iters"], info["relres"], info["refinements"])
+    assert info["status"] == "CELL_NOT_CONVERGED"
+    assert "stagnated" in msg
+    assert max(info["iters"]) < 1500
+    assert max(info["relres"]) < (1e-13 if prec == 0 else 1e-9)
+    assert np.abs(C - Cref).max() < (1e-10 if prec == 0 else 1e-8) * np.abs(Cref).max()
+    monkeypatch.setenv("CELLFFT_STAG_WINDOW", "0")
+    with lib.Cell((16, 16, 16), precision=prec, tol=1e-20, max_iter=200) as c:
+        c.set_material(E.ravel(), nu.ravel())
+        C, info = c.effective_stiffness()
+    assert info["status"] == "CELL_NOT_CONVERGED"
+    assert min(info["iters"]) >= 200
+    monkeypatch.delenv("CELLFFT_STAG_WINDOW")
 
 
 def _mean_iters(lib, g):
