@@ -185,6 +185,18 @@ void cell_destroy(cell_t c);
 
 const char* cell_last_error(void);
 
+/* Debugging aid.  The bounds-checked build of this library (compiled with
+ * -DCELLFFT_BOUNDS_CHECK: paper_2004_05197_amd/build.py build_checked(),
+ * libcellfft_checked.so) compares every field, spectrum, material and
+ * reduction-partial access of the PCG iteration kernels (operator, x/y/z
+ * FFT passes, finalize) and every partial written by the neo-Hookean and
+ * surrogate kernels with the extent of the slot's buffer; an access out of
+ * range is skipped (a load yields zero) and counted.  Returns the number
+ * counted on the current device since the last call and clears the
+ * counters (synchronises the device first); -2 if the device could not be
+ * read.  The normal build checks nothing and returns -1. */
+int cell_debug_bounds_violations(void);
+
 /* ---- kernel-level entry points (parity checks of single steps) ---------- */
 
 /* q = K u with the stencil kernel of the given precision (CELL_FP64 or

@@ -18,7 +18,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # CELLFFT_LIBRARY selects another build of the same library (the host-
-# sanitized one of the ABI tests); the default is the in-tree build
+# sanitized one of the ABI tests, the bounds-checked one of the debug
+# tests); the default is the in-tree build
 LIB_PATH = os.environ.get("CELLFFT_LIBRARY") or os.path.join(_HERE, "libcellfft.so")
 
 if not os.path.exists(LIB_PATH):
@@ -84,6 +85,7 @@ _SIGS = {
     "cell_get_displacement": (ct.c_int, [_P, ct.c_int, _P, ct.c_int]),
     "cell_destroy": (None, [_P]),
     "cell_last_error": (ct.c_char_p, []),
+    "cell_debug_bounds_violations": (ct.c_int, []),
     "cell_apply_operator": (ct.c_int, [_P, ct.c_int, _P, _P]),
     "cell_apply_preconditioner": (ct.c_int, [_P, ct.c_int, _P, _P]),
     "cell_reference_medium": (ct.c_int, [_P, _D, _D]),
@@ -131,6 +133,12 @@ class CellError(RuntimeError):
 
 def last_error():
     return _lib.cell_last_error().decode()
+
+
+def bounds_violations():
+    """Out-of-range kernel accesses counted by the bounds-checked build since
+    the last call (clears the counters); -1 for the normal build."""
+    return int(_lib.cell_debug_bounds_violations())
 
 
 def _check(status):

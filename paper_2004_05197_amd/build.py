@@ -87,8 +87,34 @@ def build_sanitized(verbose=False):
     return SAN_LIB
 
 
+# Bounds-checked variant for the debug tests: the kernels compare their field,
+# spectrum, material and partial-sum accesses with the buffer extents and
+# count (and skip) the ones out of range (cell_debug_bounds_violations()).
+CHK_OBJ = os.path.join(HERE, "_build_checked")
+CHK_LIB = os.path.join(CHK_OBJ, "libcellfft_checked.so")
+
+
+def build_checked(verbose=False):
+    os.makedirs(CHK_OBJ, exist_ok=True)
+    objs, cmds = [], []
+    for src in SOURCES:
+        obj = os.path.join(CHK_OBJ, src.replace(".hip", ".o"))
+        objs.append(obj)
+        cmds.append([HIPCC] + FLAGS + ["-DCELLFFT_BOUNDS_CHECK", "-c", os.path.join(CSRC, src), "-o", obj])
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        for r in ex.map(_run, cmds):
+            if verbose and (r.stdout or r.stderr):
+                print(r.stdout + r.stderr)
+    tmp = CHK_LIB + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, CHK_LIB)
+    return CHK_LIB
+
+
 if __name__ == "__main__":
-    if "--sanitize" in sys.argv:
+    if "--checked" in sys.argv:
+        print(build_checked(verbose="-v" in sys.argv))
+    elif "--sanitize" in sys.argv:
         print(build_sanitized(verbose="-v" in sys.argv))
     else:
         print(build(verbose="-v" in sys.argv))

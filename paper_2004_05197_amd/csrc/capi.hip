@@ -174,6 +174,20 @@ extern "C" {
 
 const char* cell_last_error(void) { return last_error_message(); }
 
+int cell_debug_bounds_violations(void) {
+#ifdef CELLFFT_BOUNDS_CHECK
+  if (hipDeviceSynchronize() != hipSuccess) return -2;
+  unsigned long long sum = 0;
+  for (unsigned int v : {oob_take_fft(), oob_take_stencil(), oob_take_hyper(), oob_take_surrogate()}) {
+    if (v == 0xffffffffu) return -2;
+    sum += v;
+  }
+  return sum > 0x7fffffffull ? 0x7fffffff : (int)sum;
+#else
+  return -1;
+#endif
+}
+
 cell_status cell_create(const cell_config* cfg, cell_t* out) { return instance_create(cfg, 1, nullptr, out); }
 
 void cell_destroy(cell_t c) { instance_destroy(c); }

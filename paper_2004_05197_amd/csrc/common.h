@@ -8,11 +8,59 @@
 //  * LDS FFT engine    in-place Stockham autosort FFT over a tile of columns
 //                      held in LDS, compile-time length N = 2^a 3^b, radix
 //                      16/8/4/3/2 codelets in registers, twiddles from a table.
+//  * checked accesses  ck_ld / ck_st: plain global loads and stores, which the
+//                      bounds-checked debug build (-DCELLFFT_BOUNDS_CHECK)
+//                      compares with the extent of the buffer they address
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace cellfft {
+
+// ---------------------------------------------------------------- checked accesses
+// p + i must lie in [lo, hi), the part of the buffer that the access may
+// touch (usually the slot's field).  In the bounds-checked build an access
+// outside is not performed (a load yields zero) and is counted in this
+// module's device counter (read by oob_count); in the normal build lo and hi
+// are unused and the helpers are the plain accesses.
+#ifdef CELLFFT_BOUNDS_CHECK
+static __device__ unsigned int g_oob_count;
+__device__ __forceinline__ bool ck_in(const void* a, const void* lo, const void* hi) {
+  if (a >= lo && a < hi) return true;
+  atomicAdd(&g_oob_count, 1u);
+  return false;
+}
+// host: read and clear this module's counter (current device)
+static inline unsigned int oob_take() {
+  unsigned int v = 0, z = 0;
+  if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_oob_count), sizeof(v)) != hipSuccess) return 0xffffffffu;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(g_oob_count), &z, sizeof(z)) != hipSuccess) return 0xffffffffu;
+  return v;
+}
+#endif
+template <typename T>
+__device__ __forceinline__ T ck_ld(const T* p, long long i, const void* lo, const void* hi) {
+#ifdef CELLFFT_BOUNDS_CHECK
+  if (!ck_in(p + i, lo, hi)) return T{};
+#endif
+  return p[i];
+}
+template <typename T>
+__device__ __forceinline__ void ck_st(T* p, long long i, const void* lo, const void* hi, const T& v) {
+#ifdef CELLFFT_BOUNDS_CHECK
+  if (!ck_in(p + i, lo, hi)) return;
+#endif
+  p[i] = v;
+}
+// the kernels' form: in the normal build the plain expression, lo and hi
+// unevaluated (the extents are computed only in the checked build)
+#ifdef CELLFFT_BOUNDS_CHECK
+#define CK_LD(p, i, lo, hi) ck_ld(p, i, lo, hi)
+#define CK_ST(p, i, lo, hi, v) ck_st(p, i, lo, hi, v)
+#else
+#define CK_LD(p, i, lo, hi) ((p)[i])
+#define CK_ST(p, i, lo, hi, v) ((p)[i] = (v))
+#endif
 
 // ---------------------------------------------------------------- complex
 template <typename T> struct cpx { T re, im; };

@@ -78,8 +78,16 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
   const int row0 = rb * RPB;
   const T2* in2 = reinterpret_cast<const T2*>((MODE == 0 ? a.q : a.r) + l * a.lstride);
   cpx<T>* R = a.R + l * (a.lstride / 2);
+#ifdef CELLFFT_BOUNDS_CHECK
+  // extents of the slot's fields
+  const T2* in2_hi = in2 + a.lstride / 2;
+  const cpx<T>* R_hi = R + a.lstride / 2;
+#endif
   // row-wave operator: q's rows y = 0 mod edge_rows still lack the edge rows
   const T2* edge2 = (MODE == 0 && a.edge) ? reinterpret_cast<const T2*>(a.edge + l * a.edge_stride) : nullptr;
+#ifdef CELLFFT_BOUNDS_CHECK
+  const T2* edge2_hi = edge2 ? edge2 + a.edge_stride / 2 : nullptr;
+#endif
   const int erows = a.edge_rows > 0 ? a.edge_rows : 1;  // a power of two
   const int eshift = __builtin_ctz(erows);
   const int nyt = a.ny >> eshift;
@@ -100,15 +108,15 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
       v[q] = {T(0), T(0)};
       if (e < RPB * M && row < a.nrows) {
         const long long off = (long long)row * M + m;
-        const T2 w = in2[off];
+        const T2 w = CK_LD(in2, off, in2, in2_hi);
         v[q] = {w.x, w.y};
-        if (MODE == 0) rv[q] = R[off];
+        if (MODE == 0) rv[q] = CK_LD(R, off, R, R_hi);
         if (MODE == 0 && edge2) {
           // row = (c nz + z) ny + y
           const int y = inplane ? yb + rr : row % a.ny;
           if ((y & (erows - 1)) == 0) {
             const int pl = inplane ? pb : row / a.ny;
-            const T2 ed = edge2[((long long)pl * nyt + (y >> eshift)) * M + m];
+            const T2 ed = CK_LD(edge2, ((long long)pl * nyt + (y >> eshift)) * M + m, edge2, edge2_hi);
             v[q].re += ed.x;
             v[q].im += ed.y;
           }
@@ -163,17 +171,17 @@ __global__ __launch_bounds__(NT) void k_xfwd(XArgs<T> a) {
         cpx<T> v = rv[q];
         v.re -= alpha * h.re;
         v.im -= alpha * h.im;
-        R[off] = v;
+        CK_ST(R, off, R, R_hi, v);
         acc += (m == 0 ? 1.0 : 2.0) * ((double)v.re * v.re + (double)v.im * v.im);
       } else {
-        R[off] = h;
+        CK_ST(R, off, R, R_hi, h);
       }
     }
   }
   if (MODE == 0) {
     // ||r||^2 partial of this block (finalised by k_finalize)
     const double bs = block_sum<NT>(acc * (1.0 / (2.0 * M)), sh);
-    if (tid == 0) a.red.slot_parts(RED_RR, l)[rb] = bs;
+    if (tid == 0) a.red.put(RED_RR, l, rb, bs);
   }
 }
 
@@ -197,6 +205,9 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
   if (rb < 0) return;
   const int row0 = rb * RPB;
   const cpx<T>* S = a.S + l * a.lsS;
+#ifdef CELLFFT_BOUNDS_CHECK
+  const cpx<T>* S_hi = S + a.lsS;  // the slot's spectrum
+#endif
   // S rows live in padded (component, z) planes of zsS complex values
   const int zr0 = row0 / a.ny, yb = row0 - zr0 * a.ny;
   {
@@ -218,7 +229,8 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
         zr += y / a.ny;
         y -= (y / a.ny) * a.ny;
       }
-      v[q] = (e < RPB * M && row < a.nrows) ? S[(long long)zr * a.zsS + (long long)y * M + m] : cpx<T>{T(0), T(0)};
+      v[q] = (e < RPB * M && row < a.nrows) ? CK_LD(S, (long long)zr * a.zsS + (long long)y * M + m, S, S_hi)
+                                            : cpx<T>{T(0), T(0)};
     }
 #pragma unroll
     for (int q = 0; q < QX; ++q) {
@@ -247,6 +259,10 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
   fft_lds<T, M, true, RPB, NT, 2, RowTileP<RS>, RP>(buf, tws);
   T2* x2 = reinterpret_cast<T2*>(a.x + l * a.lstride);
   T2* p2 = reinterpret_cast<T2*>(a.p + l * a.lstride);
+#ifdef CELLFFT_BOUNDS_CHECK
+  const T2* x2_hi = x2 + a.lstride / 2;
+  const T2* p2_hi = p2 + a.lstride / 2;
+#endif
   // x += alpha p, p = z + beta p: all of a thread's p and x loads first
   constexpr int QO = (RPB * M + NT - 1) / NT;
   T2 po[QO], xv[QO];
@@ -257,8 +273,8 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
     const int row = row0 + rr;
     if (e < RPB * M && row < a.nrows) {
       const long long off = (long long)row * M + m;
-      po[q] = p2[off];
-      xv[q] = x2[off];
+      po[q] = CK_LD(p2, off, p2, p2_hi);
+      xv[q] = CK_LD(x2, off, x2, x2_hi);
     }
   }
 #pragma unroll
@@ -272,11 +288,11 @@ __global__ __launch_bounds__(NT) void k_xinv(XArgs<T> a) {
       T2 xn = xv[q];
       xn.x += alpha * po[q].x;
       xn.y += alpha * po[q].y;
-      x2[off] = xn;
+      CK_ST(x2, off, x2, x2_hi, xn);
       T2 pn;
       pn.x = z.re + beta * po[q].x;
       pn.y = z.im + beta * po[q].y;
-      p2[off] = pn;
+      CK_ST(p2, off, p2, p2_hi, pn);
     }
   }
 }
@@ -304,6 +320,13 @@ __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
   for (int i = tid; i < N; i += NTY) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lsS + (long long)(c * a.nz + z) * a.zsS + s0;
   const cpx<T>* src = (!INV && a.Sin) ? a.Sin + l * a.lstrideC + ((long long)(c * a.nz + z) * a.ny) * M + s0 : base;
+#ifdef CELLFFT_BOUNDS_CHECK
+  // the slot's spectrum and input
+  const cpx<T>* S_lo = a.S + l * a.lsS;
+  const cpx<T>* S_hi = S_lo + a.lsS;
+  const cpx<T>* src_lo = (!INV && a.Sin) ? a.Sin + l * a.lstrideC : S_lo;
+  const cpx<T>* src_hi = (!INV && a.Sin) ? src_lo + a.lstrideC : S_hi;
+#endif
   // all of a thread's loads before the first LDS store (see the z pass)
   {
     constexpr int PER = (N * TX + NTY - 1) / NTY;
@@ -312,7 +335,7 @@ __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
     for (int q = 0; q < PER; ++q) {
       const int e = tid + q * NTY;
       const int y = e / TX, s = e - y * TX;
-      v[q] = (e < N * TX && s0 + s < M) ? src[(long long)y * M + s] : cpx<T>{T(0), T(0)};
+      v[q] = (e < N * TX && s0 + s < M) ? CK_LD(src, (long long)y * M + s, src_lo, src_hi) : cpx<T>{T(0), T(0)};
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -368,7 +391,7 @@ __global__ __launch_bounds__(NTY) void k_ypass(YArgs<T> a) {
   }
   for (int e = tid; e < N * TX; e += NTY) {
     const int y = e / TX, s = e - y * TX;
-    if (s0 + s < M) base[(long long)y * M + s] = buf[e];
+    if (s0 + s < M) CK_ST(base, (long long)y * M + s, S_lo, S_hi, buf[e]);
   }
 }
 
@@ -642,6 +665,10 @@ __global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NTH) tws[i] = a.tw[i];
   cpx<T>* base = a.S + l * a.lstrideC + (long long)y * M + s0;
+#ifdef CELLFFT_BOUNDS_CHECK
+  const cpx<T>* S_lo = a.S + l * a.lstrideC;  // the slot's spectrum
+  const cpx<T>* S_hi = S_lo + a.lstrideC;
+#endif
   // global <-> LDS copies: thread t keeps one column (t mod NC: component
   // and slot) and walks z in steps of ZS = NTH / NC, so each element costs
   // one address add (32-bit offsets from the block's base: a load's
@@ -662,7 +689,7 @@ __global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
 #pragma unroll
     for (int q = 0; q < QZ; ++q) {
       const int z = zi + q * ZS;
-      v[q] = (act && (N % ZS == 0 || z < N)) ? base[off0 + (unsigned)q * ostep] : cpx<T>{T(0), T(0)};
+      v[q] = (act && (N % ZS == 0 || z < N)) ? CK_LD(base, off0 + (unsigned)q * ostep, S_lo, S_hi) : cpx<T>{T(0), T(0)};
     }
 #pragma unroll
     for (int q = 0; q < QZ; ++q) {
@@ -676,10 +703,10 @@ __global__ __launch_bounds__(NTH) void k_zpass(PArgs<T> a) {
   if (act) {
     // (a plain loop: unrolled, its addresses would stay live through the FFT)
     unsigned off = off0;
-    for (int z = zi; z < N; z += ZS, off += ostep) base[off] = buf[z * NC + col];
+    for (int z = zi; z < N; z += ZS, off += ostep) CK_ST(base, off, S_lo, S_hi, buf[z * NC + col]);
   }
   const double bs = block_sum<NTH>(acc, sh);
-  if (tid == 0) a.red.slot_parts(RED_RZ, l)[pb] = bs;
+  if (tid == 0) a.red.put(RED_RZ, l, pb, bs);
 }
 
 // ===================================================== y pass (2D, last)
@@ -767,7 +794,7 @@ __global__ __launch_bounds__(NTZ) void k_ylast(PArgs<T> a) {
     if (s0 + s < M) base[c * cstride + (long long)y * M + s] = buf[e];
   }
   const double bs = block_sum<NTZ>(acc, sh);
-  if (tid == 0) a.red.slot_parts(RED_RZ, l)[blockIdx.x] = bs;
+  if (tid == 0) a.red.put(RED_RZ, l, blockIdx.x, bs);
 }
 
 // ================================================================ finalize
@@ -795,7 +822,7 @@ __global__ __launch_bounds__(NTF) void k_finalize(RedBuf red, LoadState* st, dou
   }
   const double* parts = red.slot_parts(slot, l);
   double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += NTF) v += parts[i];
+  for (int i = threadIdx.x; i < nparts; i += NTF) v += CK_LD(parts, i, parts, parts + red.maxblk);
   const double s = block_sum<NTF>(v, sh);
   if (threadIdx.x != 0) return;
   switch (slot) {
@@ -1019,5 +1046,9 @@ template hipError_t launch_ypass<float>(const YArgs<float>&, bool, int, const Sc
 template hipError_t launch_ypass<double>(const YArgs<double>&, bool, int, const Sched&, hipStream_t);
 template hipError_t launch_last<float>(const PArgs<float>&, int, int, const Sched&, hipStream_t);
 template hipError_t launch_last<double>(const PArgs<double>&, int, int, const Sched&, hipStream_t);
+
+#ifdef CELLFFT_BOUNDS_CHECK
+unsigned int oob_take_fft() { return oob_take(); }
+#endif
 
 }  // namespace cellfft

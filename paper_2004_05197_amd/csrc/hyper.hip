@@ -274,7 +274,7 @@ __global__ __launch_bounds__(NT) void k_hyper(HyArgs<T> a) {
     }
   }
   const double bs = block_sum<NT>(acc, sh);
-  if (threadIdx.x == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blockIdx.x] = bs;
+  if (threadIdx.x == 0) a.red.put(MODE == 0 ? RED_PQ : RED_RES, l, blockIdx.x, bs);
   if (MODE == 2) {
     for (int v = 0; v < 10; ++v) {
       const double s = block_sum<NT>(own[v], sh);
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(BX* BY) void k_hyper3t(HyArgs<T> a, int tz, int nxt
     __syncthreads();
   }
   const double bs = block_sum<NTH>(acc, sh);
-  if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
+  if (tid == 0) a.red.put(MODE == 0 ? RED_PQ : RED_RES, l, blk, bs);
   if constexpr (MODE == 2) {
     for (int v = 0; v < 10; ++v) {
       const double sv = block_sum<NTH>(own10[v], sh);
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(NT) void k_dot_slots(const double* x, const double*
   for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < len; i += (long long)gridDim.x * NT)
     s += x[o + i] * y[o + i];
   s = block_sum<NT>(s, sh);
-  if (threadIdx.x == 0) red.slot_parts(RED_RES, l)[blockIdx.x] = s;
+  if (threadIdx.x == 0) red.put(RED_RES, l, blockIdx.x, s);
 }
 
 // per (slot, component): partial sums of the n nodal values
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(NT) void k_rhs_residual(const double* rhs, TO* r, l
     s += v * v;
   }
   s = block_sum<NT>(s, sh);
-  if (threadIdx.x == 0) red.slot_parts(RED_RES, l)[blockIdx.x] = s;
+  if (threadIdx.x == 0) red.put(RED_RES, l, blockIdx.x, s);
 }
 
 hipError_t launch_rhs_residual(const double* rhs, void* r, bool out32, long long lstride, long long m, int nslot,
@@ -887,5 +887,9 @@ hipError_t launch_dot_slots(const double* x, const double* y, long long len, int
 
 template hipError_t launch_hyper_tangent<float>(const HyArgs<float>&, hipStream_t);
 template hipError_t launch_hyper_tangent<double>(const HyArgs<double>&, hipStream_t);
+
+#ifdef CELLFFT_BOUNDS_CHECK
+unsigned int oob_take_hyper() { return oob_take(); }
+#endif
 
 }  // namespace cellfft

@@ -22,6 +22,17 @@ struct RedBuf {
   __host__ __device__ double* slot_parts(int slot, int load) const {
     return parts + ((long long)slot * maxload + load) * maxblk;
   }
+  // partial blk of (slot, load); checked against its row in the debug build
+  __device__ void put(int slot, int load, int blk, double v) const {
+#ifdef CELLFFT_BOUNDS_CHECK
+    if (slot < 0 || slot >= RED_NSLOT || load < 0 || load >= maxload) {
+      atomicAdd(&g_oob_count, 1u);
+      return;
+    }
+#endif
+    double* row = slot_parts(slot, load);
+    CK_ST(row, blk, row, row + maxblk, v);
+  }
 };
 
 // Launch schedule of an instance: which compiled variant of each kernel
@@ -305,5 +316,13 @@ int stencil_effective_tile(const Geom& g, bool fp64, int t);
 long long rw_edge_floats(const Geom& g);
 int homog_blocks(const Geom& g);
 bool fft_size_ok(int n);      // y/z length (and x length)
+
+#ifdef CELLFFT_BOUNDS_CHECK
+// read and clear each module's out-of-range access counter (current device)
+unsigned int oob_take_fft();
+unsigned int oob_take_stencil();
+unsigned int oob_take_hyper();
+unsigned int oob_take_surrogate();
+#endif
 
 }  // namespace cellfft

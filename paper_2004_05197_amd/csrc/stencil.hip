@@ -156,7 +156,7 @@ __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >
 // element at a 32-bit byte offset from a block-uniform base pointer: the
 // access takes the scalar-base + 32-bit vector-offset form (one add per
 // access instead of a 64-bit address computation); offsets stay below 4 GiB
-// for every supported grid (3 x 256^3 FP64 values per load: 402 MB)
+// for every supported grid (3 x 256^3 FP64 values per load: 402 MB).
 template <typename T>
 __device__ __forceinline__ T ld_off(const T* base, unsigned boff) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
@@ -165,6 +165,24 @@ template <typename T>
 __device__ __forceinline__ void st_off(T* base, unsigned boff, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
+// the same with the extent [lo, hi) of the buffer the access may touch: the
+// bounds-checked build compares the address with it (the normal build
+// expands to the plain access, lo and hi unevaluated)
+#ifdef CELLFFT_BOUNDS_CHECK
+template <typename T>
+__device__ __forceinline__ T ld_off_ck(const T* base, unsigned boff, const void* lo, const void* hi) {
+  return ck_ld(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff), 0, lo, hi);
+}
+template <typename T>
+__device__ __forceinline__ void st_off_ck(T* base, unsigned boff, T v, const void* lo, const void* hi) {
+  ck_st(reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff), 0, lo, hi, v);
+}
+#define LD_OFF(base, boff, lo, hi) ld_off_ck(base, boff, lo, hi)
+#define ST_OFF(base, boff, v, lo, hi) st_off_ck(base, boff, v, lo, hi)
+#else
+#define LD_OFF(base, boff, lo, hi) ld_off(base, boff)
+#define ST_OFF(base, boff, v, lo, hi) st_off(base, boff, v)
+#endif
 
 // macro stress D eps_bar (tensor storage) scaled by sc, with lw/mw already
 // holding the |s| (and 1/h^2) factors of the caller
@@ -373,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_stencil3(KArgs<T> a, int bx, int by, int
       __syncthreads();
     }
     const double bs = block_sum<NT>(acc, sh);
-    if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
+    if (tid == 0) a.red.put(MODE == 0 ? RED_PQ : RED_RES, l, blk, bs);
     if (MODE == 1 && a.sparts) {
       for (int i = 0; i < 6; ++i) {
         const double v = block_sum<NT>(sacc[i], sh);
@@ -450,6 +468,12 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
     const T* u = a.u ? a.u + l * a.lstride : nullptr;
     TO* out = reinterpret_cast<TO*>(a.out) + l * a.lstride;
     const T* matl = a.mat + (long long)(l / a.lpc) * a.mat_stride;
+#ifdef CELLFFT_BOUNDS_CHECK
+    // extents of the slot's fields and the cell's material
+    const T* u_hi = u ? u + a.lstride : nullptr;
+    const TO* out_hi = out + a.lstride;
+    const T* mat_hi = matl + 2 * a.g.n;
+#endif
     T sbd[6];
     if (MODE == 1) {
       const double* e = a.eps[l % a.lpc];
@@ -461,7 +485,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
       const unsigned zb = (unsigned)(wrapi(zp, nz) * nxy) * (unsigned)sizeof(T);
 #pragma unroll
       for (int q = 0; q < PF; ++q)
-        if (pon[q]) pf[q] = u ? ld_off(u, poff[q] + zb) : T(0);
+        if (pon[q]) pf[q] = u ? LD_OFF(u, poff[q] + zb, u, u_hi) : T(0);
     };
     // the material goes through LDS like the node planes: loaded one layer
     // ahead, stored after the layer's last use, so no wait for a load falls
@@ -471,8 +495,8 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
     const T2* mat2 = reinterpret_cast<const T2*>(matl);
     auto fetch_mat = [&](int zl) {
       const int zo = wrapi(zl, nz) * nxy;
-      mo = ld_off(mat2, (unsigned)(zo + vown) * (unsigned)sizeof(T2));
-      if (has_extra) me = ld_off(mat2, (unsigned)(zo + vext) * (unsigned)sizeof(T2));
+      mo = LD_OFF(mat2, (unsigned)(zo + vown) * (unsigned)sizeof(T2), matl, mat_hi);
+      if (has_extra) me = LD_OFF(mat2, (unsigned)(zo + vext) * (unsigned)sizeof(T2), matl, mat_hi);
     };
     auto store_mat = [&]() {
       mt[2 * cown] = mo.x;
@@ -581,10 +605,10 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             if (MODE == 0) {
-              st_off(out, nb + c * cs, (TO)val[c]);
+              ST_OFF(out, nb + c * cs, (TO)val[c], out, out_hi);
               acc += (double)pk[c] * (double)val[c];
             } else {
-              st_off(out, nb + c * cs, (TO)(-val[c]));
+              ST_OFF(out, nb + c * cs, (TO)(-val[c]), out, out_hi);
               acc += (double)val[c] * (double)val[c];
             }
           }
@@ -599,7 +623,7 @@ __global__ __launch_bounds__(BX* BY) void k_stencil3t(KArgs<T> a, int tz, int nx
       __syncthreads();
     }
     const double bs = block_sum<NTH>(acc, sh);
-    if (tid == 0) a.red.slot_parts(MODE == 0 ? RED_PQ : RED_RES, l)[blk] = bs;
+    if (tid == 0) a.red.put(MODE == 0 ? RED_PQ : RED_RES, l, blk, bs);
     if (MODE == 1 && a.sparts) {
       for (int i = 0; i < 6; ++i) {
         const double v = block_sum<NTH>(sacc[i], sh);
@@ -715,7 +739,7 @@ __global__ __launch_bounds__(NT) void k_stencil2(KArgs<T> a) {
   }
   const int cslot = MODE == 0 ? RED_PQ : RED_RES;
   const double bs = block_sum<NT>(acc, sh);
-  if (threadIdx.x == 0) a.red.slot_parts(cslot, l)[blockIdx.x] = bs;
+  if (threadIdx.x == 0) a.red.put(cslot, l, blockIdx.x, bs);
   if (MODE == 1 && a.sparts) {
     for (int i = 0; i < 6; ++i) {
       const double v = block_sum<NT>(sacc[i], sh);
@@ -960,7 +984,7 @@ __global__ __launch_bounds__(NW* WAVE) __attribute__((amdgpu_waves_per_eu(V == 4
     if (L + 2 <= tz) step(L + 2, P2, P0, P1, M2, M0);
   }
   const double bs = block_sum<NTH>(acc, sh);
-  if (tid == 0) a.red.slot_parts(RED_PQ, l)[blk] = bs;
+  if (tid == 0) a.red.put(RED_PQ, l, blk, bs);
 }
 
 // q[rows y = 0 mod rows] += edge rows, for the active slots (the row-wave
@@ -1409,5 +1433,9 @@ hipError_t launch_grad(const HArgs& a, hipStream_t s) {
 
 template hipError_t launch_stencil<float>(const KArgs<float>&, const Sched&, hipStream_t);
 template hipError_t launch_stencil<double>(const KArgs<double>&, const Sched&, hipStream_t);
+
+#ifdef CELLFFT_BOUNDS_CHECK
+unsigned int oob_take_stencil() { return oob_take(); }
+#endif
 
 }  // namespace cellfft

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(sizeof(T
 #pragma unroll
     for (int w = 0; w < NT / WAVE; ++w) s += sh[w * NSUM + k];
     if (k < 6) {
-      if (MODE == 0 && live[k]) a.red.slot_parts(RED_PQ, k)[blk] = s;
+      if (MODE == 0 && live[k]) a.red.put(RED_PQ, k, blk, s);
     } else {
       const int l = (k - 6) / 3, c = (k - 6) % 3;
       if (live[l]) a.cparts[((long long)l * 3 + c) * nb + blk] = s;
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(WAVE* BY) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
     for (int w = 0; w < NT / WAVE; ++w) s2 += sh[w * NSUM + k];
     if (k < 6) {
-      if (live[k]) a.red.slot_parts(RED_PQ, k)[blk] = s2;
+      if (live[k]) a.red.put(RED_PQ, k, blk, s2);
     } else {
       const int l = (k - 6) / 3, c = (k - 6) % 3;
       if (live[l]) a.cparts[((long long)l * 3 + c) * nb + blk] = s2;
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(NT) void k_sr_fix(TO* r, long long lstride, long lo
     s += x * x;
   }
   s = block_sum<NT>(s, sh);
-  if (threadIdx.x == 0) red.slot_parts(RED_RES, l)[blockIdx.x] = s;
+  if (threadIdx.x == 0) red.put(RED_RES, l, blockIdx.x, s);
 }
 
 hipError_t launch_sr_expand(const double* coef, int ncx, int ncy, int ncz, int M, int q, const Geom& g, double* s64,
@@ -589,5 +589,9 @@ int sr_max_blocks(const Geom& g) { return g.dim == 3 ? sr_grid(g).nb : 0; }
 
 template hipError_t launch_sr_apply<float>(const SArgs<float>&, hipStream_t);
 template hipError_t launch_sr_apply<double>(const SArgs<double>&, hipStream_t);
+
+#ifdef CELLFFT_BOUNDS_CHECK
+unsigned int oob_take_surrogate() { return oob_take(); }
+#endif
 
 }  // namespace cellfft

@@ -69,3 +69,10 @@ def test_null_arguments(cdll):
     assert cdll.cell_create(None, None) == -1
     cdll.cell_last_error.restype = ct.c_char_p
     assert b"null" in cdll.cell_last_error()
+
+
+def test_normal_build_checks_no_bounds(cdll):
+    # the bounds counter exists only in the checked build; the normal one
+    # answers -1 without touching a device
+    cdll.cell_debug_bounds_violations.restype = ct.c_int
+    assert cdll.cell_debug_bounds_violations() == -1
