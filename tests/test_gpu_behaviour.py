@@ -13,7 +13,9 @@ Stagnation: a tolerance below what the arithmetic can reach (1e-20) leaves
 the true residual on a plateau; with CELLFFT_STAG_WINDOW=40 the solve
 refreshes and restarts once, then ends the loads with CELL_NOT_CONVERGED
 long before max_iter, keeping the best iterate (C* still equal to the
-direct solve).  With the window off, the same solve runs to max_iter.
+direct solve).  With the window off, the same solve runs to max_iter.  A
+batch of two cell sizes ends the same way (both groups polled with the
+same check).
 
 Iteration counts: the Fourier preconditioner is spectrally equivalent to
 the operator with bounds set by the local ratios of the material to the
@@ -85,6 +87,31 @@ def test_stagnation_ends_unreachable_tolerance(lib, monkeypatch, prec):
     assert info["status"] == "CELL_NOT_CONVERGED"
     assert min(info["iters"]) >= 200
     monkeypatch.delenv("CELLFFT_STAG_WINDOW")
+
+
+def test_stagnation_in_a_batch(lib, monkeypatch):
+    # the batch polls every group with the same check: cells of two sizes
+    # with an unreachable tolerance end early, the status is the worst one
+    monkeypatch.setenv("CELLFFT_STAG_WINDOW", "40")
+    shapes = [(16, 16, 16), (12, 12, 12)]
+    with lib.Batch(shapes, precision=lib.MIXED, tol=1e-20, max_iter=3000) as b:
+        for i, sh in enumerate(shapes):
+            m, _, _ = ms.rsa_spheres(sh[0], 0.3, seed=20 + i, rmin=1.0, rmax=2.0)
+            b.set_material(i, np.where(m, 20.0, 1.0).ravel(), np.full(m.size, 0.3))
+        C, infos = b.effective_stiffness()
+        msg = lib.last_error()
+    monkeypatch.delenv("CELLFFT_STAG_WINDOW")
+    print("batch stagnation:", [i["iters"] for i in infos], [max(i["relres"]) for i in infos])
+    assert all(i["status"] == "CELL_NOT_CONVERGED" for i in infos)
+    assert "stagnated" in msg
+    for i in infos:
+        assert max(i["iters"]) < 1500
+        assert max(i["relres"]) < 1e-9
+    for k, sh in enumerate(shapes):
+        m, _, _ = ms.rsa_spheres(sh[0], 0.3, seed=20 + k, rmin=1.0, rmax=2.0)
+        E = np.where(m, 20.0, 1.0)
+        Cref, _, _ = fem.effective_stiffness(fem.Grid(sh), E, np.full(E.shape, 0.3))
+        assert np.abs(C[k] - Cref).max() < 1e-8 * np.abs(Cref).max()
 
 
 def _mean_iters(lib, g):
