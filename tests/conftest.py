@@ -28,3 +28,20 @@ def lib():
         pytest.skip("no GPU")
     from paper_2004_05197_amd import binding
     return binding
+
+
+@pytest.fixture(autouse=True)
+def _bounds_violations(request):
+    """With CELLFFT_CHECK_BOUNDS=1 and CELLFFT_LIBRARY set to the bounds-
+    checked build (build.py build_checked), every GPU test must leave the
+    library's out-of-range access counter at zero: the whole GPU suite then
+    doubles as a bounds check of every kernel path it reaches."""
+    yield
+    if os.environ.get("CELLFFT_CHECK_BOUNDS") != "1" or request.node.get_closest_marker("gpu") is None:
+        return
+    if not gpu_available():
+        return
+    from paper_2004_05197_amd import binding
+    v = binding.bounds_violations()
+    assert v >= 0, "CELLFFT_CHECK_BOUNDS=1 needs CELLFFT_LIBRARY set to the bounds-checked build"
+    assert v == 0, f"{v} out-of-range kernel accesses counted by the bounds-checked build"
