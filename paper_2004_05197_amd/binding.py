@@ -25,6 +25,17 @@ LIB_PATH = os.environ.get("CELLFFT_LIBRARY") or os.path.join(_HERE, "libcellfft.
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2004_05197_amd.build`")
 
+# torch carries its own HIP runtime next to the system one this library links.
+# Whichever initialises the GPU first keeps it: after the library's runtime
+# has started, torch reports no GPU.  Torch supplies the device memory and
+# streams here, so its runtime is started before the library is loaded.
+try:
+    import torch as _torch
+except ImportError:  # plain ctypes use without torch: one runtime only
+    _torch = None
+if _torch is not None:
+    _torch.cuda.is_available()
+
 _lib = ct.CDLL(LIB_PATH)
 
 CELL_OK = 0
