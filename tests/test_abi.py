@@ -76,3 +76,25 @@ def test_normal_build_checks_no_bounds(cdll):
     # answers -1 without touching a device
     cdll.cell_debug_bounds_violations.restype = ct.c_int
     assert cdll.cell_debug_bounds_violations() == -1
+
+
+def test_last_error_is_per_thread():
+    # argument validation fails before any device work, so two threads can
+    # each see their own message
+    import threading
+    from paper_2004_05197_amd import binding as B
+    msgs = {}
+
+    def fail_here():
+        with pytest.raises(B.CellError):
+            B.Cell((10, 8, 8))
+        msgs["other"] = B.last_error()
+
+    with pytest.raises(B.CellError):
+        B.Cell((8, 8, 8), precision=7)
+    mine = B.last_error()
+    t = threading.Thread(target=fail_here)
+    t.start()
+    t.join()
+    assert "grid size 10" in msgs["other"]
+    assert mine == "invalid precision" and B.last_error() == mine
