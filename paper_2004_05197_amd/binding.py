@@ -25,16 +25,16 @@ LIB_PATH = os.environ.get("CELLFFT_LIBRARY") or os.path.join(_HERE, "libcellfft.
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2004_05197_amd.build`")
 
-# torch carries its own HIP runtime next to the system one this library links.
-# Whichever initialises the GPU first keeps it: after the library's runtime
-# has started, torch reports no GPU.  Torch supplies the device memory and
-# streams here, so its runtime is started before the library is loaded.
+# torch bundles its own HIP and HSA runtimes under the same sonames as the
+# system ones this library links.  Loaded after torch, the library binds to
+# torch's copies (one runtime in the process, so torch's device pointers and
+# streams are the library's too); loaded first, it pulls in the system copies
+# and torch, loading its own beside them, then finds no GPU.  So torch is
+# imported before the library is loaded.
 try:
-    import torch as _torch
+    import torch as _torch  # noqa: F401
 except ImportError:  # plain ctypes use without torch: one runtime only
     _torch = None
-if _torch is not None:
-    _torch.cuda.is_available()
 
 _lib = ct.CDLL(LIB_PATH)
 
