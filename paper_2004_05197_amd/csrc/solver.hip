@@ -1067,6 +1067,80 @@ cell_status instance_create(const cell_config* cfg, int ncell, hipStream_t share
   return CELL_OK;
 }
 
+namespace {
+
+// Material setup on the device (Lame parameters of Sec. 6.3 from (E, nu)).
+// k_mat_check: validity and the reference-medium extremes, one partial row
+// per block (MAT_NP values: min/max bulk modulus, min/max shear modulus,
+// max |lambda| + 2 mu, first voxel with an invalid E, first with an invalid
+// nu), reduced over the blocks on the host; k_mat_convert: (lambda, mu) in
+// FP64 and FP32 and the copy of E, written only once the check has passed,
+// so a rejected material leaves the previous one in place.
+constexpr int MAT_NP = 7;
+constexpr int MAT_BLOCKS = 1024;
+
+__device__ __forceinline__ void lame_of(double e, double p, double& lam, double& mu) {
+  lam = p * e / ((1.0 + p) * (1.0 - 2.0 * p));
+  mu = e / (2.0 * (1.0 + p));
+}
+
+__global__ __launch_bounds__(NT) void k_mat_check(const double* E, const double* nu, long long n, int d,
+                                                  double* parts) {
+  double v[MAT_NP] = {INFINITY, 0.0, INFINITY, 0.0, 0.0, (double)n, (double)n};
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const double e = E[i], p = nu[i];
+    const bool okE = isfinite(e) && e > 0.0, okN = isfinite(p) && p > -1.0 && p < 0.5;
+    if (!okE) v[5] = fmin(v[5], (double)i);
+    if (!okN) v[6] = fmin(v[6], (double)i);
+    if (okE && okN) {
+      double lam, mu;
+      lame_of(e, p, lam, mu);
+      const double bulk = lam + (d == 3 ? 2.0 * mu / 3.0 : mu);
+      v[0] = fmin(v[0], bulk);
+      v[1] = fmax(v[1], bulk);
+      v[2] = fmin(v[2], mu);
+      v[3] = fmax(v[3], mu);
+      v[4] = fmax(v[4], fabs(lam) + 2.0 * mu);
+    }
+  }
+  __shared__ double sh[NT / WAVE][MAT_NP];
+#pragma unroll
+  for (int k = 0; k < MAT_NP; ++k) {
+    const bool mx = k == 1 || k == 3 || k == 4;
+    double x = v[k];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const double y = __shfl_xor(x, o, WAVE);
+      x = mx ? fmax(x, y) : fmin(x, y);
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < MAT_NP) {
+    const int k = threadIdx.x;
+    const bool mx = k == 1 || k == 3 || k == 4;
+    double x = sh[0][k];
+    for (int w = 1; w < NT / WAVE; ++w) x = mx ? fmax(x, sh[w][k]) : fmin(x, sh[w][k]);
+    parts[(long long)blockIdx.x * MAT_NP + k] = x;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_mat_convert(const double* E, const double* nu, long long n, double* mat64,
+                                                    float* mat32, double* E64) {
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+    const double e = E[i], p = nu[i];
+    double lam, mu;
+    lame_of(e, p, lam, mu);
+    mat64[2 * i] = lam;
+    mat64[2 * i + 1] = mu;
+    mat32[2 * i] = (float)lam;
+    mat32[2 * i + 1] = (float)mu;
+    E64[i] = e;
+  }
+}
+
+}  // namespace
+
 cell_status instance_set_material(cell_s* c, int cell, const double* E, const double* nu, int on_device) {
   if (!c || !E || !nu) return fail(CELL_E_ARG, "null argument");
   if (cell < 0 || cell >= c->ncell) return fail(CELL_E_ARG, "cell index out of range");
@@ -1075,42 +1149,62 @@ cell_status instance_set_material(cell_s* c, int cell, const double* E, const do
   c->sr_M = 0;
   if (c->op == 2) c->op = 0;
   const long long n = c->n;
-  std::vector<double> Eh(n), nh(n);
-  if (on_device) {
-    HIPCHK(hipMemcpyAsync(Eh.data(), E, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(nh.data(), nu, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-  } else {
-    std::memcpy(Eh.data(), E, sizeof(double) * n);
-    std::memcpy(nh.data(), nu, sizeof(double) * n);
+  hipStream_t s = c->stream;
+  // host inputs are staged in a temporary device buffer
+  double* stage = nullptr;
+  const double *Ed = E, *nd = nu;
+  if (!on_device) {
+    if (hipMalloc((void**)&stage, sizeof(double) * 2 * n) != hipSuccess)
+      return fail(CELL_E_NOMEM, "device allocation failed (material staging)");
+    const hipError_t e1 = hipMemcpyAsync(stage, E, sizeof(double) * n, hipMemcpyHostToDevice, s);
+    const hipError_t e2 = hipMemcpyAsync(stage + n, nu, sizeof(double) * n, hipMemcpyHostToDevice, s);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(stage);
+      return fail(CELL_E_DEVICE, std::string("material upload: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    }
+    Ed = stage;
+    nd = stage + n;
   }
-  std::vector<double> m64(2 * n);
-  std::vector<float> m32(2 * n);
-  double kmin = INFINITY, kmax = 0, mmin = INFINITY, mmax = 0, modmax = 0;
-  for (long long v = 0; v < n; ++v) {
-    const double e = Eh[v], p = nh[v];
-    if (!std::isfinite(e) || !(e > 0.0))
-      return fail(CELL_E_NONFINITE, "Young's modulus must be finite and positive (voxel " + std::to_string(v) + ")");
-    if (!std::isfinite(p) || !(p > -1.0) || !(p < 0.5))
-      return fail(CELL_E_ARG, "Poisson ratio must lie in (-1, 0.5) (voxel " + std::to_string(v) + ")");
-    const double lam = p * e / ((1.0 + p) * (1.0 - 2.0 * p));
-    const double mu = e / (2.0 * (1.0 + p));
-    m64[2 * v] = lam;
-    m64[2 * v + 1] = mu;
-    m32[2 * v] = (float)lam;
-    m32[2 * v + 1] = (float)mu;
-    const double bulk = lam + (c->d == 3 ? 2.0 * mu / 3.0 : mu);
-    kmin = std::min(kmin, bulk);
-    kmax = std::max(kmax, bulk);
-    mmin = std::min(mmin, mu);
-    mmax = std::max(mmax, mu);
-    modmax = std::max(modmax, std::fabs(lam) + 2.0 * mu);
+  auto done = [&](cell_status st) {
+    if (stage) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(stage);
+    }
+    return st;
+  };
+  const int nb = (int)std::min<long long>(MAT_BLOCKS, (n + NT - 1) / NT);
+  std::vector<double> parts((size_t)nb * MAT_NP);
+  hipLaunchKernelGGL(k_mat_check, dim3(nb), dim3(NT), 0, s, Ed, nd, n, c->d, c->scratch);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(parts.data(), c->scratch, sizeof(double) * parts.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return done(fail(CELL_E_DEVICE, std::string("material check: ") + hipGetErrorString(e)));
+  double kmin = INFINITY, kmax = 0, mmin = INFINITY, mmax = 0, modmax = 0, badE = (double)n, badN = (double)n;
+  for (int b = 0; b < nb; ++b) {
+    const double* q = parts.data() + (size_t)b * MAT_NP;
+    kmin = std::min(kmin, q[0]);
+    kmax = std::max(kmax, q[1]);
+    mmin = std::min(mmin, q[2]);
+    mmax = std::max(mmax, q[3]);
+    modmax = std::max(modmax, q[4]);
+    badE = std::min(badE, q[5]);
+    badN = std::min(badN, q[6]);
   }
+  // the first invalid voxel decides; at one voxel an invalid E is reported first
+  if (badE < (double)n && badE <= badN)
+    return done(fail(CELL_E_NONFINITE, "Young's modulus must be finite and positive (voxel " +
+                                           std::to_string((long long)badE) + ")"));
+  if (badN < (double)n)
+    return done(fail(CELL_E_ARG, "Poisson ratio must lie in (-1, 0.5) (voxel " + std::to_string((long long)badN) + ")"));
   const long long off = (long long)cell * n;
-  HIPCHK(hipMemcpyAsync(c->mat64 + 2 * off, m64.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->mat32 + 2 * off, m32.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(c->E64 + off, Eh.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
+  hipLaunchKernelGGL(k_mat_convert, dim3(nb), dim3(NT), 0, s, Ed, nd, n, c->mat64 + 2 * off, c->mat32 + 2 * off,
+                     c->E64 + off);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return done(fail(CELL_E_DEVICE, std::string("material conversion: ") + hipGetErrorString(e)));
+  done(CELL_OK);
   const double K0 = std::sqrt(kmin * kmax), mu0 = std::sqrt(mmin * mmax);
   c->mu0[cell] = mu0;
   c->lam0[cell] = K0 - (c->d == 3 ? 2.0 * mu0 / 3.0 : mu0);
