@@ -77,3 +77,30 @@ def test_batch_device_material(lib):
                     b.set_material(i, torch.tensor(e, device="cuda"), torch.tensor(v, device="cuda"))
             res[mode] = b.effective_stiffness()[0]
     assert np.array_equal(res["host"], res["device"])
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_rejected_material_keeps_the_previous_one(lib, device):
+    # the device-side check reports the first invalid voxel (E before nu at
+    # one voxel) and writes nothing; the next solve uses the earlier material
+    import torch
+    E, nu = cell_material()
+    wrap = (lambda a: torch.tensor(a, device="cuda")) if device else (lambda a: a)
+    with lib.Cell((16, 16, 16), precision=lib.FP64, tol=1e-10) as c:
+        c.set_material(wrap(E), wrap(nu))
+        C0, _ = c.effective_stiffness()
+        bad_E, bad_nu = E.copy(), nu.copy()
+        bad_E[1234] = np.nan
+        bad_nu[1234] = 0.7
+        bad_nu[99] = -1.0
+        with pytest.raises(lib.CellError) as ei:
+            c.set_material(wrap(bad_E), wrap(nu))
+        assert ei.value.status == lib.CELL_E_NONFINITE and "voxel 1234" in lib.last_error()
+        with pytest.raises(lib.CellError) as ei:
+            c.set_material(wrap(bad_E), wrap(bad_nu))
+        assert ei.value.status == lib.CELL_E_ARG and "voxel 99" in lib.last_error()
+        with pytest.raises(lib.CellError) as ei:
+            c.set_material(wrap(E * 0.0), wrap(nu))
+        assert ei.value.status == lib.CELL_E_NONFINITE and "voxel 0" in lib.last_error()
+        C1, _ = c.effective_stiffness()
+    assert np.array_equal(C0, C1)
