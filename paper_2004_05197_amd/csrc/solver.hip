@@ -1636,39 +1636,110 @@ namespace {
 
 // periodic system a x_{i-1} + b x_i + a x_{i+1} = d_i with a = 1/6, b = 2/3:
 // the cubic B-spline interpolation conditions along one lattice axis.
-// Sherman-Morrison on the Thomas algorithm: A = T + u v^T with the corners
-// of A moved into u v^T, u = (g, 0, .., 0, a), v = (1, 0, .., 0, a / g),
+// Sherman-Morrison on the Thomas algorithm: A = T + u w^T with the corners
+// of A moved into u w^T, u = (g, 0, .., 0, a), w = (1, 0, .., 0, a / g),
 // g = -b, and T's first and last diagonal entries b - g and b - a^2 / g.
-void cubic_line(double* v, long long stride, int n, std::vector<double>& y, std::vector<double>& z,
-                std::vector<double>& cp) {
-  const double a = 1.0 / 6.0, b = 2.0 / 3.0;
-  if (n == 1) return;  // the periodic sum of the spline over all shifts is 1
-  if (n == 2) {
-    const double d0 = v[0], d1 = v[stride], det = b * b - 4.0 * a * a;
-    v[0] = (b * d0 - 2.0 * a * d1) / det;
-    v[stride] = (b * d1 - 2.0 * a * d0) / det;
-    return;
+// The data-independent parts (the Thomas pivots den_i, the superdiagonal
+// ratios cp_i and z = T^{-1} u) are the same for every line of a length;
+// cubic_consts computes them once per axis, k_sr_cubic solves every line.
+constexpr double SR_A = 1.0 / 6.0, SR_B = 2.0 / 3.0, SR_G = -2.0 / 3.0;
+
+void cubic_consts(int n, double* den, double* cp, double* z) {
+  auto diag = [&](int i) { return i == 0 ? SR_B - SR_G : (i == n - 1 ? SR_B - SR_A * SR_A / SR_G : SR_B); };
+  den[0] = diag(0);
+  cp[0] = SR_A / den[0];
+  for (int i = 1; i < n; ++i) {
+    den[i] = diag(i) - SR_A * cp[i - 1];
+    cp[i] = SR_A / den[i];
   }
-  const double g = -b;
-  auto diag = [&](int i) { return i == 0 ? b - g : (i == n - 1 ? b - a * a / g : b); };
-  auto thomas = [&](const double* rhs, long long rs, std::vector<double>& x) {
-    double den = diag(0);
-    cp[0] = a / den;
-    x[0] = rhs[0] / den;
-    for (int i = 1; i < n; ++i) {
-      den = diag(i) - a * cp[i - 1];
-      cp[i] = a / den;
-      x[i] = (rhs[i * rs] - a * x[i - 1]) / den;
+  for (int i = 0; i < n; ++i) z[i] = i == 0 ? SR_G : (i == n - 1 ? SR_A : 0.0);
+  z[0] /= den[0];
+  for (int i = 1; i < n; ++i) z[i] = (z[i] - SR_A * z[i - 1]) / den[i];
+  for (int i = n - 2; i >= 0; --i) z[i] -= cp[i] * z[i + 1];
+}
+
+// every line along `axis` of every stencil value, in place in S[value][ci]
+__global__ __launch_bounds__(NT) void k_sr_cubic(double* S, long long nc, int ncx, int ncy, int ncz, int axis,
+                                                 const double* den, const double* cp, const double* z) {
+  const int n = axis == 0 ? ncx : (axis == 1 ? ncy : ncz);
+  const long long lines = nc / n;
+  const long long stride = axis == 0 ? 1 : (axis == 1 ? ncx : (long long)ncx * ncy);
+  for (long long w = blockIdx.x * (long long)NT + threadIdx.x; w < lines * SR_NVAL; w += (long long)gridDim.x * NT) {
+    const long long v = w / lines, li = w - v * lines;
+    long long base;
+    if (axis == 0) base = li * ncx;                                    // li = cy + ncy cz
+    else if (axis == 1) base = (li / ncx) * ncx * ncy + li % ncx;      // li = cx + ncx cz
+    else base = li;                                                    // li = cx + ncx cy
+    double* f = S + v * nc + base;
+    if (n == 1) continue;  // the periodic sum of the spline over all shifts is 1
+    if (n == 2) {
+      const double d0 = f[0], d1 = f[stride], det = SR_B * SR_B - 4.0 * SR_A * SR_A;
+      f[0] = (SR_B * d0 - 2.0 * SR_A * d1) / det;
+      f[stride] = (SR_B * d1 - 2.0 * SR_A * d0) / det;
+      continue;
     }
-    for (int i = n - 2; i >= 0; --i) x[i] -= cp[i] * x[i + 1];
-  };
-  std::vector<double> u(n, 0.0);
-  u[0] = g;
-  u[n - 1] = a;
-  thomas(v, stride, y);
-  thomas(u.data(), 1, z);
-  const double fact = (y[0] + a / g * y[n - 1]) / (1.0 + z[0] + a / g * z[n - 1]);
-  for (int i = 0; i < n; ++i) v[i * stride] = y[i] - fact * z[i];
+    double prev = f[0] / den[0];
+    f[0] = prev;
+    for (int i = 1; i < n; ++i) {
+      prev = (f[i * stride] - SR_A * prev) / den[i];
+      f[i * stride] = prev;
+    }
+    for (int i = n - 2; i >= 0; --i) {
+      prev = f[i * stride] - cp[i] * prev;
+      f[i * stride] = prev;
+    }
+    const double fact = (f[0] + SR_A / SR_G * f[(n - 1) * stride]) / (1.0 + z[0] + SR_A / SR_G * z[n - 1]);
+    for (int i = 0; i < n; ++i) f[i * stride] -= fact * z[i];
+  }
+}
+
+// stencil functions of the exact operator at the lattice nodes (every M-th
+// node): K[X, X + delta] = sum over the simplices holding both nodes of
+// |s| (lam g1 g2^T + mu g2 g1^T + mu g1.g2 I), g the barycentric gradients
+__constant__ int kSrPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+__constant__ int kSrOff[SR_NOFF] = {1, 2, 4, 3, 6, 5, 7};  // offsets as corner bit masks (x | y << 1 | z << 2)
+
+__global__ __launch_bounds__(NT) void k_sr_sample(const double* mat, Geom g, int M, int ncx, int ncy, int ncz,
+                                                  double* S) {
+  const long long nc = (long long)ncx * ncy * ncz;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
+  const double vol = g.h[0] * g.h[1] * g.h[2] / 6.0;
+  for (long long w = blockIdx.x * (long long)NT + threadIdx.x; w < nc * SR_NOFF; w += (long long)gridDim.x * NT) {
+    const int k = (int)(w / nc);
+    const long long ci = w - (long long)k * nc;
+    const int cx = (int)(ci % ncx), cy = (int)((ci / ncx) % ncy), cz = (int)(ci / ((long long)ncx * ncy));
+    const int X[3] = {cx * M, cy * M, cz * M};
+    const int off = kSrOff[k];
+    double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c1 = 0; c1 < 8; ++c1) {
+      if (c1 & off) continue;
+      const int c2 = c1 | off;
+      const int vx = (X[0] - (c1 & 1) + nx) % nx, vy = (X[1] - ((c1 >> 1) & 1) + ny) % ny;
+      const int vz = (X[2] - ((c1 >> 2) & 1) + nz) % nz;
+      const long long vid = ((long long)vz * ny + vy) * nx + vx;
+      const double lam = mat[2 * vid], mu = mat[2 * vid + 1];
+      for (int t = 0; t < 6; ++t) {
+        int path[4] = {0, 0, 0, 0}, m1 = -1, m2 = -1;
+        for (int m = 0; m < 3; ++m) path[m + 1] = path[m] | (1 << kSrPerm[t][m]);
+        for (int m = 0; m < 4; ++m) {
+          if (path[m] == c1) m1 = m;
+          if (path[m] == c2) m2 = m;
+        }
+        if (m1 < 0 || m2 < 0) continue;
+        double g1[3] = {0.0, 0.0, 0.0}, g2[3] = {0.0, 0.0, 0.0};
+        if (m1 > 0) g1[kSrPerm[t][m1 - 1]] += ih[kSrPerm[t][m1 - 1]];
+        if (m1 < 3) g1[kSrPerm[t][m1]] -= ih[kSrPerm[t][m1]];
+        if (m2 > 0) g2[kSrPerm[t][m2 - 1]] += ih[kSrPerm[t][m2 - 1]];
+        if (m2 < 3) g2[kSrPerm[t][m2]] -= ih[kSrPerm[t][m2]];
+        const double dg = g1[0] * g2[0] + g1[1] * g2[1] + g1[2] * g2[2];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b)
+            blk[3 * a + b] += vol * (lam * g1[a] * g2[b] + mu * g1[b] * g2[a] + (a == b ? mu * dg : 0.0));
+      }
+    }
+    for (int e = 0; e < 9; ++e) S[(long long)(9 * k + e) * nc + ci] = blk[e];
+  }
 }
 
 }  // namespace
@@ -1691,82 +1762,39 @@ cell_status instance_set_surrogate(cell_s* c, int M, int q) {
   DevGuard dg(c->dev);
   const double t0 = now_s();
   const long long n = c->n;
-  std::vector<double> mat(2 * n);
-  HIPCHK(hipMemcpyAsync(mat.data(), c->mat64, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
   const int ncx = nx / M, ncy = ny / M, ncz = nz / M;
   const long long nc = (long long)ncx * ncy * ncz;
-  std::vector<double> S((size_t)SR_NVAL * nc, 0.0);
-  const double ih[3] = {1.0 / c->g.h[0], 1.0 / c->g.h[1], 1.0 / c->g.h[2]};
-  const double vol = c->g.h[0] * c->g.h[1] * c->g.h[2] / 6.0;
-  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-  static const int offm[SR_NOFF] = {1, 2, 4, 3, 6, 5, 7};  // offsets as corner bit masks (x | y << 1 | z << 2)
-  // barycentric gradient of path vertex m of simplex t
-  auto grad = [&](int t, int m, double* gv) {
-    gv[0] = gv[1] = gv[2] = 0.0;
-    if (m > 0) gv[perm[t][m - 1]] += ih[perm[t][m - 1]];
-    if (m < 3) gv[perm[t][m]] -= ih[perm[t][m]];
-  };
-  // stencil functions at the lattice nodes: K[X, X + delta] = sum over the
-  // simplices holding both nodes of |s| (lam g1 g2^T + mu g2 g1^T + mu g1.g2 I)
-  for (int cz = 0; cz < ncz; ++cz)
-    for (int cy = 0; cy < ncy; ++cy)
-      for (int cx = 0; cx < ncx; ++cx) {
-        const int X[3] = {cx * M, cy * M, cz * M};
-        const long long ci = ((long long)cz * ncy + cy) * ncx + cx;
-        for (int k = 0; k < SR_NOFF; ++k) {
-          double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-          for (int c1 = 0; c1 < 8; ++c1) {
-            if (c1 & offm[k]) continue;
-            const int c2 = c1 | offm[k];
-            const int vx = (X[0] - (c1 & 1) + nx) % nx, vy = (X[1] - ((c1 >> 1) & 1) + ny) % ny;
-            const int vz = (X[2] - ((c1 >> 2) & 1) + nz) % nz;
-            const long long vid = ((long long)vz * ny + vy) * nx + vx;
-            const double lam = mat[2 * vid], mu = mat[2 * vid + 1];
-            for (int t = 0; t < 6; ++t) {
-              int path[4] = {0, 0, 0, 0}, m1 = -1, m2 = -1;
-              for (int m = 0; m < 3; ++m) path[m + 1] = path[m] | (1 << perm[t][m]);
-              for (int m = 0; m < 4; ++m) {
-                if (path[m] == c1) m1 = m;
-                if (path[m] == c2) m2 = m;
-              }
-              if (m1 < 0 || m2 < 0) continue;
-              double g1[3], g2[3];
-              grad(t, m1, g1);
-              grad(t, m2, g2);
-              const double dg = g1[0] * g2[0] + g1[1] * g2[1] + g1[2] * g2[2];
-              for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b)
-                  blk[3 * a + b] += vol * (lam * g1[a] * g2[b] + mu * g1[b] * g2[a] + (a == b ? mu * dg : 0.0));
-            }
-          }
-          for (int e = 0; e < 9; ++e) S[(size_t)(9 * k + e) * nc + ci] = blk[e];
-        }
-      }
-  if (q == 3) {
-    // interpolation coefficients: the cubic system along x, then y, then z
-    const int nmax = std::max(ncx, std::max(ncy, ncz));
-    std::vector<double> y(nmax), z(nmax), cp(nmax);
-    for (int v = 0; v < SR_NVAL; ++v) {
-      double* f = S.data() + (size_t)v * nc;
-      for (int cz = 0; cz < ncz; ++cz)
-        for (int cy = 0; cy < ncy; ++cy) cubic_line(f + ((long long)cz * ncy + cy) * ncx, 1, ncx, y, z, cp);
-      for (int cz = 0; cz < ncz; ++cz)
-        for (int cx = 0; cx < ncx; ++cx) cubic_line(f + (long long)cz * ncy * ncx + cx, ncx, ncy, y, z, cp);
-      for (int cy = 0; cy < ncy; ++cy)
-        for (int cx = 0; cx < ncx; ++cx) cubic_line(f + (long long)cy * ncx + cx, (long long)ncx * ncy, ncz, y, z, cp);
-    }
-  }
   auto dm = [&](void** p, size_t bytes) { return *p != nullptr || hipMalloc(p, bytes) == hipSuccess; };
   if (!dm((void**)&c->sr64, sizeof(double) * sr_len(n)) || !dm((void**)&c->sr32, sizeof(float) * sr_len(n)) ||
       !dm((void**)&c->sr_rhs, sizeof(double) * (size_t)c->lstride * c->nslot) ||
       !dm((void**)&c->sr_parts, sizeof(double) * 3 * (size_t)c->nslot * c->maxblk) ||
       !dm((void**)&c->sr_mean, sizeof(double) * 3 * c->nslot))
     return fail(CELL_E_NOMEM, "device allocation of the surrogate stencil failed");
+  // the sampled stencil functions, then (cubic) their interpolation
+  // coefficients along x, y and z, in one device buffer [value][lattice node]
+  const int nmax = std::max(ncx, std::max(ncy, ncz));
   double* coef = nullptr;
-  if (hipMalloc((void**)&coef, sizeof(double) * S.size()) != hipSuccess)
+  if (hipMalloc((void**)&coef, sizeof(double) * ((size_t)SR_NVAL * nc + 9 * (size_t)nmax)) != hipSuccess)
     return fail(CELL_E_NOMEM, "device allocation of the spline coefficients failed");
-  hipError_t e = hipMemcpyAsync(coef, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice, c->stream);
+  double* consts = coef + (size_t)SR_NVAL * nc;  // per axis: den, cp, z
+  std::vector<double> ch(9 * (size_t)nmax, 0.0);
+  const int nax[3] = {ncx, ncy, ncz};
+  for (int ax = 0; ax < 3; ++ax)
+    if (nax[ax] > 2) cubic_consts(nax[ax], &ch[(3 * ax) * nmax], &ch[(3 * ax + 1) * nmax], &ch[(3 * ax + 2) * nmax]);
+  const int sblocks = (int)std::min<long long>(4096, (nc * SR_NOFF + NT - 1) / NT);
+  hipLaunchKernelGGL(k_sr_sample, dim3(sblocks), dim3(NT), 0, c->stream, (const double*)c->mat64, c->g, M, ncx, ncy,
+                     ncz, coef);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && q == 3) {
+    e = hipMemcpyAsync(consts, ch.data(), sizeof(double) * ch.size(), hipMemcpyHostToDevice, c->stream);
+    for (int ax = 0; ax < 3 && e == hipSuccess; ++ax) {
+      const long long work = nc / nax[ax] * SR_NVAL;
+      hipLaunchKernelGGL(k_sr_cubic, dim3((unsigned)std::min<long long>(4096, (work + NT - 1) / NT)), dim3(NT), 0,
+                         c->stream, coef, nc, ncx, ncy, ncz, ax, (const double*)consts + (3 * ax) * nmax,
+                         (const double*)consts + (3 * ax + 1) * nmax, (const double*)consts + (3 * ax + 2) * nmax);
+      e = hipGetLastError();
+    }
+  }
   if (e == hipSuccess) e = launch_sr_expand(coef, ncx, ncy, ncz, M, q, c->g, c->sr64, c->sr32, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->sr_mean, 0, sizeof(double) * 3 * c->nslot, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
