@@ -51,6 +51,11 @@ __global__ void k_sub_mean(const double* u, const double* mean, long long n, int
     out[i] = u[i] - mean[i / n];
 }
 
+__global__ void k_widen(const float* in, long long n, double* out) {
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+    out[i] = (double)in[i];
+}
+
 const double* solution64(cell_s* c) { return c->precision == CELL_MIXED ? c->x64 : c->f64.x; }
 
 void voigt_to_tensor(int d, const double* v, double* t) {
@@ -149,16 +154,17 @@ cell_status slot_residual(cell_s* c, int cell, int load, double* r_out, int on_d
   if (load < 0 || load >= c->nload_solved) return fail(CELL_E_ARG, "load index out of range");
   DevGuard dg(c->dev);
   const long long off = ((long long)cell * c->lpc + load) * c->lstride;
-  if (c->precision == CELL_MIXED) {
+  if (c->precision == CELL_MIXED && on_device) {
+    // widened on the device, in order on the handle's stream
+    const int nb = (int)std::min<long long>(1024, (c->lstride + NT - 1) / NT);
+    hipLaunchKernelGGL(k_widen, dim3(nb), dim3(NT), 0, c->stream, (const float*)(c->f32.r + off), c->lstride, r_out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } else if (c->precision == CELL_MIXED) {
     std::vector<float> h(c->lstride);
     HIPCHK(hipMemcpyAsync(h.data(), c->f32.r + off, sizeof(float) * c->lstride, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    if (on_device) {
-      std::vector<double> d(h.begin(), h.end());
-      HIPCHK(hipMemcpy(r_out, d.data(), sizeof(double) * c->lstride, hipMemcpyHostToDevice));
-    } else {
-      for (long long i = 0; i < c->lstride; ++i) r_out[i] = (double)h[i];
-    }
+    for (long long i = 0; i < c->lstride; ++i) r_out[i] = (double)h[i];
   } else {
     HIPCHK(hipMemcpyAsync(r_out, c->f64.r + off, sizeof(double) * c->lstride,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
