@@ -93,9 +93,12 @@ typedef struct {
 cell_status cell_create(const cell_config* cfg, cell_t* out);
 
 /* Per-voxel Young's modulus E (> 0, finite) and Poisson ratio nu in
- * (-1, 0.5), n values each, colexicographic.  Copies the data; also fixes
- * the preconditioner's reference medium (geometric means of the extreme
- * bulk and shear moduli). */
+ * (-1, 0.5), n values each, colexicographic.  Copies the data (host arrays
+ * through a temporary device buffer), validates it and converts it to the
+ * Lame parameters on the device; also fixes the preconditioner's reference
+ * medium (geometric means of the extreme bulk and shear moduli).  The first
+ * invalid voxel is reported (CELL_E_NONFINITE for E, CELL_E_ARG for nu; E
+ * first at one voxel) and the previous material, if any, stays in place. */
 cell_status cell_set_material(cell_t c, const double* E, const double* nu, int on_device);
 
 /* Solve the cell problem for nload (<= max_loads) macro strains
