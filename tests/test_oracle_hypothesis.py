@@ -18,7 +18,7 @@ from hypothesis import given, settings, strategies as st
 from oracle import fem
 from test_oracle_pins import energy_bruteforce, voigt_to_tensor
 
-SETTINGS = dict(max_examples=25, deadline=None, derandomize=True)
+SETTINGS = dict(max_examples=25, deadline=None, derandomize=True, database=None)
 
 
 @st.composite
@@ -57,7 +57,7 @@ def test_bounds_forms_and_invariances(cell):
     assert np.abs(C3 - 3.0 * C).max() <= 1e-9 * scale
 
 
-@settings(max_examples=8, deadline=None, derandomize=True)
+@settings(max_examples=8, deadline=None, derandomize=True, database=None)
 @given(cells(max_n=3))
 def test_energy_against_independent_evaluation(cell):
     grid, E, nu = cell
